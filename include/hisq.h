@@ -1,0 +1,175 @@
+/*
+ * hisq.h -- C ABI of the MI355X (gfx950) HISQ staggered Dslash / CG library.
+ *
+ * The operator is the HISQ Dslash of the paper's Sec. 5.1 ("HISQ Dslash
+ * performance model", the stencil equation there):
+ *
+ *   (D psi)(x) = sum_mu eta_mu(x) [ X_mu(x) psi(x+mu)  - X_mu(x-mu)^+  psi(x-mu)
+ *                                 + W_mu(x) psi(x+3mu) - W_mu(x-3mu)^+ psi(x-3mu) ]
+ *
+ * with X the fat (smeared) links, W the long three-hop links, the
+ * Kogut-Susskind phases eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y),
+ * eta_3 = (-1)^(x+y+z), periodic links and colour vectors periodic in space and
+ * periodic or antiperiodic in time (Sec. 3, "Physics modules").  Coefficients
+ * (c_1, c_Naik, ...) are folded into X and W by the caller; the phases and the
+ * time boundary sign are applied by the library, never folded into the links.
+ * D_eo maps odd sites to even sites and D_oe even to odd (the first index is
+ * the output parity); the solvers work with the even-site normal operator
+ * M_e = m^2 - D_eo D_oe, the role of the applyMdaggM operator of Sec. 3.2
+ * ("Inverters").
+ *
+ * Conventions for every entry point:
+ *  - Every buffer argument is device memory owned by the caller (for example
+ *    a torch tensor on the GPU) unless its comment says "host".  The library
+ *    never allocates or frees caller-visible memory.  Sizes of packed buffers
+ *    and workspaces come only from the *_bytes queries below.
+ *  - Canonical layouts (complex128, interleaved re/im):
+ *      links  (4, Nt, Nz, Ny, Nx, 3, 3): [mu][t][z][y][x][row][col], x fastest;
+ *      fields (nrhs, V/2, 3): the sites of one parity in increasing
+ *             lexicographic order lex = x + Nx (y + Ny (z + Nz t)), i.e. the
+ *             half-lattice index floor(lex/2) of the even/odd memory order of
+ *             Sec. 4.3 ("Indexing and fields").
+ *    Packed layouts are private to the library (structure of arrays split by
+ *    parity, direction and matrix chunk); convert with the pack/unpack calls.
+ *  - Every call returns a hisq_status.  Nothing throws, aborts or exits across
+ *    the ABI.  Arguments are validated on the host before any HIP call;
+ *    hisq_last_error() returns a message for the calling thread's last error.
+ *  - pack, unpack, dslash and apply_m are asynchronous on `stream` (a
+ *    hipStream_t; NULL is the default stream).  The solvers are synchronous:
+ *    they return when finished because they report convergence.
+ *  - Calls are re-entrant given distinct output and workspace buffers.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Lattice descriptor.  dims = {Nx, Ny, Nz, Nt}; each extent even and >= 4 so
+ * that parity is consistent across the periodic wrap and floor(lex/2) is a
+ * bijection on each parity.  t_bc = +1 (periodic) or -1 (antiperiodic) time
+ * boundary condition of the colour vectors. */
+typedef struct {
+    int32_t dims[4];
+    int32_t t_bc;
+} hisq_lattice;
+
+/* Storage precision of packed links and fields.
+ *   HISQ_FP64  : binary64, arithmetic in FP64.
+ *   HISQ_FP32  : binary32, arithmetic in FP32.
+ *   HISQ_FP16N : links in binary16 (each part rounded once, from binary64,
+ *                to nearest-even binary16); colour vectors in binary16 scaled
+ *                by a binary32 per-site norm n = max |component| over the 6
+ *                reals of the site (packing from complex128: each part v is
+ *                stored as binary16(v / binary32(n)), quotient in FP64 rounded
+ *                once); arithmetic in FP32. */
+typedef enum { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_FP16N = 2 } hisq_prec;
+
+typedef enum {
+    HISQ_OK = 0,
+    HISQ_ERR_INVALID_ARG = 1,
+    HISQ_ERR_NOT_CONVERGED = 2,
+    HISQ_ERR_BREAKDOWN = 3,
+    HISQ_ERR_DEVICE = 4,
+    HISQ_ERR_WORKSPACE = 5,
+    HISQ_ERR_UNSUPPORTED = 6
+} hisq_status;
+
+/* Per-solve report (host).  true_residual = ||b - A x|| / ||b|| recomputed
+ * in FP64 with FP64 links at the end of the solve; seconds = wall time of the
+ * call. */
+typedef struct {
+    int32_t iterations;
+    int32_t reliable_updates;
+    double true_residual;
+    double seconds;
+} hisq_solve_info;
+
+/* Opaque context: device ordinal and the autotuning cache.  May be NULL in
+ * every call, meaning the current device and built-in launch shapes. */
+typedef struct hisq_context hisq_context;
+
+hisq_status hisq_context_create(hisq_context **ctx, int32_t device);
+void hisq_context_destroy(hisq_context *ctx);
+const char *hisq_status_string(hisq_status s);
+/* Message describing the calling thread's most recent error ("" if none). */
+const char *hisq_last_error(void);
+
+/* Maximum number of right-hand sides per call. */
+#define HISQ_MAX_RHS 16
+
+/* Bytes of the packed X and W links of one lattice (both parities). */
+size_t hisq_links_bytes(const hisq_lattice *lat, hisq_prec prec);
+/* Bytes of nrhs packed colour-vector fields on one parity (V/2 sites). */
+size_t hisq_field_bytes(const hisq_lattice *lat, hisq_prec prec, int32_t nrhs);
+
+/* Pack canonical complex128 links fat_c128 (X) and naik_c128 (W), each of
+ * 4*V*9 complex, into `packed` (hisq_links_bytes).  Asynchronous. */
+hisq_status hisq_pack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                            const void *fat_c128, const void *naik_c128, void *packed,
+                            void *stream);
+/* Inverse of hisq_pack_links: widen packed links back to canonical complex128
+ * fat_c128 / naik_c128 (each 4*V*9 complex).  Asynchronous. */
+hisq_status hisq_unpack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                              const void *packed, void *fat_c128, void *naik_c128, void *stream);
+/* Pack nrhs canonical half-lattice fields (nrhs*V/2*3 complex128) into
+ * `packed` (hisq_field_bytes).  For HISQ_FP16N the per-site norm is formed
+ * from the FP64 input as documented at hisq_prec.  Asynchronous. */
+hisq_status hisq_pack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                            int32_t nrhs, const void *half_c128, void *packed, void *stream);
+/* Inverse of hisq_pack_field (exact widening to complex128). */
+hisq_status hisq_unpack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                              int32_t nrhs, const void *packed, void *half_c128, void *stream);
+
+/* out = D_eo in (out_parity 0: odd input, even output) or D_oe in
+ * (out_parity 1), for nrhs packed fields.  links: packed with the same prec.
+ * `in` and `out` must not overlap.  Asynchronous.  Paper Sec. 5.1; the
+ * multi-RHS form (one link load shared by all right-hand sides) follows the
+ * N_inner / N_outer scheme described there. */
+hisq_status hisq_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                        int32_t out_parity, const void *links, const void *in, void *out,
+                        int32_t nrhs, void *stream);
+
+/* out_even = (m^2) in_even - D_eo D_oe in_even, using tmp_odd (a packed
+ * field of nrhs on the odd sites) as scratch.  Asynchronous. */
+hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,
+                         double mass, const void *links, const void *in_even, void *out_even,
+                         void *tmp_odd, int32_t nrhs, void *stream);
+
+/* Launch shape of hisq_dslash (and of the Dslash inside the solvers).
+ *   variant   0: one thread per output site; 1: four lanes per site, one per
+ *             direction, combined by wavefront shuffles.
+ *   nin       right-hand sides per thread sharing each link load (1, 2, 4, 8;
+ *             the remaining right-hand sides run as further blocks: the
+ *             N_inner x N_outer split of the paper's Sec. 5.1).
+ *   block     threads per block (64, 128, 256).
+ *   xcd_remap 1: consecutive blocks of one XCD take neighbouring sites. */
+typedef struct {
+    int32_t variant;
+    int32_t nin;
+    int32_t block;
+    int32_t xcd_remap;
+} hisq_dslash_shape;
+
+/* Autotuner: time every supported shape of hisq_dslash for (lattice, prec,
+ * nrhs) on the caller's buffers (out is overwritten) and keep the fastest in
+ * ctx (required).  Synchronous on `stream`. */
+hisq_status hisq_tune_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                             const void *links, const void *in, void *out, void *stream);
+/* The shape hisq_dslash will use (tuned or set in ctx, else the built-in
+ * default; ctx may be NULL).  *shape is a host pointer. */
+hisq_status hisq_get_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                                  hisq_dslash_shape *shape);
+/* Force a shape for (lattice, prec, nrhs) in ctx (required). */
+hisq_status hisq_set_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                                  const hisq_dslash_shape *shape);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

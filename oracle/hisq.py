@@ -248,10 +248,11 @@ def multishift_reference(lat: Lattice, mass: float, shifts, b, tol, max_iter: in
 # ---------------------------------------------------------------------------
 # Storage formats of the reduced-precision path:
 #   FP32:   each real and imaginary part rounded to binary32 (nearest-even).
-#   FP16N:  links: each real part rounded to binary32, then to binary16.
+#   FP16N:  links: each real part rounded once, from binary64, to binary16
+#           (nearest-even).
 #           colour vectors: per site n = max |component| over the 6 reals,
-#           n32 = binary32(n); each real part v stored as
-#           binary16(binary32(v / n32)) (division in FP64); value = n32 * h.
+#           n32 = binary32(n); each real part v stored as binary16(v / n32)
+#           (division in FP64, then one rounding to binary16); value = n32 * h.
 
 def quantize_fp32(a):
     a = np.asarray(a)
@@ -261,7 +262,7 @@ def quantize_fp32(a):
 
 def quantize_links_fp16(a):
     a = np.asarray(a)
-    f = lambda v: v.astype(np.float32).astype(np.float16).astype(np.float64)  # noqa: E731
+    f = lambda v: v.astype(np.float16).astype(np.float64)  # noqa: E731
     return f(a.real) + 1j * f(a.imag)
 
 
@@ -271,7 +272,7 @@ def quantize_field_fp16n(psi):
     n = np.maximum(np.abs(psi.real), np.abs(psi.imag)).max(axis=-1)
     n32 = n.astype(np.float32).astype(np.float64)
     safe = np.where(n32 > 0, n32, 1.0)[..., None]
-    f = lambda v: (v / safe).astype(np.float32).astype(np.float16).astype(np.float64)  # noqa: E731
+    f = lambda v: (v / safe).astype(np.float16).astype(np.float64)  # noqa: E731
     out = (f(psi.real) + 1j * f(psi.imag)) * n32[..., None]
     return out
 

@@ -1,0 +1,169 @@
+// Device loads and stores of packed links and colour-vector fields.
+#pragma once
+
+#include "common.hpp"
+
+namespace hisq {
+
+// ---------------------------------------------------------------------------
+// Link matrices: 18 reals, row-major, (re, im) interleaved.
+// ---------------------------------------------------------------------------
+template <int LP> struct LinkIO;
+
+template <> struct LinkIO<HISQ_FP64> {
+    using A = double;
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double2 v = reinterpret_cast<const double2 *>(blk + (size_t)vh * 16 * k)[i];
+            m[2 * k] = v.x;
+            m[2 * k + 1] = v.y;
+        }
+    }
+};
+
+template <> struct LinkIO<HISQ_FP32> {
+    using A = float;
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 v = reinterpret_cast<const float4 *>(blk + (size_t)vh * 16 * k)[i];
+            m[4 * k] = v.x;
+            m[4 * k + 1] = v.y;
+            m[4 * k + 2] = v.z;
+            m[4 * k + 3] = v.w;
+        }
+        const float2 t = reinterpret_cast<const float2 *>(blk + (size_t)vh * 64)[i];
+        m[16] = t.x;
+        m[17] = t.y;
+    }
+};
+
+union H8 {
+    uint4 u;
+    _Float16 h[8];
+};
+union H2 {
+    uint32_t u;
+    _Float16 h[2];
+};
+
+template <> struct LinkIO<HISQ_FP16N> {
+    using A = float;
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            H8 v;
+            v.u = reinterpret_cast<const uint4 *>(blk + (size_t)vh * 16 * k)[i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                m[8 * k + j] = (float)v.h[j];
+        }
+        H2 t;
+        t.u = reinterpret_cast<const uint32_t *>(blk + (size_t)vh * 32)[i];
+        m[16] = (float)t.h[0];
+        m[17] = (float)t.h[1];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Colour-vector fields on one parity.
+// ---------------------------------------------------------------------------
+template <int FP> struct FieldIO;
+
+template <> struct FieldIO<HISQ_FP64> {
+    template <typename A>
+    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
+        const double2 *p = reinterpret_cast<const double2 *>(f) + (size_t)r * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 d = p[(size_t)c * vh];
+            v[c].re = (A)d.x;
+            v[c].im = (A)d.y;
+        }
+    }
+    template <typename A>
+    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
+        double2 *p = reinterpret_cast<double2 *>(f) + (size_t)r * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            p[(size_t)c * vh] = make_double2((double)v[c].re, (double)v[c].im);
+    }
+    template <typename A>
+    __device__ __forceinline__ static void store_colour(void *f, int vh, int r, int i, int c, cplx<A> v) {
+        reinterpret_cast<double2 *>(f)[((size_t)r * 3 + c) * vh + i] = make_double2((double)v.re, (double)v.im);
+    }
+};
+
+template <> struct FieldIO<HISQ_FP32> {
+    template <typename A>
+    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
+        const float2 *p = reinterpret_cast<const float2 *>(f) + (size_t)r * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 d = p[(size_t)c * vh];
+            v[c].re = (A)d.x;
+            v[c].im = (A)d.y;
+        }
+    }
+    template <typename A>
+    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
+        float2 *p = reinterpret_cast<float2 *>(f) + (size_t)r * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            p[(size_t)c * vh] = make_float2((float)v[c].re, (float)v[c].im);
+    }
+    template <typename A>
+    __device__ __forceinline__ static void store_colour(void *f, int vh, int r, int i, int c, cplx<A> v) {
+        reinterpret_cast<float2 *>(f)[((size_t)r * 3 + c) * vh + i] = make_float2((float)v.re, (float)v.im);
+    }
+};
+
+// binary16 components scaled by a binary32 per-site norm, one 16-byte record
+// per site: {re0, im0, re1, im1, re2, im2} halves, then the float norm.
+union F16NRecord {
+    uint4 u;
+    struct {
+        _Float16 h[6];
+        float norm;
+    } s;
+};
+
+template <> struct FieldIO<HISQ_FP16N> {
+    template <typename A>
+    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
+        F16NRecord rec;
+        rec.u = reinterpret_cast<const uint4 *>(f)[(size_t)r * vh + i];
+        const float n = rec.s.norm;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c].re = (A)((float)rec.s.h[2 * c] * n);
+            v[c].im = (A)((float)rec.s.h[2 * c + 1] * n);
+        }
+    }
+    // Norm n = max |component| (exact in FP32); components stored as
+    // binary16(v / n) with the division in FP32.
+    template <typename A>
+    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
+        float x[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[2 * c] = (float)v[c].re;
+            x[2 * c + 1] = (float)v[c].im;
+        }
+        float n = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            n = fmaxf(n, fabsf(x[k]));
+        F16NRecord rec;
+        const float inv_ok = n > 0.f ? 1.f : 0.f;
+        const float d = n > 0.f ? n : 1.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            rec.s.h[k] = (_Float16)(inv_ok * (x[k] / d));
+        rec.s.norm = n;
+        reinterpret_cast<uint4 *>(f)[(size_t)r * vh + i] = rec.u;
+    }
+};
+
+}  // namespace hisq

@@ -1,0 +1,254 @@
+// C ABI entry points: argument validation (host only, before any HIP call),
+// error reporting and dispatch to the kernels.
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "api_util.hpp"
+#include "dslash.hpp"
+
+using namespace hisq;
+
+namespace hisq {
+
+thread_local std::string g_last_error;
+
+hisq_status fail(hisq_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+hisq_status device_fail(hipError_t e, const char *where) {
+    return fail(HISQ_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+hisq_status check_lattice(const hisq_lattice *lat) {
+    if (!lat)
+        return fail(HISQ_ERR_INVALID_ARG, "lattice descriptor is NULL");
+    int64_t v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int n = lat->dims[mu];
+        if (n < 4 || (n & 1))
+            return fail(HISQ_ERR_INVALID_ARG, "extent dims[%d] = %d must be even and >= 4", mu, n);
+        v *= n;
+    }
+    if (v > (int64_t)1 << 30)
+        return fail(HISQ_ERR_INVALID_ARG, "lattice volume %lld exceeds 2^30 sites", (long long)v);
+    if (lat->t_bc != 1 && lat->t_bc != -1)
+        return fail(HISQ_ERR_INVALID_ARG, "t_bc = %d must be +1 or -1", lat->t_bc);
+    return HISQ_OK;
+}
+
+hisq_status check_prec(int prec) {
+    if (prec != HISQ_FP64 && prec != HISQ_FP32 && prec != HISQ_FP16N)
+        return fail(HISQ_ERR_INVALID_ARG, "unknown precision %d", prec);
+    return HISQ_OK;
+}
+
+hisq_status check_nrhs(int nrhs) {
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS)
+        return fail(HISQ_ERR_INVALID_ARG, "nrhs = %d outside [1, %d]", nrhs, HISQ_MAX_RHS);
+    return HISQ_OK;
+}
+
+hisq_status check_ptr(const void *p, const char *name) {
+    if (!p)
+        return fail(HISQ_ERR_INVALID_ARG, "%s is NULL", name);
+    return HISQ_OK;
+}
+
+hisq_status set_device(hisq_context *ctx) {
+    if (!ctx)
+        return HISQ_OK;
+    const hipError_t e = hipSetDevice(ctx->device);
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "hipSetDevice");
+}
+
+DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs) {
+    if (ctx) {
+        DslashShape s;
+        if (ctx->lookup(g, lp, fp, nrhs, &s))
+            return s;
+    }
+    return default_shape(g, lp, fp, nrhs);
+}
+
+}  // namespace hisq
+
+#define TRY(expr)                        \
+    do {                                 \
+        const hisq_status _s = (expr);   \
+        if (_s != HISQ_OK)               \
+            return _s;                   \
+    } while (0)
+
+extern "C" {
+
+hisq_status hisq_context_create(hisq_context **ctx, int32_t device) {
+    if (!ctx)
+        return fail(HISQ_ERR_INVALID_ARG, "ctx is NULL");
+    *ctx = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess)
+        return device_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n)
+        return fail(HISQ_ERR_INVALID_ARG, "device %d outside [0, %d)", device, n);
+    hisq_context *c = new (std::nothrow) hisq_context();
+    if (!c)
+        return fail(HISQ_ERR_DEVICE, "out of host memory");
+    c->device = device;
+    *ctx = c;
+    return HISQ_OK;
+}
+
+void hisq_context_destroy(hisq_context *ctx) { delete ctx; }
+
+const char *hisq_status_string(hisq_status s) {
+    switch (s) {
+    case HISQ_OK: return "ok";
+    case HISQ_ERR_INVALID_ARG: return "invalid argument";
+    case HISQ_ERR_NOT_CONVERGED: return "not converged";
+    case HISQ_ERR_BREAKDOWN: return "breakdown";
+    case HISQ_ERR_DEVICE: return "device error";
+    case HISQ_ERR_WORKSPACE: return "workspace too small";
+    case HISQ_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *hisq_last_error(void) { return g_last_error.c_str(); }
+
+size_t hisq_links_bytes(const hisq_lattice *lat, hisq_prec prec) {
+    if (check_lattice(lat) != HISQ_OK || check_prec(prec) != HISQ_OK)
+        return 0;
+    const Geom g = make_geom(*lat);
+    return links_bytes(g, prec == HISQ_FP64 ? 8 : prec == HISQ_FP32 ? 4 : 2);
+}
+
+size_t hisq_field_bytes(const hisq_lattice *lat, hisq_prec prec, int32_t nrhs) {
+    if (check_lattice(lat) != HISQ_OK || check_prec(prec) != HISQ_OK || check_nrhs(nrhs) != HISQ_OK)
+        return 0;
+    return field_bytes(make_geom(*lat), prec, nrhs);
+}
+
+hisq_status hisq_pack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, const void *fat_c128,
+                            const void *naik_c128, void *packed, void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_ptr(fat_c128, "fat_c128"));
+    TRY(check_ptr(naik_c128, "naik_c128"));
+    TRY(check_ptr(packed, "packed"));
+    TRY(set_device(ctx));
+    const hipError_t e = launch_pack_links(make_geom(*lat), prec, fat_c128, naik_c128, packed,
+                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "pack_links");
+}
+
+hisq_status hisq_unpack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, const void *packed,
+                              void *fat_c128, void *naik_c128, void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_ptr(packed, "packed"));
+    TRY(check_ptr(fat_c128, "fat_c128"));
+    TRY(check_ptr(naik_c128, "naik_c128"));
+    TRY(set_device(ctx));
+    const hipError_t e = launch_unpack_links(make_geom(*lat), prec, packed, fat_c128, naik_c128,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "unpack_links");
+}
+
+hisq_status hisq_pack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                            const void *half_c128, void *packed, void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_nrhs(nrhs));
+    TRY(check_ptr(half_c128, "half_c128"));
+    TRY(check_ptr(packed, "packed"));
+    TRY(set_device(ctx));
+    const hipError_t e =
+        launch_pack_field(make_geom(*lat), prec, nrhs, half_c128, packed, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "pack_field");
+}
+
+hisq_status hisq_unpack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                              const void *packed, void *half_c128, void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_nrhs(nrhs));
+    TRY(check_ptr(packed, "packed"));
+    TRY(check_ptr(half_c128, "half_c128"));
+    TRY(set_device(ctx));
+    const hipError_t e =
+        launch_unpack_field(make_geom(*lat), prec, nrhs, packed, half_c128, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "unpack_field");
+}
+
+hisq_status hisq_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t out_parity,
+                        const void *links, const void *in, void *out, int32_t nrhs, void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_nrhs(nrhs));
+    if (out_parity != 0 && out_parity != 1)
+        return fail(HISQ_ERR_INVALID_ARG, "out_parity = %d must be 0 or 1", out_parity);
+    TRY(check_ptr(links, "links"));
+    TRY(check_ptr(in, "in"));
+    TRY(check_ptr(out, "out"));
+    if (in == out)
+        return fail(HISQ_ERR_INVALID_ARG, "in and out must not alias");
+    TRY(set_device(ctx));
+    DslashParams prm{};
+    prm.g = make_geom(*lat);
+    prm.out_parity = out_parity;
+    prm.nrhs = nrhs;
+    prm.links = static_cast<const char *>(links);
+    prm.in = in;
+    prm.out = out;
+    const DslashShape s = pick_shape(ctx, prm.g, prec, prec, nrhs);
+    const hipError_t e = launch_dslash(prm, prec, prec, EPI_PLAIN, s, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "dslash");
+}
+
+hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, double mass,
+                         const void *links, const void *in_even, void *out_even, void *tmp_odd, int32_t nrhs,
+                         void *stream) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(prec));
+    TRY(check_nrhs(nrhs));
+    TRY(check_ptr(links, "links"));
+    TRY(check_ptr(in_even, "in_even"));
+    TRY(check_ptr(out_even, "out_even"));
+    TRY(check_ptr(tmp_odd, "tmp_odd"));
+    if (in_even == out_even || tmp_odd == in_even || tmp_odd == out_even)
+        return fail(HISQ_ERR_INVALID_ARG, "in_even, out_even and tmp_odd must be distinct");
+    if (!(mass == mass) || mass * mass <= 0.0)
+        return fail(HISQ_ERR_INVALID_ARG, "mass^2 must be positive (mass = %g)", mass);
+    TRY(set_device(ctx));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    DslashParams prm{};
+    prm.g = make_geom(*lat);
+    prm.nrhs = nrhs;
+    prm.links = static_cast<const char *>(links);
+    const DslashShape s = pick_shape(ctx, prm.g, prec, prec, nrhs);
+    prm.out_parity = 1;
+    prm.in = in_even;
+    prm.out = tmp_odd;
+    hipError_t e = launch_dslash(prm, prec, prec, EPI_PLAIN, s, st);
+    if (e != hipSuccess)
+        return device_fail(e, "apply_m (D_oe)");
+    prm.out_parity = 0;
+    prm.in = tmp_odd;
+    prm.out = out_even;
+    prm.y = in_even;
+    prm.ad = -1.0;
+    prm.ay = mass * mass;
+    e = launch_dslash(prm, prec, prec, EPI_AXPY, s, st);
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "apply_m (D_eo)");
+}
+
+}  // extern "C"

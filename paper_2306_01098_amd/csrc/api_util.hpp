@@ -1,0 +1,48 @@
+// Host helpers shared by the C ABI translation units: error reporting,
+// argument checks and the context (device + autotune cache).
+#pragma once
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "internal.hpp"
+
+struct hisq_context {
+    int device = 0;
+    // Autotuned Dslash shapes keyed by (extents, link precision, field
+    // precision, nrhs).
+    using Key = std::tuple<int, int, int, int, int, int, int>;
+    std::map<Key, hisq::DslashShape> shapes;
+    std::mutex mu;
+
+    static Key key(const hisq::Geom &g, int lp, int fp, int nrhs) {
+        return Key(g.nx, g.ny, g.nz, g.nt, lp, fp, nrhs);
+    }
+    bool lookup(const hisq::Geom &g, int lp, int fp, int nrhs, hisq::DslashShape *s) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = shapes.find(key(g, lp, fp, nrhs));
+        if (it == shapes.end())
+            return false;
+        *s = it->second;
+        return true;
+    }
+    void store(const hisq::Geom &g, int lp, int fp, int nrhs, hisq::DslashShape s) {
+        std::lock_guard<std::mutex> lk(mu);
+        shapes[key(g, lp, fp, nrhs)] = s;
+    }
+};
+
+namespace hisq {
+
+hisq_status fail(hisq_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+hisq_status device_fail(hipError_t e, const char *where);
+hisq_status check_lattice(const hisq_lattice *lat);
+hisq_status check_prec(int prec);
+hisq_status check_nrhs(int nrhs);
+hisq_status check_ptr(const void *p, const char *name);
+hisq_status set_device(hisq_context *ctx);
+DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs);
+DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs);
+
+}  // namespace hisq

@@ -1,0 +1,118 @@
+// Shared device/host definitions of the gfx950 HISQ library: packed layouts,
+// lattice index helpers and small complex arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "hisq.h"
+
+namespace hisq {
+
+// ---------------------------------------------------------------------------
+// Lattice geometry on the device.  A site of parity p with coordinates
+// (x, y, z, t) has half-lattice index i = floor(lex / 2) with
+// lex = x + Nx (y + Ny (z + Nz t)) (the even/odd memory order of Sec. 4.3);
+// because Nx is even, i = x/2 + (Nx/2) (y + Ny (z + Nz t)).
+// ---------------------------------------------------------------------------
+struct Geom {
+    int nx, ny, nz, nt;  // extents
+    int hx;              // nx / 2
+    int vh;              // V / 2 sites per parity
+    int t_bc;            // +1 / -1 time boundary sign of colour vectors
+};
+
+inline Geom make_geom(const hisq_lattice &l) {
+    Geom g;
+    g.nx = l.dims[0];
+    g.ny = l.dims[1];
+    g.nz = l.dims[2];
+    g.nt = l.dims[3];
+    g.hx = g.nx / 2;
+    g.vh = (int)((int64_t)g.nx * g.ny * g.nz * g.nt / 2);
+    g.t_bc = l.t_bc;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Packed link layout.  For each field f (0 = X fat, 1 = W long), parity p of
+// the site the link leaves from, and direction mu, one block of vh matrices.
+// A block stores the 18 reals of each matrix (row-major, re/im interleaved)
+// split into 16-byte chunks, structure of arrays: chunk k of all vh sites is
+// contiguous, so a wavefront reading chunk k for 64 consecutive sites issues
+// one fully coalesced 1 KiB request.  The last chunk may be shorter
+// (FP32: 8 bytes, FP16: 4 bytes).
+// ---------------------------------------------------------------------------
+template <int P> struct Prec;
+template <> struct Prec<HISQ_FP64> {
+    using store = double;
+    using acc = double;
+    static constexpr int real_bytes = 8;
+};
+template <> struct Prec<HISQ_FP32> {
+    using store = float;
+    using acc = float;
+    static constexpr int real_bytes = 4;
+};
+template <> struct Prec<HISQ_FP16N> {
+    using store = _Float16;
+    using acc = float;
+    static constexpr int real_bytes = 2;
+};
+
+__host__ __device__ constexpr int matrix_bytes(int real_bytes) { return 18 * real_bytes; }
+__host__ __device__ constexpr int full_chunks(int real_bytes) { return (18 * real_bytes) / 16; }
+__host__ __device__ constexpr int tail_bytes(int real_bytes) { return (18 * real_bytes) % 16; }
+
+inline size_t links_bytes(const Geom &g, int real_bytes) {
+    return (size_t)2 * 2 * 4 * (size_t)g.vh * matrix_bytes(real_bytes);
+}
+
+// Byte offset of the block (f, p, mu).
+__host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int real_bytes) {
+    return (size_t)((f * 2 + p) * 4 + mu) * (size_t)vh * matrix_bytes(real_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Packed field layout (one parity, nrhs right-hand sides).
+//   FP64 / FP32: [rhs][colour][site] complex (16 / 8 bytes per element).
+//   FP16N:       [rhs][site] 16-byte records {half2 c0, half2 c1, half2 c2,
+//                float norm}: one dwordx4 load fetches a whole site.
+// ---------------------------------------------------------------------------
+inline size_t field_bytes(const Geom &g, int prec, int nrhs) {
+    size_t per = prec == HISQ_FP64 ? 48 : prec == HISQ_FP32 ? 24 : 16;
+    return (size_t)nrhs * (size_t)g.vh * per;
+}
+
+// ---------------------------------------------------------------------------
+// Complex helpers (real arithmetic, written out for the compiler).
+// ---------------------------------------------------------------------------
+template <typename T> struct cplx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ void cmac(cplx<T> &acc, T ar, T ai, cplx<T> b) {
+    acc.re = fma(ar, b.re, acc.re);
+    acc.re = fma(-ai, b.im, acc.re);
+    acc.im = fma(ar, b.im, acc.im);
+    acc.im = fma(ai, b.re, acc.im);
+}
+
+// acc += conj(a) * b
+template <typename T> __device__ __forceinline__ void cmac_conj(cplx<T> &acc, T ar, T ai, cplx<T> b) {
+    acc.re = fma(ar, b.re, acc.re);
+    acc.re = fma(ai, b.im, acc.re);
+    acc.im = fma(ar, b.im, acc.im);
+    acc.im = fma(-ai, b.re, acc.im);
+}
+
+// Wavefront-wide sum (wave64) by butterfly shuffles.
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace hisq

@@ -1,0 +1,239 @@
+// The even/odd HISQ Dslash on gfx950.
+//
+// Two thread mappings, chosen per problem by the autotuner:
+//  * SITE:  one thread per output site; NIN right-hand sides per thread share
+//           every link load (the N_inner loop of the paper's Sec. 5.1), more
+//           right-hand sides over gridDim.y (N_outer).
+//  * DIR:   four consecutive lanes per output site, lane mu handling the four
+//           hops (+-1, +-3) along direction mu; the partial sums are combined
+//           by two butterfly shuffles.  Four times the wavefronts of SITE, so
+//           a 32^3x8 lattice fills all 256 CUs with more loads in flight.
+// Both read every link matrix exactly once per application, as 16-byte
+// coalesced chunks of the structure-of-arrays link layout.
+#pragma once
+
+#include "access.hpp"
+#include "reduce.hpp"
+
+namespace hisq {
+
+enum { VAR_SITE = 0, VAR_DIR = 1 };
+enum { EPI_PLAIN = 0, EPI_AXPY = 1 };
+
+struct DslashParams {
+    Geom g;
+    int out_parity;
+    int nrhs;
+    int xcd_remap;  // map consecutive workgroups of one XCD to neighbouring sites
+    const char *links;
+    const void *in;
+    void *out;
+    const void *y;  // EPI_AXPY: out = ad * D in + ay * y (y on the output parity)
+    double ad, ay;
+};
+
+// Coordinates of half-lattice site i of parity p.
+struct Site {
+    int x, y, z, t;
+};
+
+__device__ __forceinline__ Site site_coords(const Geom &g, int p, int i) {
+    Site s;
+    const int xh = i % g.hx;
+    int rest = i / g.hx;
+    s.y = rest % g.ny;
+    rest /= g.ny;
+    s.z = rest % g.nz;
+    s.t = rest / g.nz;
+    s.x = 2 * xh + ((s.y + s.z + s.t + p) & 1);
+    return s;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip.  With
+// remapping, XCD k works on one contiguous range of logical blocks (nearby
+// sites), so neighbour colour vectors are shared within that XCD's L2.
+__device__ __forceinline__ int logical_block(int remap) {
+    const int b = blockIdx.x;
+    if (!remap)
+        return b;
+    const int G = gridDim.x;
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, j = b >> 3;
+    return x * q + min(x, r) + j;
+}
+
+// One hop: load the link once, apply it (BACK: its adjoint) to NIN colour
+// vectors at the neighbour and accumulate into tmp with sign sg.
+template <int LP, int FP, int NIN, bool BACK, typename A>
+__device__ __forceinline__ void hop(const char *blk, int vh, int ilink, const void *in, int ipsi,
+                                    int r0, int nr, A sg, cplx<A> (&tmp)[NIN][3]) {
+    A m[18];
+    LinkIO<LP>::load(blk, vh, ilink, m);
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        if (r < nr) {
+            cplx<A> v[3];
+            FieldIO<FP>::template load<A>(in, vh, r0 + r, ipsi, v);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c].re *= sg;
+                v[c].im *= sg;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    if (!BACK)
+                        cmac(tmp[r][a], m[6 * a + 2 * b], m[6 * a + 2 * b + 1], v[b]);
+                    else  // -(U^+)_{ab} v_b = -conj(U_{ba}) v_b
+                        cmac_conj(tmp[r][a], -m[6 * b + 2 * a], -m[6 * b + 2 * a + 1], v[b]);
+                }
+            }
+        }
+    }
+}
+
+template <int NIN, typename A> __device__ __forceinline__ void zero(cplx<A> (&v)[NIN][3]) {
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            v[r][a].re = v[r][a].im = (A)0;
+}
+
+// Half-lattice index and time-boundary sign of the neighbour `step` sites
+// along mu of a site with coordinate c (extent n, half-index stride `stride`).
+template <typename A>
+__device__ __forceinline__ void neighbour(const Geom &g, int i, int c, int n, int stride, int mu, int step,
+                                          int &nb, A &sg) {
+    int v = c + step;
+    const bool wrap = v >= n || v < 0;
+    v = v >= n ? v - n : (v < 0 ? v + n : v);
+    nb = mu == 0 ? i + ((v >> 1) - (c >> 1)) : i + (v - c) * stride;
+    sg = (wrap && mu == 3) ? (A)g.t_bc : (A)1;
+}
+
+// The four hops along direction mu (runtime) of site s (half index i, parity
+// p), times eta_mu(s), accumulated into acc.
+template <int LP, int FP, int NIN, typename A>
+__device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
+                                                 int i, const Site &s, int mu, int r0, int nr,
+                                                 cplx<A> (&acc)[NIN][3]) {
+    constexpr int RB = Prec<LP>::real_bytes;
+    const int vh = g.vh;
+    const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
+    const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
+    const int stride = mu == 1 ? g.hx : mu == 2 ? g.hx * g.ny : g.hx * g.ny * g.nz;
+    int n1, n2, n3, n4;
+    A s1, s2, s3, s4;
+    neighbour<A>(g, i, c, n, stride, mu, +1, n1, s1);
+    neighbour<A>(g, i, c, n, stride, mu, -1, n2, s2);
+    neighbour<A>(g, i, c, n, stride, mu, +3, n3, s3);
+    neighbour<A>(g, i, c, n, stride, mu, -3, n4, s4);
+    cplx<A> tmp[NIN][3];
+    zero<NIN, A>(tmp);
+    const int q = 1 - p;
+    hop<LP, FP, NIN, false>(links + link_block(0, p, mu, vh, RB), vh, i, in, n1, r0, nr, s1, tmp);
+    hop<LP, FP, NIN, true>(links + link_block(0, q, mu, vh, RB), vh, n2, in, n2, r0, nr, s2, tmp);
+    hop<LP, FP, NIN, false>(links + link_block(1, p, mu, vh, RB), vh, i, in, n3, r0, nr, s3, tmp);
+    hop<LP, FP, NIN, true>(links + link_block(1, q, mu, vh, RB), vh, n4, in, n4, r0, nr, s4, tmp);
+    const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+    const A eta = (par & 1) ? (A)-1 : (A)1;
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[r][a].re = fma(eta, tmp[r][a].re, acc[r][a].re);
+            acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
+        }
+}
+
+// acc = (D psi)(site i of parity p), all four directions in this thread.
+template <int LP, int FP, int NIN, typename A>
+__device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
+                                            int r0, int nr, cplx<A> (&acc)[NIN][3]) {
+    const Site s = site_coords(g, p, i);
+    zero<NIN, A>(acc);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+        dslash_direction<LP, FP, NIN, A>(g, p, links, in, i, s, mu, r0, nr, acc);
+}
+
+// out = ad * acc + ay * y  (EPI_AXPY) for right-hand side r at site i.
+template <int FP, int EPI, typename A>
+__device__ __forceinline__ void epilogue(const DslashParams &prm, int r, int i, cplx<A> (&v)[3]) {
+    if (EPI == EPI_AXPY) {
+        cplx<A> yv[3];
+        FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r, i, yv);
+        const A ad = (A)prm.ad, ay = (A)prm.ay;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a].re = fma(ad, v[a].re, ay * yv[a].re);
+            v[a].im = fma(ad, v[a].im, ay * yv[a].im);
+        }
+    }
+}
+
+template <int LP, int FP, int NIN, int EPI>
+__global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm) {
+    using A = typename Prec<LP>::acc;
+    const int i = logical_block(prm.xcd_remap) * blockDim.x + threadIdx.x;
+    if (i >= prm.g.vh)
+        return;
+    const int r0 = blockIdx.y * NIN;
+    const int nr = min(NIN, prm.nrhs - r0);
+    cplx<A> acc[NIN][3];
+    dslash_site<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        if (r < nr) {
+            epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
+        }
+    }
+}
+
+template <int LP, int FP, int NIN, int EPI>
+__global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm) {
+    using A = typename Prec<LP>::acc;
+    const int mu = threadIdx.x & 3;
+    const int i = logical_block(prm.xcd_remap) * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    // a site's four lanes are in one wavefront and share validity, so whole
+    // quads leave together and the shuffles below see only active partners
+    if (i >= prm.g.vh)
+        return;
+    const int r0 = blockIdx.y * NIN;
+    const int nr = min(NIN, prm.nrhs - r0);
+    const Site s = site_coords(prm.g, prm.out_parity, i);
+    cplx<A> acc[NIN][3];
+    zero<NIN, A>(acc);
+    dslash_direction<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, r0, nr, acc);
+    // sum over the quad: (mu0 + mu1) + (mu2 + mu3), identical in all 4 lanes
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[r][a].re += __shfl_xor(acc[r][a].re, 1, 64);
+            acc[r][a].im += __shfl_xor(acc[r][a].im, 1, 64);
+            acc[r][a].re += __shfl_xor(acc[r][a].re, 2, 64);
+            acc[r][a].im += __shfl_xor(acc[r][a].im, 2, 64);
+        }
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        if (r < nr) {
+            epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            if constexpr (FP == HISQ_FP16N) {
+                if (mu == 0)  // one 16-byte record holds the whole site
+                    FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
+            } else {
+                // lane mu < 3 writes colour mu (static indices keep acc in registers)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (mu == c)
+                        FieldIO<FP>::template store_colour<A>(prm.out, prm.g.vh, r0 + r, i, c, acc[r][c]);
+            }
+        }
+    }
+}
+
+}  // namespace hisq

@@ -1,0 +1,42 @@
+// Template dispatch of the Dslash kernels over (variant, NIN, epilogue) for
+// one (link precision, field precision) pair; each pair is instantiated in
+// its own translation unit so the instantiations compile in parallel.
+#pragma once
+
+#include "internal.hpp"
+#include "dslash.hpp"
+
+namespace hisq {
+
+template <int LP, int FP, int NIN, int EPI>
+hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
+    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
+    const dim3 grid((unsigned)((prm.g.vh + sites_per_block - 1) / sites_per_block),
+                    (unsigned)((prm.nrhs + NIN - 1) / NIN));
+    DslashParams p = prm;
+    p.xcd_remap = s.xcd_remap;
+    if (s.variant == VAR_DIR)
+        dslash_dir_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
+    else
+        dslash_site_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+template <int LP, int FP, int EPI>
+hipError_t dslash_by_nin(const DslashParams &prm, DslashShape s, hipStream_t st) {
+    switch (s.nin) {
+    case 1: return dslash_go<LP, FP, 1, EPI>(prm, s, st);
+    case 2: return dslash_go<LP, FP, 2, EPI>(prm, s, st);
+    case 4: return dslash_go<LP, FP, 4, EPI>(prm, s, st);
+    case 8: return dslash_go<LP, FP, 8, EPI>(prm, s, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LP, int FP>
+hipError_t dslash_launch_pair(const DslashParams &prm, int epi, DslashShape s, hipStream_t st) {
+    return epi == EPI_AXPY ? dslash_by_nin<LP, FP, EPI_AXPY>(prm, s, st)
+                           : dslash_by_nin<LP, FP, EPI_PLAIN>(prm, s, st);
+}
+
+}  // namespace hisq

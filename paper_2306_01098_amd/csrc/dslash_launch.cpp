@@ -1,0 +1,34 @@
+// Host dispatch of the Dslash over precisions and launch shapes.
+#include "internal.hpp"
+#include "dslash.hpp"
+
+namespace hisq {
+
+hipError_t dslash_launch_f64(const DslashParams &, int, DslashShape, hipStream_t);
+hipError_t dslash_launch_f32(const DslashParams &, int, DslashShape, hipStream_t);
+hipError_t dslash_launch_f16(const DslashParams &, int, DslashShape, hipStream_t);
+hipError_t dslash_launch_f16f32(const DslashParams &, int, DslashShape, hipStream_t);
+
+bool dslash_shape_supported(DslashShape s) {
+    const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR;
+    const bool nin_ok = s.nin == 1 || s.nin == 2 || s.nin == 4 || s.nin == 8;
+    const bool blk_ok = s.block == 64 || s.block == 128 || s.block == 256;
+    const bool remap_ok = s.xcd_remap == 0 || s.xcd_remap == 1;
+    return var_ok && nin_ok && blk_ok && remap_ok;
+}
+
+hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape s, hipStream_t st) {
+    if (!dslash_shape_supported(s))
+        return hipErrorInvalidValue;
+    if (lp == HISQ_FP64 && fp == HISQ_FP64)
+        return dslash_launch_f64(prm, epi, s, st);
+    if (lp == HISQ_FP32 && fp == HISQ_FP32)
+        return dslash_launch_f32(prm, epi, s, st);
+    if (lp == HISQ_FP16N && fp == HISQ_FP16N)
+        return dslash_launch_f16(prm, epi, s, st);
+    if (lp == HISQ_FP16N && fp == HISQ_FP32)
+        return dslash_launch_f16f32(prm, epi, s, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hisq

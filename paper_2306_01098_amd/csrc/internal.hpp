@@ -1,0 +1,32 @@
+// Host-side declarations shared by the translation units of the library.
+#pragma once
+
+#include "common.hpp"
+#include "access.hpp"
+
+namespace hisq {
+
+hipError_t launch_pack_links(const Geom &g, int prec, const void *fat, const void *naik, void *packed,
+                             hipStream_t st);
+hipError_t launch_unpack_links(const Geom &g, int prec, const void *packed, void *fat, void *naik,
+                               hipStream_t st);
+hipError_t launch_pack_field(const Geom &g, int prec, int nrhs, const void *src, void *dst, hipStream_t st);
+hipError_t launch_unpack_field(const Geom &g, int prec, int nrhs, const void *src, void *dst, hipStream_t st);
+
+// Launch shape of the Dslash: thread mapping (VAR_SITE / VAR_DIR),
+// right-hand sides per thread, block size, XCD-aware block order.
+struct DslashShape {
+    int variant;
+    int nin;
+    int block;
+    int xcd_remap;
+};
+
+struct DslashParams;
+// lp: link precision; fp: field precision (equal to lp except the mixed
+// variant lp = FP16N, fp = FP32).  epi: EPI_PLAIN or EPI_AXPY.
+hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape shape,
+                         hipStream_t st);
+bool dslash_shape_supported(DslashShape s);
+
+}  // namespace hisq

@@ -1,0 +1,166 @@
+// The Dslash autotuner: times every supported launch shape on the caller's
+// buffers with HIP events and keeps the fastest per (extents, precisions,
+// nrhs) in the context.
+#include <algorithm>
+#include <vector>
+
+#include "api_util.hpp"
+#include "dslash.hpp"
+
+namespace hisq {
+
+DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
+    (void)g;
+    (void)fp;
+    DslashShape s;
+    s.variant = VAR_DIR;
+    s.block = 256;
+    s.xcd_remap = 1;
+    s.nin = nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    if (lp == HISQ_FP64 && s.nin > 2)
+        s.nin = 2;
+    return s;
+}
+
+std::vector<DslashShape> candidate_shapes(int nrhs) {
+    std::vector<DslashShape> out;
+    for (int var : {VAR_SITE, VAR_DIR})
+        for (int nin : {1, 2, 4, 8}) {
+            if (nin > 1 && nin > nrhs)
+                continue;
+            for (int block : {64, 128, 256})
+                for (int remap : {0, 1})
+                    out.push_back(DslashShape{var, nin, block, remap});
+        }
+    return out;
+}
+
+// Median time (ms) of `reps` launches of one shape; <0 on a launch error.
+static float time_shape(const DslashParams &prm, int lp, int fp, DslashShape s, hipStream_t st, int reps,
+                        hipEvent_t e0, hipEvent_t e1, hipError_t *err) {
+    std::vector<float> t;
+    for (int k = 0; k < 2; ++k) {  // warm-up
+        *err = launch_dslash(prm, lp, fp, EPI_PLAIN, s, st);
+        if (*err != hipSuccess)
+            return -1.f;
+    }
+    for (int k = 0; k < reps; ++k) {
+        hipEventRecord(e0, st);
+        *err = launch_dslash(prm, lp, fp, EPI_PLAIN, s, st);
+        hipEventRecord(e1, st);
+        if (*err != hipSuccess)
+            return -1.f;
+        *err = hipEventSynchronize(e1);
+        if (*err != hipSuccess)
+            return -1.f;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+hisq_status tune_dslash(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs, const void *links,
+                        const void *in, void *out, hipStream_t st, DslashShape *best_out) {
+    DslashParams prm{};
+    prm.g = g;
+    prm.out_parity = 0;
+    prm.nrhs = nrhs;
+    prm.links = static_cast<const char *>(links);
+    prm.in = in;
+    prm.out = out;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess)
+        return device_fail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return device_fail(e, "hipEventCreate");
+    }
+    DslashShape best = default_shape(g, lp, fp, nrhs);
+    float best_ms = 1e30f;
+    hisq_status status = HISQ_OK;
+    for (const DslashShape &s : candidate_shapes(nrhs)) {
+        hipError_t err = hipSuccess;
+        const float ms = time_shape(prm, lp, fp, s, st, 5, e0, e1, &err);
+        if (err != hipSuccess) {
+            status = device_fail(err, "tune_dslash");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (status != HISQ_OK)
+        return status;
+    ctx->store(g, lp, fp, nrhs, best);
+    if (best_out)
+        *best_out = best;
+    return HISQ_OK;
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" {
+
+hisq_status hisq_tune_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                             const void *links, const void *in, void *out, void *stream) {
+    if (!ctx)
+        return fail(HISQ_ERR_INVALID_ARG, "ctx is NULL (the tuned shape is kept in the context)");
+    hisq_status s = check_lattice(lat);
+    if (s == HISQ_OK) s = check_prec(prec);
+    if (s == HISQ_OK) s = check_nrhs(nrhs);
+    if (s == HISQ_OK) s = check_ptr(links, "links");
+    if (s == HISQ_OK) s = check_ptr(in, "in");
+    if (s == HISQ_OK) s = check_ptr(out, "out");
+    if (s == HISQ_OK && in == out)
+        s = fail(HISQ_ERR_INVALID_ARG, "in and out must not alias");
+    if (s == HISQ_OK) s = set_device(ctx);
+    if (s != HISQ_OK)
+        return s;
+    return tune_dslash(ctx, make_geom(*lat), prec, prec, nrhs, links, in, out, static_cast<hipStream_t>(stream),
+                       nullptr);
+}
+
+hisq_status hisq_get_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                                  hisq_dslash_shape *shape) {
+    hisq_status s = check_lattice(lat);
+    if (s == HISQ_OK) s = check_prec(prec);
+    if (s == HISQ_OK) s = check_nrhs(nrhs);
+    if (s == HISQ_OK) s = check_ptr(shape, "shape");
+    if (s != HISQ_OK)
+        return s;
+    const DslashShape d = pick_shape(ctx, make_geom(*lat), prec, prec, nrhs);
+    shape->variant = d.variant;
+    shape->nin = d.nin;
+    shape->block = d.block;
+    shape->xcd_remap = d.xcd_remap;
+    return HISQ_OK;
+}
+
+hisq_status hisq_set_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, int32_t nrhs,
+                                  const hisq_dslash_shape *shape) {
+    if (!ctx)
+        return fail(HISQ_ERR_INVALID_ARG, "ctx is NULL");
+    hisq_status s = check_lattice(lat);
+    if (s == HISQ_OK) s = check_prec(prec);
+    if (s == HISQ_OK) s = check_nrhs(nrhs);
+    if (s == HISQ_OK) s = check_ptr(shape, "shape");
+    if (s != HISQ_OK)
+        return s;
+    const DslashShape d{shape->variant, shape->nin, shape->block, shape->xcd_remap};
+    if (!dslash_shape_supported(d))
+        return fail(HISQ_ERR_INVALID_ARG, "unsupported shape (variant %d, nin %d, block %d, remap %d)", d.variant,
+                    d.nin, d.block, d.xcd_remap);
+    ctx->store(make_geom(*lat), prec, prec, nrhs, d);
+    return HISQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""Thin Python binding of ``libhisq.so`` (the C ABI in ``include/hisq.h``).
+
+Argument marshalling only: torch tensors on the GPU are passed as raw device
+pointers, ``torch.cuda.current_stream()`` supplies the ``hipStream_t``, and a
+non-OK status raises :class:`HisqError`.  Every computation runs in the HIP
+kernels of the library; there is no CPU fallback.  If the library is not
+built, :func:`load` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhisq.so")
+
+HISQ_FP64, HISQ_FP32, HISQ_FP16N = 0, 1, 2
+PRECS = {"fp64": HISQ_FP64, "fp32": HISQ_FP32, "fp16n": HISQ_FP16N}
+HISQ_MAX_RHS = 16
+
+OK, INVALID_ARG, NOT_CONVERGED, BREAKDOWN, DEVICE, WORKSPACE, UNSUPPORTED = range(7)
+
+
+class HisqError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class hisq_lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("t_bc", ctypes.c_int32)]
+
+
+class hisq_dslash_shape(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("nin", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.variant, self.nin, self.block, self.xcd_remap)
+
+
+class hisq_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
+                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_LAT = ctypes.POINTER(hisq_lattice)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "hisq_context_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32]),
+    "hisq_context_destroy": (None, [_vp]),
+    "hisq_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "hisq_last_error": (ctypes.c_char_p, []),
+    "hisq_links_bytes": (ctypes.c_size_t, [_LAT, ctypes.c_int]),
+    "hisq_field_bytes": (ctypes.c_size_t, [_LAT, ctypes.c_int, ctypes.c_int32]),
+    "hisq_pack_links": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "hisq_unpack_links": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "hisq_pack_field": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp]),
+    "hisq_unpack_field": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp]),
+    "hisq_dslash": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp,
+                                   ctypes.c_int32, _vp]),
+    "hisq_apply_m": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                    ctypes.c_int32, _vp]),
+    "hisq_tune_dslash": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "hisq_get_dslash_shape": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32,
+                                             ctypes.POINTER(hisq_dslash_shape)]),
+    "hisq_set_dslash_shape": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32,
+                                             ctypes.POINTER(hisq_dslash_shape)]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        lib = load()
+        detail = lib.hisq_last_error().decode() or lib.hisq_status_string(status).decode()
+        raise HisqError(status, where, detail)
+
+
+def lattice(dims, t_bc: int) -> hisq_lattice:
+    lat = hisq_lattice()
+    for k in range(4):
+        lat.dims[k] = int(dims[k])
+    lat.t_bc = int(t_bc)
+    return lat
+
+
+def _prec(p) -> int:
+    return PRECS[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None, name: str, nbytes: int | None = None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """Owns a hisq_context (device + autotune cache)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(load().hisq_context_create(ctypes.byref(h), int(device)), "hisq_context_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load().hisq_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ctx(ctx):
+    return None if ctx is None else ctx.handle
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def hisq_links_bytes(lat: hisq_lattice, prec) -> int:
+    return int(load().hisq_links_bytes(ctypes.byref(lat), _prec(prec)))
+
+
+def hisq_field_bytes(lat: hisq_lattice, prec, nrhs: int = 1) -> int:
+    return int(load().hisq_field_bytes(ctypes.byref(lat), _prec(prec), int(nrhs)))
+
+
+def empty_links(lat, prec, device="cuda") -> torch.Tensor:
+    return torch.empty(hisq_links_bytes(lat, prec), dtype=torch.uint8, device=device)
+
+
+def empty_field(lat, prec, nrhs: int = 1, device="cuda") -> torch.Tensor:
+    return torch.empty(hisq_field_bytes(lat, prec, nrhs), dtype=torch.uint8, device=device)
+
+
+def hisq_pack_links(lat, prec, fat_c128: torch.Tensor, naik_c128: torch.Tensor, packed: torch.Tensor,
+                    ctx=None, stream=None):
+    vol = 1
+    for d in lat.dims:
+        vol *= d
+    n = 4 * vol * 9 * 16
+    _check(load().hisq_pack_links(_ctx(ctx), ctypes.byref(lat), _prec(prec),
+                                  _ptr(fat_c128, "fat_c128", n), _ptr(naik_c128, "naik_c128", n),
+                                  _ptr(packed, "packed", hisq_links_bytes(lat, prec)), _stream(stream)),
+           "hisq_pack_links")
+
+
+def hisq_unpack_links(lat, prec, packed: torch.Tensor, fat_c128: torch.Tensor, naik_c128: torch.Tensor,
+                      ctx=None, stream=None):
+    vol = 1
+    for d in lat.dims:
+        vol *= d
+    n = 4 * vol * 9 * 16
+    _check(load().hisq_unpack_links(_ctx(ctx), ctypes.byref(lat), _prec(prec),
+                                    _ptr(packed, "packed", hisq_links_bytes(lat, prec)),
+                                    _ptr(fat_c128, "fat_c128", n), _ptr(naik_c128, "naik_c128", n),
+                                    _stream(stream)), "hisq_unpack_links")
+
+
+def _half_bytes(lat, nrhs):
+    vol = 1
+    for d in lat.dims:
+        vol *= d
+    return nrhs * (vol // 2) * 3 * 16
+
+
+def hisq_pack_field(lat, prec, nrhs: int, half_c128: torch.Tensor, packed: torch.Tensor,
+                    ctx=None, stream=None):
+    _check(load().hisq_pack_field(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
+                                  _ptr(half_c128, "half_c128", _half_bytes(lat, nrhs)),
+                                  _ptr(packed, "packed", hisq_field_bytes(lat, prec, nrhs)),
+                                  _stream(stream)), "hisq_pack_field")
+
+
+def hisq_unpack_field(lat, prec, nrhs: int, packed: torch.Tensor, half_c128: torch.Tensor,
+                      ctx=None, stream=None):
+    _check(load().hisq_unpack_field(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
+                                    _ptr(packed, "packed", hisq_field_bytes(lat, prec, nrhs)),
+                                    _ptr(half_c128, "half_c128", _half_bytes(lat, nrhs)),
+                                    _stream(stream)), "hisq_unpack_field")
+
+
+def hisq_dslash(lat, prec, out_parity: int, links, inp, out, nrhs: int = 1, ctx=None, stream=None):
+    fb = hisq_field_bytes(lat, prec, nrhs)
+    _check(load().hisq_dslash(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(out_parity),
+                              _ptr(links, "links", hisq_links_bytes(lat, prec)),
+                              _ptr(inp, "in", fb), _ptr(out, "out", fb), int(nrhs), _stream(stream)),
+           "hisq_dslash")
+
+
+def hisq_apply_m(lat, prec, mass: float, links, in_even, out_even, tmp_odd, nrhs: int = 1,
+                 ctx=None, stream=None):
+    fb = hisq_field_bytes(lat, prec, nrhs)
+    _check(load().hisq_apply_m(_ctx(ctx), ctypes.byref(lat), _prec(prec), float(mass),
+                               _ptr(links, "links", hisq_links_bytes(lat, prec)),
+                               _ptr(in_even, "in_even", fb), _ptr(out_even, "out_even", fb),
+                               _ptr(tmp_odd, "tmp_odd", fb), int(nrhs), _stream(stream)),
+           "hisq_apply_m")
+
+
+def hisq_tune_dslash(lat, prec, nrhs: int, links, inp, out, ctx, stream=None):
+    fb = hisq_field_bytes(lat, prec, nrhs)
+    _check(load().hisq_tune_dslash(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
+                                   _ptr(links, "links", hisq_links_bytes(lat, prec)),
+                                   _ptr(inp, "in", fb), _ptr(out, "out", fb), _stream(stream)),
+           "hisq_tune_dslash")
+
+
+def hisq_get_dslash_shape(lat, prec, nrhs: int = 1, ctx=None):
+    sh = hisq_dslash_shape()
+    _check(load().hisq_get_dslash_shape(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
+                                        ctypes.byref(sh)), "hisq_get_dslash_shape")
+    return sh.as_tuple()
+
+
+def hisq_set_dslash_shape(lat, prec, nrhs: int, shape, ctx):
+    sh = hisq_dslash_shape(*[int(v) for v in shape])
+    _check(load().hisq_set_dslash_shape(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
+                                        ctypes.byref(sh)), "hisq_set_dslash_shape")
+
+
+# ---------------------------------------------------------------------------
+# Conveniences built only from the entry points above
+# ---------------------------------------------------------------------------
+
+def to_device_c128(a) -> torch.Tensor:
+    """Host complex array -> contiguous complex128 GPU tensor."""
+    return torch.as_tensor(a, dtype=torch.complex128).contiguous().cuda()
+
+
+def pack_links_from_host(lat, prec, fat, naik, ctx=None) -> torch.Tensor:
+    packed = empty_links(lat, prec)
+    f, w = to_device_c128(fat), to_device_c128(naik)
+    hisq_pack_links(lat, prec, f, w, packed, ctx=ctx)
+    del f, w
+    return packed
+
+
+def pack_field_from_host(lat, prec, half, ctx=None) -> torch.Tensor:
+    half = torch.as_tensor(half, dtype=torch.complex128)
+    if half.dim() == 2:
+        half = half[None]
+    nrhs = half.shape[0]
+    packed = empty_field(lat, prec, nrhs)
+    hisq_pack_field(lat, prec, nrhs, half.contiguous().cuda(), packed, ctx=ctx)
+    return packed
+
+
+def unpack_field_to_host(lat, prec, packed, nrhs: int = 1, ctx=None):
+    vol = 1
+    for d in lat.dims:
+        vol *= d
+    out = torch.empty((nrhs, vol // 2, 3), dtype=torch.complex128, device="cuda")
+    hisq_unpack_field(lat, prec, nrhs, packed, out, ctx=ctx)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

@@ -1,0 +1,80 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hisq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hisq_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2306_01098_amd import hisq as h
+    return h.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2306_01098_amd import hisq as h
+    assert sorted(h.declared_symbols()) == declared_functions()
+
+
+def test_status_strings(lib):
+    from paper_2306_01098_amd import hisq as h
+    for s in range(7):
+        assert lib.hisq_status_string(s)
+    assert lib.hisq_status_string(h.NOT_CONVERGED) == b"not converged"
+
+
+@pytest.mark.parametrize("dims,t_bc", [((4, 4, 4, 5), 1), ((2, 4, 4, 4), 1), ((4, 4, 4, 4), 0),
+                                      ((0, 4, 4, 4), -1)])
+def test_invalid_lattice_rejected(lib, dims, t_bc):
+    from paper_2306_01098_amd import hisq as h
+    lat = h.lattice(dims, t_bc)
+    assert h.hisq_links_bytes(lat, "fp64") == 0
+    st = lib.hisq_dslash(None, ctypes.byref(lat), 0, 0, ctypes.c_void_p(16), ctypes.c_void_p(32),
+                         ctypes.c_void_p(48), 1, None)
+    assert st == h.INVALID_ARG
+    assert lib.hisq_last_error()
+
+
+def test_sizes(lib):
+    from paper_2306_01098_amd import hisq as h
+    lat = h.lattice((32, 32, 32, 8), -1)
+    V = 32 ** 3 * 8
+    assert h.hisq_links_bytes(lat, "fp64") == 2 * 4 * V * 18 * 8 == 301989888
+    assert h.hisq_links_bytes(lat, "fp32") == 2 * 4 * V * 18 * 4
+    assert h.hisq_links_bytes(lat, "fp16n") == 2 * 4 * V * 18 * 2
+    assert h.hisq_field_bytes(lat, "fp64", 3) == 3 * (V // 2) * 48
+    assert h.hisq_field_bytes(lat, "fp16n", 1) == (V // 2) * 16
+    assert h.hisq_field_bytes(lat, "fp64", 17) == 0
+    assert h.hisq_field_bytes(lat, "fp64", 0) == 0
+
+
+def test_dslash_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    lat = ctypes.byref(h.lattice((4, 4, 4, 4), 1))
+    p = ctypes.c_void_p
+    # bad parity, NULL pointer, aliasing, bad nrhs, bad precision
+    assert lib.hisq_dslash(None, lat, 0, 2, p(16), p(32), p(48), 1, None) == h.INVALID_ARG
+    assert lib.hisq_dslash(None, lat, 0, 0, None, p(32), p(48), 1, None) == h.INVALID_ARG
+    assert lib.hisq_dslash(None, lat, 0, 0, p(16), p(32), p(32), 1, None) == h.INVALID_ARG
+    assert lib.hisq_dslash(None, lat, 0, 0, p(16), p(32), p(48), 0, None) == h.INVALID_ARG
+    assert lib.hisq_dslash(None, lat, 7, 0, p(16), p(32), p(48), 1, None) == h.INVALID_ARG
+    assert lib.hisq_apply_m(None, lat, 0, 0.0, p(16), p(32), p(48), p(64), 1, None) == h.INVALID_ARG
+    assert b"mass" in lib.hisq_last_error()

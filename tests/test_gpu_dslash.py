@@ -1,0 +1,244 @@
+"""GPU parity of the packed layouts, the Dslash and M_e against the FP64 oracle.
+
+Tolerances:
+  FP64       relative L2 and max-norm error <= 1e-13 against the oracle.
+  FP32       against the oracle evaluated in FP64 on FP32-rounded inputs
+             (same storage rounding as the kernel): relative <= 1e-6, which
+             bounds the FP32 accumulation error of 16 mat-vecs.
+  FP16N      against the oracle on inputs rounded to the FP16+norm format; the
+             output is itself rounded to that format, so each component may
+             differ by half a binary16 ulp of its site norm (2^-12 n) plus the
+             FP32 accumulation error.
+"""
+import numpy as np
+import pytest
+import torch
+
+import hisq_inputs as gen
+from oracle import hisq as O
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [((4, 4, 4, 4), +1), ((8, 8, 8, 8), +1), ((8, 8, 8, 8), -1), ((6, 4, 8, 10), -1),
+            ((12, 12, 12, 4), -1)]
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def fields():
+    cache = {}
+
+    def get(dims, t_bc, nsrc=1, kind="haar"):
+        key = (dims, t_bc, nsrc, kind)
+        if key not in cache:
+            k = 100 + len(cache)
+            if kind == "haar":
+                w = gen.workload_haar(dims, k, t_bc, nsrc)
+            else:
+                w = gen.workload_smooth(dims, k, t_bc, 0.3, nsrc)
+            w["src_o"] = gen.gaussian_half_field(gen.rng_for(k, 20), dims, nsrc)
+            cache[key] = w
+        return cache[key]
+    return get
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16n"])
+def test_pack_unpack_field_format(gpu_lib, fields, prec):
+    h = gpu_lib
+    w = fields((6, 4, 8, 10), -1, 3)
+    lat = h.lattice(w["dims"], w["t_bc"])
+    src = w["src"] * np.array([1.0, 1e-3, 37.0])[:, None, None]
+    src[1, 5] = 0.0                      # a zero site keeps a zero norm
+    packed = h.pack_field_from_host(lat, prec, src)
+    back = h.unpack_field_to_host(lat, prec, packed, 3)
+    # bit-exact agreement with the storage format as the oracle defines it
+    np.testing.assert_array_equal(back, O.quantize_field(src, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16n"])
+def test_pack_unpack_links_format(gpu_lib, fields, prec):
+    h = gpu_lib
+    w = fields((6, 4, 8, 10), -1, 1, "smooth")
+    lat = h.lattice(w["dims"], w["t_bc"])
+    packed = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    f = torch.empty(w["fat"].shape, dtype=torch.complex128, device="cuda")
+    n = torch.empty_like(f)
+    h.hisq_unpack_links(lat, prec, packed, f, n)
+    torch.cuda.synchronize()
+    ql = O.quantized_lattice(O.lattice_from(w), prec)
+    np.testing.assert_array_equal(f.cpu().numpy(), ql.X)
+    np.testing.assert_array_equal(n.cpu().numpy(), ql.W)
+
+
+@pytest.mark.parametrize("dims,t_bc", LATTICES)
+@pytest.mark.parametrize("parity", [0, 1])
+def test_dslash_fp64(gpu_lib, fields, dims, t_bc, parity):
+    h = gpu_lib
+    w = fields(dims, t_bc)
+    lat = h.lattice(dims, t_bc)
+    lat_o = O.lattice_from(w)
+    links = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    src = w["src_o"][0] if parity == 0 else w["src"][0]
+    inp = h.pack_field_from_host(lat, "fp64", src)
+    out = h.empty_field(lat, "fp64")
+    h.hisq_dslash(lat, "fp64", parity, links, inp, out)
+    got = h.unpack_field_to_host(lat, "fp64", out)[0]
+    ref = lat_o.D_eo(src) if parity == 0 else lat_o.D_oe(src)
+    assert relerr(got, ref) <= 1e-13
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("fp16n", None)])
+@pytest.mark.parametrize("dims,t_bc", [((8, 8, 8, 8), -1), ((6, 4, 8, 10), +1)])
+def test_dslash_reduced_precision(gpu_lib, fields, prec, tol, dims, t_bc):
+    h = gpu_lib
+    w = fields(dims, t_bc, kind="smooth")
+    lat = h.lattice(dims, t_bc)
+    lat_q = O.quantized_lattice(O.lattice_from(w), prec)
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    for parity in (0, 1):
+        src = w["src_o"][0] if parity == 0 else w["src"][0]
+        inp = h.pack_field_from_host(lat, prec, src)
+        out = h.empty_field(lat, prec)
+        h.hisq_dslash(lat, prec, parity, links, inp, out)
+        got = h.unpack_field_to_host(lat, prec, out)[0]
+        srcq = O.quantize_field(src, prec)
+        ref = lat_q.D_eo(srcq) if parity == 0 else lat_q.D_oe(srcq)
+        if prec == "fp32":
+            assert relerr(got, ref) <= tol
+        else:
+            n = np.maximum(np.abs(ref.real), np.abs(ref.imag)).max(-1, keepdims=True)
+            bound = (2.0 ** -12 + 2e-6) * n + 1e-6 * np.abs(ref).max()
+            err = np.maximum(np.abs(got.real - ref.real), np.abs(got.imag - ref.imag))
+            worst = np.unravel_index(np.argmax(err / bound), err.shape)
+            assert np.all(err <= bound), (
+                f"parity {parity} site {worst[0]} colour {worst[1]}: err {err[worst]:.3e} "
+                f"bound {bound[worst[0], 0]:.3e} n {n[worst[0], 0]:.3e} got {got[worst]} ref {ref[worst]} "
+                f"sites over: {int((err > bound).any(-1).sum())}")
+        # storage error vs the exact FP64 operator stays at the format's level
+        ref64 = O.lattice_from(w).D_eo(src) if parity == 0 else O.lattice_from(w).D_oe(src)
+        assert relerr(got, ref64) <= (1e-6 if prec == "fp32" else 4e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16n"])
+@pytest.mark.parametrize("nrhs", [3, 16])
+def test_dslash_multi_rhs_columns(gpu_lib, fields, prec, nrhs):
+    """Each column of the batched Dslash equals the single-RHS Dslash."""
+    h = gpu_lib
+    dims, t_bc = (8, 4, 6, 8), -1
+    w = fields(dims, t_bc, nrhs)
+    lat = h.lattice(dims, t_bc)
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, prec, w["src_o"])
+    out = h.empty_field(lat, prec, nrhs)
+    h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs)
+    got = h.unpack_field_to_host(lat, prec, out, nrhs)
+    for r in range(nrhs):
+        one_in = h.pack_field_from_host(lat, prec, w["src_o"][r])
+        one_out = h.empty_field(lat, prec)
+        h.hisq_dslash(lat, prec, 0, links, one_in, one_out, 1)
+        one = h.unpack_field_to_host(lat, prec, one_out)[0]
+        np.testing.assert_array_equal(got[r], one)
+    if prec == "fp64":
+        ref = O.lattice_from(w).D_eo(w["src_o"])
+        assert relerr(got, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_m(gpu_lib, fields, prec):
+    h = gpu_lib
+    dims, t_bc = (8, 8, 8, 8), -1
+    w = fields(dims, t_bc, 2)
+    lat = h.lattice(dims, t_bc)
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, prec, w["src"])
+    out = h.empty_field(lat, prec, 2)
+    tmp = h.empty_field(lat, prec, 2)
+    h.hisq_apply_m(lat, prec, 0.1, links, inp, out, tmp, 2)
+    got = h.unpack_field_to_host(lat, prec, out, 2)
+    lat_q = O.quantized_lattice(O.lattice_from(w), prec)
+    ref = np.stack([lat_q.M_e(0.1, O.quantize_field(s, prec)) for s in w["src"]])
+    assert relerr(got, ref) <= (1e-13 if prec == "fp64" else 2e-6)
+
+
+def test_dslash_32x32x32x8_full_and_deterministic(gpu_lib):
+    """Headline lattice, launch shape of the benchmark: full comparison with the
+    oracle, and two applications bitwise identical."""
+    h = gpu_lib
+    w = gen.workload_2()
+    dims, t_bc = w["dims"], w["t_bc"]
+    lat = h.lattice(dims, t_bc)
+    links = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    src_o = gen.gaussian_half_field(gen.rng_for(2, 30), dims)[0]
+    inp = h.pack_field_from_host(lat, "fp64", src_o)
+    out1, out2 = h.empty_field(lat, "fp64"), h.empty_field(lat, "fp64")
+    h.hisq_dslash(lat, "fp64", 0, links, inp, out1)
+    h.hisq_dslash(lat, "fp64", 0, links, inp, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)
+    got = h.unpack_field_to_host(lat, "fp64", out1)[0]
+    ref = O.lattice_from(w).D_eo(src_o)
+    assert relerr(got, ref) <= 1e-13
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_dslash_rejects_bad_sizes(gpu_lib):
+    h = gpu_lib
+    lat = h.lattice((4, 4, 4, 4), 1)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        h.hisq_dslash(lat, "fp64", 0, small, small, small)
+
+
+def _all_shapes(nrhs):
+    out = []
+    for var in (0, 1):
+        for nin in (1, 2, 4, 8):
+            if nin > 1 and nin > nrhs:
+                continue
+            for block in (64, 128, 256):
+                for remap in (0, 1):
+                    out.append((var, nin, block, remap))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_launch_shape_matches_oracle(gpu_lib, fields, prec):
+    """All shapes the autotuner may pick, on a lattice whose site count is not
+    a multiple of the block (ragged tail) and nrhs = 3 (partial N_inner)."""
+    h = gpu_lib
+    dims, t_bc, nrhs = (6, 4, 8, 10), -1, 3
+    w = fields(dims, t_bc, nrhs)
+    lat = h.lattice(dims, t_bc)
+    ctx = h.Context(0)
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, prec, w["src_o"])
+    lat_q = O.quantized_lattice(O.lattice_from(w), prec)
+    ref = lat_q.D_eo(O.quantize_field(w["src_o"], prec))
+    for shape in _all_shapes(nrhs):
+        h.hisq_set_dslash_shape(lat, prec, nrhs, shape, ctx)
+        assert h.hisq_get_dslash_shape(lat, prec, nrhs, ctx) == shape
+        out = h.empty_field(lat, prec, nrhs)
+        out.fill_(0xFF)
+        h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs, ctx=ctx)
+        got = h.unpack_field_to_host(lat, prec, out, nrhs)
+        assert relerr(got, ref) <= (1e-13 if prec == "fp64" else 1e-6), shape
+
+
+def test_autotuner_picks_a_supported_shape(gpu_lib, fields):
+    h = gpu_lib
+    dims, t_bc = (8, 8, 8, 8), -1
+    w = fields(dims, t_bc)
+    lat = h.lattice(dims, t_bc)
+    ctx = h.Context(0)
+    links = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, "fp64", w["src_o"][0])
+    out = h.empty_field(lat, "fp64")
+    h.hisq_tune_dslash(lat, "fp64", 1, links, inp, out, ctx)
+    assert h.hisq_get_dslash_shape(lat, "fp64", 1, ctx) in _all_shapes(1)
+    h.hisq_dslash(lat, "fp64", 0, links, inp, out, ctx=ctx)
+    got = h.unpack_field_to_host(lat, "fp64", out)[0]
+    assert relerr(got, O.lattice_from(w).D_eo(w["src_o"][0])) <= 1e-13

@@ -92,3 +92,14 @@ def test_quantize_fp16n_format():
     # per site, every component is within half a binary16 ulp of 1 (relative to n)
     assert np.all(np.abs(q - psi) <= (2.0 ** -11 + 2.0 ** -23) * n * np.sqrt(2))
     assert np.all(O.quantize_field_fp16n(np.zeros((2, 3))) == 0)
+
+
+def test_fp16_format_rounds_once_from_binary64():
+    """1 + 2^-11 + 2^-40 is above the binary16 midpoint: one rounding gives
+    1 + 2^-10, while rounding through binary32 first would tie down to 1."""
+    v = np.array([1 + 2.0 ** -11 + 2.0 ** -40])
+    assert O.quantize_links_fp16(v)[0] == 1 + 2.0 ** -10
+    psi = np.array([[1 + 2.0 ** -11 + 2.0 ** -40, 0.5, 0.25]], dtype=complex) * 2.0
+    q = O.quantize_field_fp16n(psi)
+    # the site norm is 2 + 2^-10 + 2^-39 -> binary32 rounds it to 2 + 2^-10
+    assert q[0, 0].real == np.float32(2 + 2.0 ** -10)
