@@ -140,6 +140,52 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
                          double mass, const void *links, const void *in_even, void *out_even,
                          void *tmp_odd, int32_t nrhs, void *stream);
 
+/* Workspace bytes for hisq_cg (nshift = 0) or hisq_multishift_cg (nrhs = 1,
+ * nshift shifts) with inner precision `inner`.  0 on invalid arguments. */
+size_t hisq_cg_workspace_bytes(const hisq_lattice *lat, hisq_prec inner, int32_t nrhs, int32_t nshift);
+
+/* Solve (m^2 - D_eo D_oe) x_k = b_k for nrhs independent right-hand sides
+ * (the CG of Sec. 3.2, "Inverters", with its multi-right-hand-side form: the
+ * columns share every Dslash launch and link load but keep their own Krylov
+ * scalars; a converged column stops updating).
+ *   links_f64   packed HISQ_FP64 links (always required: the true residual
+ *               b - A x is formed in FP64 with them).
+ *   links_inner packed links of precision `inner` for the iterations, or NULL
+ *               when inner == HISQ_FP64.  With inner = HISQ_FP32 or FP16N the
+ *               iteration vectors are FP32 and the solver is reliable-update
+ *               mixed-precision CG: x is accumulated in FP64, all inner
+ *               products and norms are FP64, and r is replaced by the FP64
+ *               b - A x whenever the iterated residual has fallen by 10x.
+ *   b, x        packed HISQ_FP64 fields of nrhs columns on the even sites;
+ *               x holds the initial guess on entry and the solution on exit.
+ *   tol         stop when ||b - A x|| <= tol ||b|| (FP64 true residual).
+ *   ws          workspace of hisq_cg_workspace_bytes(lat, inner, nrhs, 0).
+ *   info        host array [nrhs], filled on every return after argument checks.
+ * Returns HISQ_ERR_NOT_CONVERGED after max_iter iterations (x holds the last
+ * iterate), HISQ_ERR_BREAKDOWN on <p, A p> <= 0 or non-finite values.
+ * Synchronous: returns when done. */
+hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                    const void *links_inner, hisq_prec inner, int32_t nrhs, const void *b, void *x, double tol,
+                    int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, void *stream);
+
+/* Multi-shift CG (Sec. 3.2): solve (m^2 - D_eo D_oe + shifts[k]) x[k] = b for
+ * nshift (1..32) shifts at the cost of one operator application per iteration:
+ * the Krylov space of the smallest shift is built and the other shifts follow
+ * Jegerlehner's recurrences (zeta, alpha_k, beta_k in FP64); a shift is frozen
+ * once |zeta_k| ||r|| <= tol[k] ||b||.  Afterwards every shift whose FP64 true
+ * residual is above tol[k] is refined by (reliable-update) CG from x[k].
+ *   shifts, tol  host arrays [nshift]; m^2 + shifts[k] > 0.
+ *   x            host array of nshift distinct device pointers to packed
+ *                HISQ_FP64 fields (overwritten; the initial guess is zero).
+ *   ws           workspace of hisq_cg_workspace_bytes(lat, inner, 1, nshift).
+ *   info         host array [nshift]; iterations = shared Krylov iterations up
+ *                to the freeze + refinement iterations.
+ * Other arguments and statuses as for hisq_cg.  Synchronous. */
+hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                               const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                               const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                               size_t ws_bytes, hisq_solve_info *info, void *stream);
+
 /* Launch shape of hisq_dslash (and of the Dslash inside the solvers).
  *   variant   0: one thread per output site; 1: four lanes per site, one per
  *             direction, combined by wavefront shuffles.

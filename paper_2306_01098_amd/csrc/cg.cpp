@@ -1,0 +1,688 @@
+// Host drivers of the conjugate-gradient solvers (paper Sec. 3.2,
+// "Inverters"): plain and multi-right-hand-side CG, reliable-update
+// mixed-precision CG, and multi-shift CG with per-shift refinement, all for
+// the even-site operator M_e = m^2 - D_eo D_oe (+ shift).
+//
+// One CG iteration is four kernels on the device: D_oe p -> t;
+// q = (m^2 + sigma) p - D_eo t with Re<p, q>; x += alpha p, r -= alpha q with
+// <r, r> and the scalar update; p = r + beta p.  Chunks of iterations are
+// captured once into a HIP graph and replayed; kernels of converged
+// right-hand sides do nothing, and the host looks at the device state only
+// between chunks (to run a reliable update or to stop).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "api_util.hpp"
+#include "dslash.hpp"
+#include "solver.hpp"
+
+namespace hisq {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    int fs;  // sloppy field precision (FP64 or FP32)
+    int nblk_max;
+    size_t state, shifts, ms, flags, scal, partials, r, p, q, t, ps, ax, t64, total;
+};
+
+Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
+    Layout L;
+    L.fs = inner == HISQ_FP64 ? HISQ_FP64 : HISQ_FP32;
+    L.nblk_max = std::max(g.vh / 16 + 1, blas_blocks(g.vh));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.state = take(sizeof(CgScalars) * HISQ_MAX_RHS);
+    L.shifts = take(sizeof(ShiftScalars) * MAX_SHIFTS);
+    L.ms = take(sizeof(MsGlobal));
+    L.flags = take(64 * sizeof(unsigned));
+    L.scal = take(64 * sizeof(double));
+    L.partials = take(sizeof(double) * (size_t)std::max(nrhs, 1) * L.nblk_max);
+    const size_t fb = field_bytes(g, L.fs, 1);
+    L.r = take(fb * nrhs);
+    L.p = take(fb * nrhs);
+    L.q = take(fb * nrhs);
+    L.t = take(fb * nrhs);
+    L.ps = take(fb * std::max(nshift, 0));
+    const size_t f64 = field_bytes(g, HISQ_FP64, 1);
+    L.ax = take(f64);
+    L.t64 = take(f64);
+    L.total = off;
+    return L;
+}
+
+// flags[] slots
+enum { F_SKIP = 0, F_CNT_DOT = 8, F_CNT_XR = 9, F_CNT_RES = 10, F_CNT_NORM = 11 };
+// scal[] slots
+enum { S_TMP = 0 };
+
+struct Solver {
+    hisq_context *ctx = nullptr;
+    Geom g{};
+    hipStream_t st = nullptr;
+    double mass = 0.0;
+    const char *links64 = nullptr;
+    const char *links_in = nullptr;
+    int lp_in = HISQ_FP64;
+    Layout L{};
+    char *ws = nullptr;
+    DslashShape shape64{};
+    DslashShape shape_in{};
+    int chunk = 16;
+
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    unsigned *flags() const { return at<unsigned>(L.flags); }
+    double *scal() const { return at<double>(L.scal); }
+    double *partials() const { return at<double>(L.partials); }
+    size_t f64_col() const { return field_bytes(g, HISQ_FP64, 1); }
+    size_t fs_col() const { return field_bytes(g, L.fs, 1); }
+
+    hisq_status dev(hipError_t e, const char *where) const {
+        return e == hipSuccess ? HISQ_OK : device_fail(e, where);
+    }
+
+    // out = (m^2 + sigma) in - D_eo D_oe in, FP64, one column.
+    hisq_status apply_m64(double sigma, const void *in, void *out) {
+        DslashParams prm{};
+        prm.g = g;
+        prm.nrhs = 1;
+        prm.links = links64;
+        prm.out_parity = 1;
+        prm.in = in;
+        prm.out = at<void>(L.t64);
+        hipError_t e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_PLAIN, shape64, st);
+        if (e != hipSuccess)
+            return device_fail(e, "M_e (D_oe)");
+        prm.out_parity = 0;
+        prm.in = at<void>(L.t64);
+        prm.out = out;
+        prm.y = in;
+        prm.ad = -1.0;
+        prm.ay = mass * mass + sigma;
+        return dev(launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, shape64, st), "M_e (D_eo)");
+    }
+
+    hisq_status read_double(const double *d, double *h) {
+        hipError_t e = hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        return dev(e, "read scalar");
+    }
+
+    // ||v||^2 of an FP64 column.
+    hisq_status norm2(const void *v, double *out) {
+        hisq_status s = dev(launch_norm2(g.vh, v, partials(), flags() + F_CNT_NORM, scal() + S_TMP, st), "norm2");
+        return s == HISQ_OK ? read_double(scal() + S_TMP, out) : s;
+    }
+
+    // r_sloppy[col] = b - (M + sigma) x and its FP64 norm^2.
+    hisq_status true_residual(double sigma, const void *b, const void *x, void *r_sloppy, double *out2) {
+        hisq_status s = apply_m64(sigma, x, at<void>(L.ax));
+        if (s != HISQ_OK)
+            return s;
+        s = dev(launch_residual(g.vh, L.fs, b, at<void>(L.ax), r_sloppy, partials(), flags() + F_CNT_RES,
+                                scal() + S_TMP, st),
+                "residual");
+        return s == HISQ_OK ? read_double(scal() + S_TMP, out2) : s;
+    }
+
+    // The four kernels of one iteration for nrhs right-hand sides.
+    hipError_t iteration(const CgVecParams &vp, double sigma, int nrhs) {
+        DslashParams prm{};
+        prm.g = g;
+        prm.nrhs = nrhs;
+        prm.links = links_in;
+        prm.skip = reinterpret_cast<const int *>(flags() + F_SKIP);
+        prm.out_parity = 1;
+        prm.in = vp.p;
+        prm.out = at<void>(L.t);
+        hipError_t e = launch_dslash(prm, lp_in, L.fs, EPI_PLAIN, shape_in, st);
+        if (e != hipSuccess)
+            return e;
+        prm.out_parity = 0;
+        prm.in = at<void>(L.t);
+        prm.out = const_cast<void *>(vp.q);
+        prm.y = vp.p;
+        prm.ad = -1.0;
+        prm.ay = mass * mass + sigma;
+        prm.partials = partials();
+        prm.counter = flags() + F_CNT_DOT;
+        prm.dot_out = &vp.st[0].pq;
+        prm.dot_stride = sizeof(CgScalars) / sizeof(double);
+        e = launch_dslash(prm, lp_in, L.fs, EPI_AXPY_DOT, shape_in, st);
+        if (e != hipSuccess)
+            return e;
+        e = launch_cg_xr(vp, L.fs, st);
+        if (e != hipSuccess)
+            return e;
+        return launch_cg_p(vp, L.fs, 0, nrhs, st);
+    }
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// A private non-blocking stream ordered after the caller's stream (graphs
+// cannot be captured on the legacy default stream).
+struct StreamGuard {
+    hipStream_t caller = nullptr, own = nullptr;
+    hipEvent_t ev = nullptr;
+    hipError_t init(hipStream_t c) {
+        caller = c;
+        hipError_t e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventRecord(ev, caller);
+        if (e != hipSuccess)
+            return e;
+        return hipStreamWaitEvent(own, ev, 0);
+    }
+    ~StreamGuard() {
+        if (own) {
+            hipStreamSynchronize(own);
+            hipStreamDestroy(own);
+        }
+        if (ev)
+            hipEventDestroy(ev);
+    }
+};
+
+struct GraphChunk {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~GraphChunk() {
+        if (exec)
+            hipGraphExecDestroy(exec);
+        if (graph)
+            hipGraphDestroy(graph);
+    }
+};
+
+}  // namespace
+
+size_t cg_workspace_bytes(const Geom &g, int inner, int nrhs, int nshift) {
+    return make_layout(g, inner, nrhs, nshift).total;
+}
+
+// CG / reliable-update CG on (M_e + sigma) for nrhs columns of b, x (FP64
+// packed).  x holds the initial guess on entry.  info[nrhs] is filled.
+static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void *x, double tol, int max_iter,
+                          double delta, hisq_solve_info *info, const int *prior_iters) {
+    const double t0 = now_s();
+    const Geom &g = S.g;
+    const Layout &L = S.L;
+    hipStream_t st = S.st;
+    CgScalars *dst = S.at<CgScalars>(L.state);
+    std::vector<CgScalars> hs(nrhs);
+    std::vector<double> bnorm2(nrhs), rtrue2(nrhs);
+    std::vector<int> reliable(nrhs, 0);
+    hisq_status s = S.dev(launch_fill_u32(S.flags(), 64, 0u, st), "fill");
+    if (s != HISQ_OK)
+        return s;
+
+    const char *bb = static_cast<const char *>(b);
+    char *xb = static_cast<char *>(x);
+    char *rs = S.at<char>(L.r);
+    const size_t c64 = S.f64_col(), cs = S.fs_col();
+    bool breakdown = false;
+    for (int j = 0; j < nrhs; ++j) {
+        if ((s = S.norm2(bb + j * c64, &bnorm2[j])) != HISQ_OK)
+            return s;
+        if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &rtrue2[j])) != HISQ_OK)
+            return s;
+        CgScalars c{};
+        c.rho = rtrue2[j];
+        c.rmax2 = rtrue2[j];
+        c.target2 = tol * tol * bnorm2[j];
+        c.delta2 = delta * delta;
+        c.max_iter = max_iter;
+        c.iters = 0;
+        const bool bad = !std::isfinite(bnorm2[j]) || !std::isfinite(rtrue2[j]);
+        if (bad) {
+            c.flag = FLAG_BREAKDOWN;
+            breakdown = true;
+        } else if (rtrue2[j] <= c.target2) {
+            c.flag = FLAG_DONE;
+        } else {
+            c.flag = FLAG_RUN;
+            c.active = 1;
+        }
+        hs[j] = c;
+    }
+    // p = r
+    if ((s = S.dev(launch_copy(g.vh, nrhs, L.fs, L.fs, rs, S.at<void>(L.p), st), "copy")) != HISQ_OK)
+        return s;
+    auto push_state = [&]() -> hisq_status {
+        int any = 0;
+        for (int j = 0; j < nrhs; ++j)
+            any |= hs[j].active;
+        unsigned skip = any ? 0u : 1u;
+        hipError_t e = hipMemcpyAsync(dst, hs.data(), sizeof(CgScalars) * nrhs, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.flags() + F_SKIP, &skip, sizeof(unsigned), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        return S.dev(e, "push state");
+    };
+    if ((s = push_state()) != HISQ_OK)
+        return s;
+
+    CgVecParams vp{};
+    vp.vh = g.vh;
+    vp.nrhs = nrhs;
+    vp.x = x;
+    vp.r = rs;
+    vp.p = S.at<void>(L.p);
+    vp.q = S.at<void>(L.q);
+    vp.st = dst;
+    vp.partials = S.partials();
+    vp.counter = S.flags() + F_CNT_XR;
+    vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+    vp.nshift = 0;
+
+    // capture one chunk of iterations
+    GraphChunk gc;
+    bool use_graph = false;
+    {
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < S.chunk && le == hipSuccess; ++k)
+                le = S.iteration(vp, sigma, nrhs);
+            e = hipStreamEndCapture(st, &gc.graph);
+            if (le == hipSuccess && e == hipSuccess)
+                e = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
+            use_graph = le == hipSuccess && e == hipSuccess;
+        }
+        (void)hipGetLastError();
+    }
+
+    const int max_chunks = max_iter + 64;
+    for (int chunk = 0; chunk < max_chunks; ++chunk) {
+        bool any = false;
+        for (int j = 0; j < nrhs; ++j)
+            any |= hs[j].active != 0;
+        if (!any)
+            break;
+        hipError_t e = hipSuccess;
+        if (use_graph) {
+            e = hipGraphLaunch(gc.exec, st);
+        } else {
+            for (int k = 0; k < S.chunk && e == hipSuccess; ++k)
+                e = S.iteration(vp, sigma, nrhs);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hs.data(), dst, sizeof(CgScalars) * nrhs, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "cg chunk");
+        std::vector<int> restart;
+        for (int j = 0; j < nrhs; ++j) {
+            CgScalars &c = hs[j];
+            if (c.active || c.flag == FLAG_DONE)
+                continue;
+            if (c.flag == FLAG_CONV || c.flag == FLAG_RELIABLE) {
+                if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &rtrue2[j])) != HISQ_OK)
+                    return s;
+                if (!std::isfinite(rtrue2[j])) {
+                    c.flag = FLAG_BREAKDOWN;
+                    breakdown = true;
+                } else if (rtrue2[j] <= c.target2) {
+                    c.flag = FLAG_DONE;
+                } else if (c.iters >= c.max_iter) {
+                    c.flag = FLAG_MAXIT;
+                } else {
+                    // residual replacement: r = b - A x (already in r), then
+                    // beta = <r,r>_true / rho and p = r + beta p
+                    reliable[j] += 1;
+                    c.beta = rtrue2[j] / c.rho;
+                    c.rho = rtrue2[j];
+                    c.rmax2 = rtrue2[j];
+                    c.flag = FLAG_RUN;
+                    c.active = 1;
+                    restart.push_back(j);
+                }
+            } else if (c.flag == FLAG_BREAKDOWN) {
+                breakdown = true;
+            }
+        }
+        if (!restart.empty()) {
+            // only the restarted columns are active while their p is updated
+            std::vector<CgScalars> tmp = hs;
+            for (int j = 0; j < nrhs; ++j)
+                tmp[j].active = 0;
+            for (int j : restart)
+                tmp[j].active = 1;
+            std::swap(tmp, hs);
+            if ((s = push_state()) != HISQ_OK)
+                return s;
+            for (int j : restart)
+                if ((s = S.dev(launch_cg_p(vp, L.fs, j, 1, st), "p update")) != HISQ_OK)
+                    return s;
+            std::swap(tmp, hs);
+        }
+        if ((s = push_state()) != HISQ_OK)
+            return s;
+    }
+    // final report
+    hisq_status result = HISQ_OK;
+    for (int j = 0; j < nrhs; ++j) {
+        CgScalars &c = hs[j];
+        if (c.flag != FLAG_DONE) {
+            double r2 = 0.0;
+            if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &r2)) != HISQ_OK)
+                return s;
+            rtrue2[j] = r2;
+            if (std::isfinite(r2) && r2 <= c.target2 && c.flag != FLAG_BREAKDOWN)
+                c.flag = FLAG_DONE;
+        }
+        if (info) {
+            info[j].iterations = c.iters + (prior_iters ? prior_iters[j] : 0);
+            info[j].reliable_updates = reliable[j];
+            info[j].true_residual = bnorm2[j] > 0 ? std::sqrt(rtrue2[j] / bnorm2[j]) : std::sqrt(rtrue2[j]);
+            info[j].seconds = now_s() - t0;
+        }
+        if (c.flag == FLAG_BREAKDOWN)
+            result = HISQ_ERR_BREAKDOWN;
+        else if (c.flag != FLAG_DONE && result == HISQ_OK)
+            result = HISQ_ERR_NOT_CONVERGED;
+    }
+    if (breakdown)
+        result = HISQ_ERR_BREAKDOWN;
+    if (result == HISQ_ERR_NOT_CONVERGED)
+        fail(result, "true residual above tolerance after %d iterations", max_iter);
+    if (result == HISQ_ERR_BREAKDOWN)
+        fail(result, "CG breakdown: <p, A p> not positive or non-finite values");
+    return result;
+}
+
+// Multi-shift CG (Sec. 3.2: one Krylov space built on the smallest shift,
+// the other shifts advanced by Jegerlehner's zeta recurrences in FP64), then
+// per-shift refinement by (reliable-update) CG from x_k where the FP64 true
+// residual is still above tol_k.
+static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, const void *b, void *const *x,
+                                  const double *tol, int max_iter, double delta, hisq_solve_info *info) {
+    const double t0 = now_s();
+    const Geom &g = S.g;
+    const Layout &L = S.L;
+    hipStream_t st = S.st;
+    hisq_status s;
+    int base = 0;
+    for (int k = 1; k < nshift; ++k)
+        if (shifts[k] < shifts[base])
+            base = k;
+    std::vector<int> others;
+    for (int k = 0; k < nshift; ++k)
+        if (k != base)
+            others.push_back(k);
+    const int no = (int)others.size();
+
+    if ((s = S.dev(launch_fill_u32(S.flags(), 64, 0u, st), "fill")) != HISQ_OK)
+        return s;
+    double bnorm2 = 0.0;
+    if ((s = S.norm2(b, &bnorm2)) != HISQ_OK)
+        return s;
+    const size_t c64 = S.f64_col();
+    for (int k = 0; k < nshift; ++k)
+        if ((s = S.dev(launch_fill_u32(static_cast<unsigned *>(x[k]), c64 / 4, 0u, st), "zero x")) != HISQ_OK)
+            return s;
+    std::vector<int> krylov_iters(nshift, 0);
+    if (!std::isfinite(bnorm2)) {
+        for (int k = 0; k < nshift; ++k)
+            if (info) info[k] = hisq_solve_info{0, 0, NAN, now_s() - t0};
+        return fail(HISQ_ERR_BREAKDOWN, "non-finite source");
+    }
+    if (bnorm2 > 0.0) {
+        void *rs = S.at<void>(L.r);
+        if ((s = S.dev(launch_copy(g.vh, 1, HISQ_FP64, L.fs, b, rs, st), "copy")) != HISQ_OK)
+            return s;
+        if ((s = S.dev(launch_copy(g.vh, 1, L.fs, L.fs, rs, S.at<void>(L.p), st), "copy")) != HISQ_OK)
+            return s;
+        for (int j = 0; j < no; ++j)
+            if ((s = S.dev(launch_copy(g.vh, 1, L.fs, L.fs, rs, S.at<char>(L.ps) + j * S.fs_col(), st), "copy")) !=
+                HISQ_OK)
+                return s;
+        CgScalars c{};
+        c.rho = bnorm2;
+        c.rmax2 = bnorm2;
+        c.target2 = tol[base] * tol[base] * bnorm2;
+        c.delta2 = 0.0;
+        c.max_iter = max_iter;
+        c.active = 1;
+        c.flag = FLAG_RUN;
+        std::vector<ShiftScalars> sh(std::max(no, 1));
+        for (int j = 0; j < no; ++j) {
+            ShiftScalars z{};
+            z.s = shifts[others[j]] - shifts[base];
+            z.zeta = z.zeta_old = z.zeta_new = 1.0;
+            z.target2 = tol[others[j]] * tol[others[j]] * bnorm2;
+            z.active = 1;
+            sh[j] = z;
+        }
+        MsGlobal ms{1.0, 0.0, no, 0};
+        CgScalars *dst = S.at<CgScalars>(L.state);
+        ShiftScalars *dsh = S.at<ShiftScalars>(L.shifts);
+        MsGlobal *dms = S.at<MsGlobal>(L.ms);
+        hipError_t e = hipMemcpyAsync(dst, &c, sizeof c, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && no > 0)
+            e = hipMemcpyAsync(dsh, sh.data(), sizeof(ShiftScalars) * no, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dms, &ms, sizeof ms, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "multishift setup");
+
+        CgVecParams vp{};
+        vp.vh = g.vh;
+        vp.nrhs = 1;
+        vp.x = x[base];
+        vp.r = rs;
+        vp.p = S.at<void>(L.p);
+        vp.q = S.at<void>(L.q);
+        vp.st = dst;
+        vp.partials = S.partials();
+        vp.counter = S.flags() + F_CNT_XR;
+        vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+        vp.nshift = no;
+        vp.sh = dsh;
+        vp.ms = dms;
+        for (int j = 0; j < no; ++j)
+            vp.xs[j] = x[others[j]];
+        vp.ps = S.at<void>(L.ps);
+
+        GraphChunk gc;
+        bool use_graph = false;
+        {
+            hipError_t ce = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (ce == hipSuccess) {
+                hipError_t le = hipSuccess;
+                for (int k = 0; k < S.chunk && le == hipSuccess; ++k)
+                    le = S.iteration(vp, shifts[base], 1);
+                ce = hipStreamEndCapture(st, &gc.graph);
+                if (le == hipSuccess && ce == hipSuccess)
+                    ce = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
+                use_graph = le == hipSuccess && ce == hipSuccess;
+            }
+            (void)hipGetLastError();
+        }
+        for (int chunk = 0; chunk < max_iter + 64 && c.active; ++chunk) {
+            e = use_graph ? hipGraphLaunch(gc.exec, st) : hipSuccess;
+            for (int k = 0; !use_graph && k < S.chunk && e == hipSuccess; ++k)
+                e = S.iteration(vp, shifts[base], 1);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&c, dst, sizeof c, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(st);
+            if (e != hipSuccess)
+                return device_fail(e, "multishift chunk");
+        }
+        if (no > 0) {
+            e = hipMemcpyAsync(sh.data(), dsh, sizeof(ShiftScalars) * no, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(st);
+            if (e != hipSuccess)
+                return device_fail(e, "multishift state");
+        }
+        krylov_iters[base] = c.iters;
+        for (int j = 0; j < no; ++j)
+            krylov_iters[others[j]] = sh[j].iters;
+        if (c.flag == FLAG_BREAKDOWN)
+            return fail(HISQ_ERR_BREAKDOWN, "multi-shift CG breakdown");
+    }
+    // refinement: each shift to its own FP64 true residual
+    hisq_status result = HISQ_OK;
+    for (int k = 0; k < nshift; ++k) {
+        hisq_solve_info one{};
+        const int left = std::max(1, max_iter - krylov_iters[k]);
+        hisq_status rs = run_cg(S, shifts[k], 1, b, x[k], tol[k], left, delta, &one, &krylov_iters[k]);
+        if (rs == HISQ_ERR_DEVICE || rs == HISQ_ERR_INVALID_ARG)
+            return rs;
+        if (rs == HISQ_ERR_BREAKDOWN)
+            result = rs;
+        else if (rs == HISQ_ERR_NOT_CONVERGED && result == HISQ_OK)
+            result = rs;
+        if (info) {
+            info[k] = one;
+            info[k].seconds = now_s() - t0;
+        }
+    }
+    if (result != HISQ_OK)
+        fail(result, result == HISQ_ERR_BREAKDOWN ? "multi-shift refinement breakdown"
+                                                  : "a shift did not reach its tolerance");
+    return result;
+}
+
+hisq_status setup_solver(Solver &S, hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                         const void *links_inner, hisq_prec inner, int nrhs, int nshift, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+    S.ctx = ctx;
+    S.g = make_geom(*lat);
+    S.st = st;
+    S.mass = mass;
+    S.links64 = static_cast<const char *>(links_f64);
+    S.lp_in = inner;
+    S.links_in = inner == HISQ_FP64 ? S.links64 : static_cast<const char *>(links_inner);
+    S.L = make_layout(S.g, inner, nrhs, nshift);
+    if (ws_bytes < S.L.total)
+        return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, S.L.total);
+    S.ws = static_cast<char *>(ws);
+    S.shape64 = pick_shape(ctx, S.g, HISQ_FP64, HISQ_FP64, 1);
+    S.shape_in = pick_shape(ctx, S.g, S.lp_in, S.L.fs, nrhs);
+    // chunk length: ~1 ms of iterations, 8 .. 64
+    const double bytes_per_iter = 2.0 * (double)S.g.vh * 16 * 18 * (inner == HISQ_FP64 ? 8 : inner == HISQ_FP32 ? 4 : 2);
+    const double est_us = bytes_per_iter / 5.0e6 + 12.0;
+    S.chunk = std::max(8, std::min(64, (int)(1000.0 / est_us)));
+    return HISQ_OK;
+}
+
+hisq_status check_solver_args(const hisq_lattice *lat, double mass, const void *links_f64, const void *links_inner,
+                              hisq_prec inner, const void *ws) {
+    hisq_status s = check_lattice(lat);
+    if (s == HISQ_OK) s = check_prec(inner);
+    if (s == HISQ_OK) s = check_ptr(links_f64, "links_f64");
+    if (s == HISQ_OK && inner != HISQ_FP64) s = check_ptr(links_inner, "links_inner");
+    if (s == HISQ_OK) s = check_ptr(ws, "ws");
+    if (s == HISQ_OK && (!std::isfinite(mass) || mass * mass <= 0.0))
+        s = fail(HISQ_ERR_INVALID_ARG, "mass^2 must be positive and finite (mass = %g)", mass);
+    return s;
+}
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" {
+
+size_t hisq_cg_workspace_bytes(const hisq_lattice *lat, hisq_prec inner, int32_t nrhs, int32_t nshift) {
+    if (check_lattice(lat) != HISQ_OK || check_prec(inner) != HISQ_OK)
+        return 0;
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS || nshift < 0 || nshift > MAX_SHIFTS)
+        return 0;
+    return cg_workspace_bytes(make_geom(*lat), inner, nrhs, nshift);
+}
+
+hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                    const void *links_inner, hisq_prec inner, int32_t nrhs, const void *b, void *x, double tol,
+                    int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, void *stream) {
+    hisq_status s = check_solver_args(lat, mass, links_f64, links_inner, inner, ws);
+    if (s == HISQ_OK) s = check_nrhs(nrhs);
+    if (s == HISQ_OK) s = check_ptr(b, "b");
+    if (s == HISQ_OK) s = check_ptr(x, "x");
+    if (s == HISQ_OK && !(tol > 0.0 && tol < 1.0))
+        s = fail(HISQ_ERR_INVALID_ARG, "tol = %g must be in (0, 1)", tol);
+    if (s == HISQ_OK && max_iter < 1)
+        s = fail(HISQ_ERR_INVALID_ARG, "max_iter = %d must be >= 1", max_iter);
+    if (s == HISQ_OK && b == x)
+        s = fail(HISQ_ERR_INVALID_ARG, "b and x must not alias");
+    if (s == HISQ_OK) s = set_device(ctx);
+    if (s != HISQ_OK)
+        return s;
+    StreamGuard sg;
+    hipError_t e = sg.init(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return device_fail(e, "stream setup");
+    Solver S;
+    if ((s = setup_solver(S, ctx, lat, mass, links_f64, links_inner, inner, nrhs, 0, ws, ws_bytes, sg.own)) !=
+        HISQ_OK)
+        return s;
+    // reliable updates whenever the iterated residual fell by 10x (reduced
+    // precision); FP64 CG checks the true residual at convergence only
+    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    return run_cg(S, 0.0, nrhs, b, x, tol, max_iter, delta, info, nullptr);
+}
+
+hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                               const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                               const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                               size_t ws_bytes, hisq_solve_info *info, void *stream) {
+    hisq_status s = check_solver_args(lat, mass, links_f64, links_inner, inner, ws);
+    if (s == HISQ_OK && (nshift < 1 || nshift > MAX_SHIFTS))
+        s = fail(HISQ_ERR_INVALID_ARG, "nshift = %d outside [1, %d]", nshift, MAX_SHIFTS);
+    if (s == HISQ_OK) s = check_ptr(shifts, "shifts");
+    if (s == HISQ_OK) s = check_ptr(tol, "tol");
+    if (s == HISQ_OK) s = check_ptr(b, "b");
+    if (s == HISQ_OK) s = check_ptr(x, "x");
+    if (s == HISQ_OK && max_iter < 1)
+        s = fail(HISQ_ERR_INVALID_ARG, "max_iter = %d must be >= 1", max_iter);
+    for (int k = 0; s == HISQ_OK && k < nshift; ++k) {
+        if (!std::isfinite(shifts[k]) || mass * mass + shifts[k] <= 0.0)
+            s = fail(HISQ_ERR_INVALID_ARG, "m^2 + shift[%d] = %g must be positive", k, mass * mass + shifts[k]);
+        else if (!(tol[k] > 0.0 && tol[k] < 1.0))
+            s = fail(HISQ_ERR_INVALID_ARG, "tol[%d] = %g must be in (0, 1)", k, tol[k]);
+        else if (!x[k] || x[k] == b)
+            s = fail(HISQ_ERR_INVALID_ARG, "x[%d] is NULL or aliases b", k);
+        for (int j = 0; s == HISQ_OK && j < k; ++j)
+            if (x[j] == x[k])
+                s = fail(HISQ_ERR_INVALID_ARG, "x[%d] and x[%d] alias", j, k);
+    }
+    if (s == HISQ_OK) s = set_device(ctx);
+    if (s != HISQ_OK)
+        return s;
+    StreamGuard sg;
+    hipError_t e = sg.init(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return device_fail(e, "stream setup");
+    Solver S;
+    if ((s = setup_solver(S, ctx, lat, mass, links_f64, links_inner, inner, 1, nshift, ws, ws_bytes, sg.own)) !=
+        HISQ_OK)
+        return s;
+    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    return run_multishift(S, nshift, shifts, b, x, tol, max_iter, delta, info);
+}
+
+}  // extern "C"

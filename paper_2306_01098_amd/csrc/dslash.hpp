@@ -18,7 +18,10 @@
 namespace hisq {
 
 enum { VAR_SITE = 0, VAR_DIR = 1 };
-enum { EPI_PLAIN = 0, EPI_AXPY = 1 };
+// EPI_PLAIN: out = D in.  EPI_AXPY: out = ad * D in + ay * y.
+// EPI_AXPY_DOT: as EPI_AXPY, and dot_out[r] = Re <y_r, out_r> (FP64 sums,
+// deterministic: block partials summed in block order by the last block).
+enum { EPI_PLAIN = 0, EPI_AXPY = 1, EPI_AXPY_DOT = 2 };
 
 struct DslashParams {
     Geom g;
@@ -28,8 +31,13 @@ struct DslashParams {
     const char *links;
     const void *in;
     void *out;
-    const void *y;  // EPI_AXPY: out = ad * D in + ay * y (y on the output parity)
+    const void *y;  // EPI_AXPY*: out = ad * D in + ay * y (y on the output parity)
     double ad, ay;
+    const int *skip;     // optional: if *skip != 0 the whole launch does nothing
+    double *partials;    // EPI_AXPY_DOT: [nrhs][gridDim.x] block partials
+    unsigned *counter;   // EPI_AXPY_DOT: zero before the first launch; reset by the last block
+    double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride]
+    int dot_stride;
 };
 
 // Coordinates of half-lattice site i of parity p.
@@ -159,10 +167,12 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         dslash_direction<LP, FP, NIN, A>(g, p, links, in, i, s, mu, r0, nr, acc);
 }
 
-// out = ad * acc + ay * y  (EPI_AXPY) for right-hand side r at site i.
+// out = ad * acc + ay * y  (EPI_AXPY*) for right-hand side r at site i;
+// returns Re <y, out> in FP64 (products of the stored-precision values).
 template <int FP, int EPI, typename A>
-__device__ __forceinline__ void epilogue(const DslashParams &prm, int r, int i, cplx<A> (&v)[3]) {
-    if (EPI == EPI_AXPY) {
+__device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i, cplx<A> (&v)[3]) {
+    double dot = 0.0;
+    if (EPI != EPI_PLAIN) {
         cplx<A> yv[3];
         FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r, i, yv);
         const A ad = (A)prm.ad, ay = (A)prm.ay;
@@ -170,40 +180,81 @@ __device__ __forceinline__ void epilogue(const DslashParams &prm, int r, int i, 
         for (int a = 0; a < 3; ++a) {
             v[a].re = fma(ad, v[a].re, ay * yv[a].re);
             v[a].im = fma(ad, v[a].im, ay * yv[a].im);
+            if (EPI == EPI_AXPY_DOT) {
+                dot = fma((double)yv[a].re, (double)v[a].re, dot);
+                dot = fma((double)yv[a].im, (double)v[a].im, dot);
+            }
         }
     }
+    return dot;
+}
+
+// Block partials of the NIN dot products, and the last block's totals.
+template <int NIN>
+__device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, double (&dot)[NIN], int r0, int nr) {
+    __shared__ double lds[4 * NIN];
+    __shared__ int last_flag;
+    block_sum<NIN>(dot, lds);
+    const int nblk = gridDim.x;
+    const int blk = blockIdx.y * nblk + blockIdx.x;
+    if (threadIdx.x == 0)
+        for (int r = 0; r < nr; ++r)
+            prm.partials[(size_t)(r0 + r) * nblk + blockIdx.x] = dot[r];
+    const bool last = publish_and_check_last(nullptr, 0, nullptr, 0, blk, nblk, prm.counter,
+                                             gridDim.x * gridDim.y, &last_flag);
+    if (last)
+        sum_partials_block(prm.partials, prm.nrhs, nblk, prm.dot_out, prm.dot_stride > 0 ? prm.dot_stride : 1);
 }
 
 template <int LP, int FP, int NIN, int EPI>
 __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm) {
     using A = typename Prec<LP>::acc;
+    if (prm.skip && *prm.skip)
+        return;
     const int i = logical_block(prm.xcd_remap) * blockDim.x + threadIdx.x;
-    if (i >= prm.g.vh)
+    const bool valid = i < prm.g.vh;
+    if (EPI != EPI_AXPY_DOT && !valid)
         return;
     const int r0 = blockIdx.y * NIN;
     const int nr = min(NIN, prm.nrhs - r0);
-    cplx<A> acc[NIN][3];
-    dslash_site<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
+    double dot[NIN];
 #pragma unroll
-    for (int r = 0; r < NIN; ++r) {
-        if (r < nr) {
-            epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
-            FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
+    for (int r = 0; r < NIN; ++r)
+        dot[r] = 0.0;
+    if (valid) {
+        cplx<A> acc[NIN][3];
+        dslash_site<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
+#pragma unroll
+        for (int r = 0; r < NIN; ++r) {
+            if (r < nr) {
+                dot[r] = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+                FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
+            }
         }
     }
+    if (EPI == EPI_AXPY_DOT)
+        dslash_dot_reduce<NIN>(prm, dot, r0, nr);
 }
 
 template <int LP, int FP, int NIN, int EPI>
 __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm) {
     using A = typename Prec<LP>::acc;
+    if (prm.skip && *prm.skip)
+        return;
     const int mu = threadIdx.x & 3;
     const int i = logical_block(prm.xcd_remap) * (blockDim.x >> 2) + (threadIdx.x >> 2);
     // a site's four lanes are in one wavefront and share validity, so whole
-    // quads leave together and the shuffles below see only active partners
-    if (i >= prm.g.vh)
+    // quads drop out together and the shuffles below see only valid partners
+    const bool valid = i < prm.g.vh;
+    if (EPI != EPI_AXPY_DOT && !valid)
         return;
     const int r0 = blockIdx.y * NIN;
     const int nr = min(NIN, prm.nrhs - r0);
+    double dot[NIN];
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+        dot[r] = 0.0;
+    if (valid) {
     const Site s = site_coords(prm.g, prm.out_parity, i);
     cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
@@ -221,7 +272,8 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
 #pragma unroll
     for (int r = 0; r < NIN; ++r) {
         if (r < nr) {
-            epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            const double d = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            dot[r] = mu == 0 ? d : 0.0;  // one lane of the quad counts the site
             if constexpr (FP == HISQ_FP16N) {
                 if (mu == 0)  // one 16-byte record holds the whole site
                     FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
@@ -234,6 +286,9 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
             }
         }
     }
+    }
+    if (EPI == EPI_AXPY_DOT)
+        dslash_dot_reduce<NIN>(prm, dot, r0, nr);
 }
 
 }  // namespace hisq

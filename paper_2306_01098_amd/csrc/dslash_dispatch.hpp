@@ -35,8 +35,12 @@ hipError_t dslash_by_nin(const DslashParams &prm, DslashShape s, hipStream_t st)
 
 template <int LP, int FP>
 hipError_t dslash_launch_pair(const DslashParams &prm, int epi, DslashShape s, hipStream_t st) {
-    return epi == EPI_AXPY ? dslash_by_nin<LP, FP, EPI_AXPY>(prm, s, st)
-                           : dslash_by_nin<LP, FP, EPI_PLAIN>(prm, s, st);
+    switch (epi) {
+    case EPI_PLAIN: return dslash_by_nin<LP, FP, EPI_PLAIN>(prm, s, st);
+    case EPI_AXPY: return dslash_by_nin<LP, FP, EPI_AXPY>(prm, s, st);
+    case EPI_AXPY_DOT: return dslash_by_nin<LP, FP, EPI_AXPY_DOT>(prm, s, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace hisq

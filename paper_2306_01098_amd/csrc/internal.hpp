@@ -30,3 +30,17 @@ hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, Dslas
 bool dslash_shape_supported(DslashShape s);
 
 }  // namespace hisq
+
+namespace hisq {
+
+struct CgVecParams;
+int blas_blocks(int vh);
+hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st);
+hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st);
+hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
+                           unsigned *counter, double *out2, hipStream_t st);
+hipError_t launch_norm2(int vh, const void *v, double *partials, unsigned *counter, double *out2, hipStream_t st);
+hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst, hipStream_t st);
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t st);
+
+}  // namespace hisq

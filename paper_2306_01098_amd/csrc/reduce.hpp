@@ -42,6 +42,7 @@ __device__ __forceinline__ bool publish_and_check_last(const double *vals, int n
                                                        int slot0, int blk, int nblk,
                                                        unsigned *counter, unsigned nblocks_total,
                                                        int *lds_flag) {
+    __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 0; k < nv; ++k)
             partials[(size_t)(slot0 + k) * nblk + blk] = vals[k];
@@ -59,16 +60,21 @@ __device__ __forceinline__ bool publish_and_check_last(const double *vals, int n
     return last;
 }
 
-// In the last block: tot[s] = sum_b partials[s * nblk + b] for s < nslots, in
-// block order (deterministic), computed by one thread per slot.
-__device__ __forceinline__ void sum_partials(const double *partials, int nslots, int nblk,
-                                             double *tot) {
-    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-        double acc = 0.0;
+// In the last block (all threads): tot[s] = sum_b partials[s * nblk + b] for
+// s < nslots.  Thread t sums the partials t, t + blockDim, ... in order, then
+// the block sums the threads in a fixed tree: the result is deterministic.
+__device__ __forceinline__ void sum_partials_block(const double *partials, int nslots, int nblk,
+                                                   double *tot, int stride = 1) {
+    __shared__ double lds[4];
+    for (int s = 0; s < nslots; ++s) {
+        double v[1] = {0.0};
         const double *p = partials + (size_t)s * nblk;
-        for (int b = 0; b < nblk; ++b)
-            acc += __builtin_nontemporal_load(p + b);
-        tot[s] = acc;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+            v[0] += __builtin_nontemporal_load(p + b);
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0)
+            tot[(size_t)s * stride] = v[0];
+        __syncthreads();
     }
 }
 

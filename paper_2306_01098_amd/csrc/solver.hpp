@@ -1,0 +1,80 @@
+// Device-resident solver state and the vector kernels of the CG family.
+//
+// All scalars of the Krylov recurrences (rho, <p,Ap>, alpha, beta, the
+// multi-shift zeta's) live in device memory in FP64 and are updated by the
+// last block of the kernel that reduces them, so an iteration needs no host
+// round trip; the host reads the state only once per chunk of iterations.
+#pragma once
+
+#include "common.hpp"
+#include "access.hpp"
+
+namespace hisq {
+
+enum {
+    FLAG_RUN = 0,       // iterating
+    FLAG_CONV = 1,      // iterated residual met the target: check the true residual
+    FLAG_BREAKDOWN = 2, // <p, A p> not positive or not finite
+    FLAG_RELIABLE = 3,  // reliable update requested (residual fell by delta)
+    FLAG_MAXIT = 4,     // iteration limit reached
+    FLAG_DONE = 5       // true residual met the target
+};
+
+// Per right-hand side (or per shift for the multi-shift solver's base system).
+struct alignas(16) CgScalars {
+    double rho;      // <r, r> (iterated residual)
+    double pq;       // Re <p, A p>
+    double beta;     // for p = r + beta p
+    double rmax2;    // max <r, r> since the last reliable update
+    double target2;  // (tol ||b||)^2
+    double delta2;   // reliable-update threshold delta^2 (0: only at convergence)
+    double rho_new;  // <r, r> after the last update (kept when a flag is raised)
+    double spare;
+    int active;      // 1 while the recurrence runs
+    int flag;        // FLAG_*
+    int iters;       // iterations performed
+    int max_iter;
+};
+
+// Per shift k of the multi-shift solver (Jegerlehner's recurrences, FP64).
+struct alignas(16) ShiftScalars {
+    double s;         // sigma_k - sigma_0
+    double zeta, zeta_old, zeta_new;
+    double alpha, beta;
+    double target2;   // (tol_k ||b||)^2
+    double spare;
+    int active;
+    int flag;
+    int iters;
+    int pad;
+};
+
+struct MsGlobal {
+    double alpha_old, beta_old;
+    int nshift;
+    int pad;
+};
+
+constexpr int MAX_SHIFTS = 32;
+
+// Kernel arguments of the CG vector updates.
+struct CgVecParams {
+    int vh;
+    int nrhs;
+    void *x;            // FP64 solution [nrhs]
+    void *r;            // sloppy residual [nrhs]
+    void *p;            // sloppy direction [nrhs]
+    const void *q;      // sloppy A p [nrhs]
+    CgScalars *st;      // [nrhs]
+    double *partials;   // [nrhs][gridDim.x]
+    unsigned *counter;
+    int *skip;          // 1 when no right-hand side is active
+    // multi-shift (nshift > 0): per-shift solutions and directions
+    int nshift;
+    ShiftScalars *sh;
+    MsGlobal *ms;
+    void *xs[MAX_SHIFTS];  // FP64 x_k
+    void *ps;              // sloppy p_k, [nshift] fields
+};
+
+}  // namespace hisq

@@ -9,16 +9,25 @@
 
 namespace hisq {
 
+// Built-in shapes (measured on MI355X at 32^3x8 and 48^3x12): one thread per
+// site for a single right-hand side; for several, four lanes per site with
+// eight right-hand sides per thread.
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     (void)g;
     (void)fp;
     DslashShape s;
+    s.xcd_remap = 1;
+    if (nrhs == 1) {
+        s.variant = VAR_SITE;
+        s.nin = 1;
+        s.block = 128;
+        return s;
+    }
     s.variant = VAR_DIR;
     s.block = 256;
-    s.xcd_remap = 1;
-    s.nin = nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
-    if (lp == HISQ_FP64 && s.nin > 2)
-        s.nin = 2;
+    s.nin = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : 2;
+    if (lp == HISQ_FP64 && s.nin > 4)
+        s.nin = 4;
     return s;
 }
 

@@ -74,6 +74,14 @@ _SIGS = {
                                              ctypes.POINTER(hisq_dslash_shape)]),
     "hisq_set_dslash_shape": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32,
                                              ctypes.POINTER(hisq_dslash_shape)]),
+    "hisq_cg_workspace_bytes": (ctypes.c_size_t, [_LAT, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    "hisq_cg": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32, _vp, _vp,
+                               ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_size_t,
+                               ctypes.POINTER(hisq_solve_info), _vp]),
+    "hisq_multishift_cg": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), _vp, ctypes.POINTER(_vp),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_size_t,
+                                          ctypes.POINTER(hisq_solve_info), _vp]),
 }
 
 
@@ -261,6 +269,52 @@ def hisq_set_dslash_shape(lat, prec, nrhs: int, shape, ctx):
     sh = hisq_dslash_shape(*[int(v) for v in shape])
     _check(load().hisq_set_dslash_shape(_ctx(ctx), ctypes.byref(lat), _prec(prec), int(nrhs),
                                         ctypes.byref(sh)), "hisq_set_dslash_shape")
+
+
+def hisq_cg_workspace_bytes(lat, inner, nrhs: int = 1, nshift: int = 0) -> int:
+    return int(load().hisq_cg_workspace_bytes(ctypes.byref(lat), _prec(inner), int(nrhs), int(nshift)))
+
+
+def empty_workspace(nbytes: int) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def hisq_cg(lat, mass: float, links_f64, links_inner, inner, nrhs: int, b, x, tol: float, max_iter: int,
+            ws, ctx=None, stream=None, check: bool = True):
+    """Returns (status, [info dict per right-hand side]); raises on errors other
+    than NOT_CONVERGED / BREAKDOWN unless check is False."""
+    info = (hisq_solve_info * int(nrhs))()
+    fb = hisq_field_bytes(lat, "fp64", nrhs)
+    st = load().hisq_cg(_ctx(ctx), ctypes.byref(lat), float(mass),
+                        _ptr(links_f64, "links_f64", hisq_links_bytes(lat, "fp64")),
+                        None if links_inner is None else _ptr(links_inner, "links_inner",
+                                                              hisq_links_bytes(lat, inner)),
+                        _prec(inner), int(nrhs), _ptr(b, "b", fb), _ptr(x, "x", fb), float(tol),
+                        int(max_iter), _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), info, _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_cg")
+    return st, [info[k].as_dict() for k in range(int(nrhs))]
+
+
+def hisq_multishift_cg(lat, mass: float, links_f64, links_inner, inner, shifts, b, xs, tol, max_iter: int,
+                       ws, ctx=None, stream=None, check: bool = True):
+    """xs: list of packed FP64 fields, one per shift.  tol: scalar or per shift."""
+    n = len(shifts)
+    sh = (ctypes.c_double * n)(*[float(v) for v in shifts])
+    tols = [float(tol)] * n if not hasattr(tol, "__len__") else [float(v) for v in tol]
+    tl = (ctypes.c_double * n)(*tols)
+    fb = hisq_field_bytes(lat, "fp64", 1)
+    xp = (_vp * n)(*[_ptr(xk, f"x[{k}]", fb) for k, xk in enumerate(xs)])
+    info = (hisq_solve_info * n)()
+    st = load().hisq_multishift_cg(_ctx(ctx), ctypes.byref(lat), float(mass),
+                                   _ptr(links_f64, "links_f64", hisq_links_bytes(lat, "fp64")),
+                                   None if links_inner is None else _ptr(links_inner, "links_inner",
+                                                                         hisq_links_bytes(lat, inner)),
+                                   _prec(inner), n, sh, _ptr(b, "b", fb), xp, tl, int(max_iter),
+                                   _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), info, _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_multishift_cg")
+    return st, [info[k].as_dict() for k in range(n)]
 
 
 # ---------------------------------------------------------------------------

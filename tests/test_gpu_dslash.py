@@ -125,21 +125,26 @@ def test_dslash_reduced_precision(gpu_lib, fields, prec, tol, dims, t_bc):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16n"])
 @pytest.mark.parametrize("nrhs", [3, 16])
-def test_dslash_multi_rhs_columns(gpu_lib, fields, prec, nrhs):
-    """Each column of the batched Dslash equals the single-RHS Dslash."""
+@pytest.mark.parametrize("variant", [0, 1])
+def test_dslash_multi_rhs_columns(gpu_lib, fields, prec, nrhs, variant):
+    """Each column of the batched Dslash equals, bit for bit, the single-RHS
+    Dslash with the same thread mapping (same summation order)."""
     h = gpu_lib
     dims, t_bc = (8, 4, 6, 8), -1
     w = fields(dims, t_bc, nrhs)
     lat = h.lattice(dims, t_bc)
+    ctx = h.Context(0)
+    h.hisq_set_dslash_shape(lat, prec, nrhs, (variant, 8 if prec != "fp64" else 4, 256, 1), ctx)
+    h.hisq_set_dslash_shape(lat, prec, 1, (variant, 1, 256, 1), ctx)
     links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
     inp = h.pack_field_from_host(lat, prec, w["src_o"])
     out = h.empty_field(lat, prec, nrhs)
-    h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs)
+    h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs, ctx=ctx)
     got = h.unpack_field_to_host(lat, prec, out, nrhs)
     for r in range(nrhs):
         one_in = h.pack_field_from_host(lat, prec, w["src_o"][r])
         one_out = h.empty_field(lat, prec)
-        h.hisq_dslash(lat, prec, 0, links, one_in, one_out, 1)
+        h.hisq_dslash(lat, prec, 0, links, one_in, one_out, 1, ctx=ctx)
         one = h.unpack_field_to_host(lat, prec, one_out)[0]
         np.testing.assert_array_equal(got[r], one)
     if prec == "fp64":
