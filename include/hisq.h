@@ -186,6 +186,40 @@ hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, doubl
                                const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
                                size_t ws_bytes, hisq_solve_info *info, void *stream);
 
+/* One problem of a batched solve. */
+typedef struct {
+    hisq_lattice lat;
+    double mass;
+    const void *links_f64;   /* packed HISQ_FP64 links of this lattice */
+    const void *links_inner; /* packed links of the batch's inner precision (NULL for FP64) */
+    const void *b;           /* packed HISQ_FP64 field, even sites */
+    void *x;                 /* packed HISQ_FP64 field: initial guess in, solution out */
+    double tol;              /* ||b - M_e x|| <= tol ||b|| */
+} hisq_problem;
+
+/* Workspace bytes of hisq_cg_batch for these problems (0 on invalid input). */
+size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *problems, hisq_prec inner);
+
+/* Batched CG: nproblems (1..256) independent systems M_e x = b, each on its
+ * own lattice with its own mass, links and tolerance, solved together.  Every
+ * launch covers the sites of all problems through a block -> problem work
+ * list, so one iteration of all problems is four kernels; chunks of
+ * iterations are captured in a HIP graph and replayed; a problem whose
+ * iterated residual meets its target stops updating while the others go on.
+ * With inner = FP32/FP16N the iterations use that link precision with FP32
+ * vectors and FP64 reliable updates (batched over the problems that need
+ * one), as in hisq_cg.
+ *   problems    host array [nproblems]; the structs may be freed on return.
+ *   info        host array [nproblems] (seconds = wall time of the batch).
+ *   latency_s   host array [nproblems] or NULL: device-clock time from the
+ *               start of the batched iterations to the iteration at which the
+ *               problem's solution met its tolerance.
+ * Statuses as for hisq_cg (NOT_CONVERGED / BREAKDOWN if any problem ends so).
+ * Synchronous. */
+hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_problem *problems, hisq_prec inner,
+                          int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, double *latency_s,
+                          void *stream);
+
 /* Launch shape of hisq_dslash (and of the Dslash inside the solvers).
  *   variant   0: one thread per output site; 1: four lanes per site, one per
  *             direction, combined by wavefront shuffles.

@@ -40,7 +40,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     pending = []
     objs = []
     for src in sources():
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(BUILD_DIR, src + ".o")
         objs.append(obj)
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         pending.append((src, cmd))

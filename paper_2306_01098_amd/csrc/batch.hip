@@ -1,0 +1,341 @@
+// Batched CG over many independent problems on lattices of different sizes.
+//
+// One launch covers the sites of every problem: a work list maps each block
+// to (problem, first site), so 64 small solves advance together with four
+// launches per iteration instead of 256, and the sequence is captured once in
+// a HIP graph.  Per-problem Krylov scalars live on the device; the last block
+// of each reducing kernel advances them for all problems in a fixed order.
+#include "batch.hpp"
+#include "dslash.hpp"
+#include "reduce.hpp"
+
+namespace hisq {
+
+namespace {
+
+constexpr int BB = BATCH_BLOCK;
+
+template <int FP> struct SloppyT;
+template <> struct SloppyT<HISQ_FP64> { using T = double; };
+template <> struct SloppyT<HISQ_FP32> { using T = float; };
+
+__device__ __forceinline__ bool pos_finite(double v) { return v > 0.0 && v < 1.0e308; }
+
+// Whether problem j takes part in a launch of the given role.
+__device__ __forceinline__ bool participates(const BatchArgs &a, int j, int role) {
+    return role <= ROLE_ITER_DEO ? a.st[j].active != 0 : a.mask[j] != 0;
+}
+
+// Per-problem totals of block partials (blocks of a problem are contiguous).
+__device__ void batch_totals(const BatchArgs &a, double *tot /* shared [MAX_BATCH] */) {
+    __shared__ double lds[4];
+    for (int j = 0; j < a.nprob; ++j) {
+        const BatchProb &P = a.probs[j];
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < P.nblk; b += blockDim.x)
+            v[0] += __builtin_nontemporal_load(a.partials + P.first_blk + b);
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0)
+            tot[j] = v[0];
+        __syncthreads();
+    }
+}
+
+// Dslash over all participating problems.
+//  ROLE_ITER_DOE: t = D_oe p             (sloppy links/fields)
+//  ROLE_ITER_DEO: q = m^2 p - D_eo t, Re<p, q> -> st[j].pq
+//  ROLE_TRUE_DOE: t64 = D_oe x           (FP64)
+//  ROLE_TRUE_DEO: ax = m^2 x - D_eo t64  (FP64)
+template <int LP, int FP, int ROLE>
+__global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
+    using A = typename Prec<LP>::acc;
+    if (ROLE <= ROLE_ITER_DEO && *a.skip)  // iterations stop once no problem is active
+        return;
+    constexpr bool DOT = ROLE == ROLE_ITER_DEO;
+    constexpr bool AXPY = ROLE == ROLE_ITER_DEO || ROLE == ROLE_TRUE_DEO;
+    constexpr int parity = (ROLE == ROLE_ITER_DOE || ROLE == ROLE_TRUE_DOE) ? 1 : 0;
+    const int blk = blockIdx.x;
+    const int j = a.blk_prob[blk];
+    const BatchProb &P = a.probs[j];
+    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const bool go = participates(a, j, ROLE) && i < P.g.vh;
+    double dot[1] = {0.0};
+    if (go) {
+        const char *links = ROLE <= ROLE_ITER_DEO ? P.links_in : P.links64;
+        const void *in = ROLE == ROLE_ITER_DOE ? P.p : ROLE == ROLE_ITER_DEO ? P.t : ROLE == ROLE_TRUE_DOE ? P.x : P.t64;
+        void *out = ROLE == ROLE_ITER_DOE ? P.t : ROLE == ROLE_ITER_DEO ? P.q : ROLE == ROLE_TRUE_DOE ? P.t64 : P.ax;
+        cplx<A> acc[1][3];
+        dslash_site<LP, FP, 1, A>(P.g, parity, links, in, i, 0, 1, acc);
+        if (AXPY) {
+            const void *y = ROLE == ROLE_ITER_DEO ? P.p : P.x;
+            cplx<A> yv[3];
+            FieldIO<FP>::template load<A>(y, P.g.vh, 0, i, yv);
+            const A m2 = (A)P.m2;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc[0][c].re = fma(m2, yv[c].re, -acc[0][c].re);
+                acc[0][c].im = fma(m2, yv[c].im, -acc[0][c].im);
+                if (DOT) {
+                    dot[0] = fma((double)yv[c].re, (double)acc[0][c].re, dot[0]);
+                    dot[0] = fma((double)yv[c].im, (double)acc[0][c].im, dot[0]);
+                }
+            }
+        }
+        FieldIO<FP>::template store<A>(out, P.g.vh, 0, i, acc[0]);
+    }
+    if (!DOT)
+        return;
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot[MAX_BATCH];
+    block_sum<1>(dot, lds);
+    if (threadIdx.x == 0)
+        a.partials[blk] = dot[0];
+    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
+        return;
+    batch_totals(a, tot);
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+        if (a.st[jj].active)
+            a.st[jj].pq = tot[jj];
+}
+
+// x += alpha p, r -= alpha q, <r, r>; the last block advances every active
+// problem's scalars (and stamps the device clock when a problem's iterated
+// residual meets its target).
+template <int FP>
+__global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
+    using T = typename SloppyT<FP>::T;
+    if (*a.skip)
+        return;
+    const int blk = blockIdx.x;
+    const int j = a.blk_prob[blk];
+    const BatchProb &P = a.probs[j];
+    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const CgScalars st = a.st[j];
+    const bool go = st.active && pos_finite(st.pq) && i < P.g.vh;
+    double part[1] = {0.0};
+    if (go) {
+        const double alpha = st.rho / st.pq;
+        const T al = (T)alpha;
+        cplx<T> p[3], q[3], r[3];
+        cplx<double> x[3];
+        FieldIO<FP>::template load<T>(P.p, P.g.vh, 0, i, p);
+        FieldIO<FP>::template load<T>(P.q, P.g.vh, 0, i, q);
+        FieldIO<FP>::template load<T>(P.r, P.g.vh, 0, i, r);
+        FieldIO<HISQ_FP64>::template load<double>(P.x, P.g.vh, 0, i, x);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c].re = fma(alpha, (double)p[c].re, x[c].re);
+            x[c].im = fma(alpha, (double)p[c].im, x[c].im);
+            r[c].re = fma(-al, q[c].re, r[c].re);
+            r[c].im = fma(-al, q[c].im, r[c].im);
+            part[0] = fma((double)r[c].re, (double)r[c].re, part[0]);
+            part[0] = fma((double)r[c].im, (double)r[c].im, part[0]);
+        }
+        FieldIO<HISQ_FP64>::template store<double>(P.x, P.g.vh, 0, i, x);
+        FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, r);
+    }
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot[MAX_BATCH];
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        a.partials[blk] = part[0];
+    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
+        return;
+    batch_totals(a, tot);
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    const double now = (double)wall_clock64();
+    int any = 0;
+    for (int jj = 0; jj < a.nprob; ++jj) {
+        CgScalars s = a.st[jj];
+        if (s.active) {
+            if (!pos_finite(s.pq)) {
+                s.flag = FLAG_BREAKDOWN;
+                s.active = 0;
+            } else {
+                const double rho_new = tot[jj];
+                s.iters += 1;
+                s.rho_new = rho_new;
+                if (!(rho_new == rho_new)) {
+                    s.flag = FLAG_BREAKDOWN;
+                    s.active = 0;
+                } else if (rho_new <= s.target2) {
+                    s.flag = FLAG_CONV;
+                    s.active = 0;
+                } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
+                    s.flag = FLAG_RELIABLE;
+                    s.active = 0;
+                } else if (s.iters >= s.max_iter) {
+                    s.flag = FLAG_MAXIT;
+                    s.active = 0;
+                } else {
+                    s.beta = rho_new / s.rho;
+                    s.rho = rho_new;
+                    s.rmax2 = fmax(s.rmax2, rho_new);
+                }
+            }
+            if (!s.active)
+                s.spare = now;  // device clock when the recurrence stopped
+            a.st[jj] = s;
+        }
+        any |= s.active;
+    }
+    *a.skip = any ? 0 : 1;
+}
+
+// p = r + beta p for active problems.
+template <int FP>
+__global__ void __launch_bounds__(BB) batch_p_kernel(BatchArgs a) {
+    using T = typename SloppyT<FP>::T;
+    if (*a.skip)
+        return;
+    const int blk = blockIdx.x;
+    const int j = a.blk_prob[blk];
+    const BatchProb &P = a.probs[j];
+    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const CgScalars st = a.st[j];
+    if (!st.active || i >= P.g.vh)
+        return;
+    cplx<T> p[3], r[3];
+    FieldIO<FP>::template load<T>(P.p, P.g.vh, 0, i, p);
+    FieldIO<FP>::template load<T>(P.r, P.g.vh, 0, i, r);
+    const T b = (T)st.beta;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p[c].re = fma(b, p[c].re, r[c].re);
+        p[c].im = fma(b, p[c].im, r[c].im);
+    }
+    FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, p);
+}
+
+// For masked problems: r = b - ax (sloppy copy) and ||b - ax||^2 -> st.rho_new
+// (FP64); with `copy_p` also p = r (start of a solve).
+template <int FP>
+__global__ void __launch_bounds__(BB) batch_residual_kernel(BatchArgs a, int copy_p) {
+    using T = typename SloppyT<FP>::T;
+    const int blk = blockIdx.x;
+    const int j = a.blk_prob[blk];
+    const BatchProb &P = a.probs[j];
+    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    double part[1] = {0.0};
+    if (a.mask[j] && i < P.g.vh) {
+        cplx<double> bv[3], av[3];
+        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 0, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(P.ax, P.g.vh, 0, i, av);
+        cplx<T> rv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double re = bv[c].re - av[c].re, im = bv[c].im - av[c].im;
+            part[0] = fma(re, re, part[0]);
+            part[0] = fma(im, im, part[0]);
+            rv[c].re = (T)re;
+            rv[c].im = (T)im;
+        }
+        FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, rv);
+        if (copy_p)
+            FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, rv);
+    }
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot[MAX_BATCH];
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        a.partials[blk] = part[0];
+    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
+        return;
+    batch_totals(a, tot);
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+        if (a.mask[jj])
+            a.st[jj].rho_new = tot[jj];
+}
+
+// ||b||^2 of every problem -> st.rmax2 (used once, before the solve).
+__global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a, double *bnorm2) {
+    const int blk = blockIdx.x;
+    const int j = a.blk_prob[blk];
+    const BatchProb &P = a.probs[j];
+    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    double part[1] = {0.0};
+    if (i < P.g.vh) {
+        cplx<double> bv[3];
+        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 0, i, bv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            part[0] = fma(bv[c].re, bv[c].re, part[0]);
+            part[0] = fma(bv[c].im, bv[c].im, part[0]);
+        }
+    }
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot[MAX_BATCH];
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        a.partials[blk] = part[0];
+    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
+        return;
+    batch_totals(a, tot);
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+        bnorm2[jj] = tot[jj];
+}
+
+__global__ void batch_clock_kernel(double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *out = (double)wall_clock64();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st) {
+    const dim3 g((unsigned)nblocks);
+    const bool f64 = lp == HISQ_FP64;
+    const bool f16 = lp == HISQ_FP16N;
+    switch (op) {
+    case BOP_ITER_DOE:
+        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
+        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
+        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
+        break;
+    case BOP_ITER_DEO:
+        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
+        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
+        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
+        break;
+    case BOP_TRUE_DOE: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DOE><<<g, BB, 0, st>>>(a); break;
+    case BOP_TRUE_DEO: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DEO><<<g, BB, 0, st>>>(a); break;
+    case BOP_XR:
+        if (f64) batch_xr_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a);
+        else batch_xr_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a);
+        break;
+    case BOP_P:
+        if (f64) batch_p_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a);
+        else batch_p_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a);
+        break;
+    case BOP_RESIDUAL:
+    case BOP_RESIDUAL_COPY_P: {
+        const int cp = op == BOP_RESIDUAL_COPY_P;
+        if (f64) batch_residual_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a, cp);
+        else batch_residual_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a, cp);
+        break;
+    }
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bnorm(const BatchArgs &a, int nblocks, double *bnorm2, hipStream_t st) {
+    batch_bnorm_kernel<<<dim3((unsigned)nblocks), BB, 0, st>>>(a, bnorm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_clock(double *out, hipStream_t st) {
+    batch_clock_kernel<<<1, 64, 0, st>>>(out);
+    return hipGetLastError();
+}
+
+}  // namespace hisq

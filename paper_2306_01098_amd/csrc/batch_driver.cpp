@@ -1,0 +1,395 @@
+// Host driver of the batched CG (hisq_cg_batch): many independent problems,
+// each with its own lattice, mass, links and tolerance, solved together.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "api_util.hpp"
+#include "batch.hpp"
+
+namespace hisq {
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    int fs;
+    int nblocks;
+    size_t probs, blk, state, mask, partials, flags, scal, fields, total;
+    std::vector<size_t> r, p, q, t, ax, t64;
+    std::vector<int> first_blk, nblk;
+};
+
+BatchLayout batch_layout(int n, const hisq_problem *pr, int inner) {
+    BatchLayout L;
+    L.fs = inner == HISQ_FP64 ? HISQ_FP64 : HISQ_FP32;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = al256(off + b);
+        return o;
+    };
+    L.nblocks = 0;
+    for (int j = 0; j < n; ++j) {
+        const Geom g = make_geom(pr[j].lat);
+        const int nb = (g.vh + BATCH_BLOCK - 1) / BATCH_BLOCK;
+        L.first_blk.push_back(L.nblocks);
+        L.nblk.push_back(nb);
+        L.nblocks += nb;
+    }
+    L.probs = take(sizeof(BatchProb) * n);
+    L.blk = take(sizeof(int) * L.nblocks);
+    L.state = take(sizeof(CgScalars) * n);
+    L.mask = take(sizeof(int) * n);
+    L.partials = take(sizeof(double) * L.nblocks);
+    L.flags = take(64 * sizeof(unsigned));
+    L.scal = take(sizeof(double) * (MAX_BATCH + 8));
+    for (int j = 0; j < n; ++j) {
+        const Geom g = make_geom(pr[j].lat);
+        const size_t fb = field_bytes(g, L.fs, 1), f64 = field_bytes(g, HISQ_FP64, 1);
+        L.r.push_back(take(fb));
+        L.p.push_back(take(fb));
+        L.q.push_back(take(fb));
+        L.t.push_back(take(fb));
+        L.ax.push_back(take(f64));
+        L.t64.push_back(take(f64));
+    }
+    L.total = off;
+    return L;
+}
+
+double wall_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum { BF_SKIP = 0, BF_COUNTER = 8 };
+
+}  // namespace
+
+}  // namespace hisq
+
+using namespace hisq;
+
+extern "C" {
+
+size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *problems, hisq_prec inner) {
+    if (nproblems < 1 || nproblems > MAX_BATCH || !problems || check_prec(inner) != HISQ_OK)
+        return 0;
+    for (int j = 0; j < nproblems; ++j)
+        if (check_lattice(&problems[j].lat) != HISQ_OK)
+            return 0;
+    return batch_layout(nproblems, problems, inner).total;
+}
+
+hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_problem *problems, hisq_prec inner,
+                          int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, double *latency_s,
+                          void *stream) {
+    const double t0 = wall_s();
+    if (nproblems < 1 || nproblems > MAX_BATCH)
+        return fail(HISQ_ERR_INVALID_ARG, "nproblems = %d outside [1, %d]", nproblems, MAX_BATCH);
+    hisq_status s = check_ptr(problems, "problems");
+    if (s == HISQ_OK) s = check_prec(inner);
+    if (s == HISQ_OK) s = check_ptr(ws, "ws");
+    if (s == HISQ_OK && max_iter < 1)
+        s = fail(HISQ_ERR_INVALID_ARG, "max_iter = %d must be >= 1", max_iter);
+    for (int j = 0; s == HISQ_OK && j < nproblems; ++j) {
+        const hisq_problem &P = problems[j];
+        s = check_lattice(&P.lat);
+        if (s == HISQ_OK && (!std::isfinite(P.mass) || P.mass * P.mass <= 0.0))
+            s = fail(HISQ_ERR_INVALID_ARG, "problem %d: mass^2 must be positive", j);
+        if (s == HISQ_OK && !(P.tol > 0.0 && P.tol < 1.0))
+            s = fail(HISQ_ERR_INVALID_ARG, "problem %d: tol = %g must be in (0, 1)", j, P.tol);
+        if (s == HISQ_OK && (!P.links_f64 || !P.b || !P.x || (inner != HISQ_FP64 && !P.links_inner)))
+            s = fail(HISQ_ERR_INVALID_ARG, "problem %d: NULL links, b or x", j);
+        if (s == HISQ_OK && P.b == P.x)
+            s = fail(HISQ_ERR_INVALID_ARG, "problem %d: b and x alias", j);
+    }
+    if (s == HISQ_OK) s = set_device(ctx);
+    if (s != HISQ_OK)
+        return s;
+    const BatchLayout L = batch_layout(nproblems, problems, inner);
+    if (ws_bytes < L.total)
+        return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, L.total);
+    char *W = static_cast<char *>(ws);
+    const int n = nproblems;
+    const int lp = inner;
+
+    // private stream ordered after the caller's (graphs cannot capture the legacy stream)
+    hipStream_t caller = static_cast<hipStream_t>(stream), st = nullptr;
+    hipEvent_t ev = nullptr;
+    struct Cleanup {
+        hipStream_t *st;
+        hipEvent_t *ev;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~Cleanup() {
+            if (exec) hipGraphExecDestroy(exec);
+            if (graph) hipGraphDestroy(graph);
+            if (*st) {
+                hipStreamSynchronize(*st);
+                hipStreamDestroy(*st);
+            }
+            if (*ev) hipEventDestroy(*ev);
+        }
+    } cleanup{&st, &ev};
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+    if (e != hipSuccess)
+        return device_fail(e, "stream setup");
+
+    // problem table and work list
+    std::vector<BatchProb> probs(n);
+    std::vector<int> blk(L.nblocks);
+    for (int j = 0; j < n; ++j) {
+        const hisq_problem &P = problems[j];
+        BatchProb &B = probs[j];
+        B.g = make_geom(P.lat);
+        B.m2 = P.mass * P.mass;
+        B.links64 = static_cast<const char *>(P.links_f64);
+        B.links_in = inner == HISQ_FP64 ? B.links64 : static_cast<const char *>(P.links_inner);
+        B.b = P.b;
+        B.x = P.x;
+        B.r = W + L.r[j];
+        B.p = W + L.p[j];
+        B.q = W + L.q[j];
+        B.t = W + L.t[j];
+        B.ax = W + L.ax[j];
+        B.t64 = W + L.t64[j];
+        B.first_blk = L.first_blk[j];
+        B.nblk = L.nblk[j];
+        for (int b = 0; b < L.nblk[j]; ++b)
+            blk[L.first_blk[j] + b] = j;
+    }
+    BatchArgs a{};
+    a.probs = reinterpret_cast<const BatchProb *>(W + L.probs);
+    a.nprob = n;
+    a.blk_prob = reinterpret_cast<const int *>(W + L.blk);
+    a.st = reinterpret_cast<CgScalars *>(W + L.state);
+    a.mask = reinterpret_cast<const int *>(W + L.mask);
+    a.partials = reinterpret_cast<double *>(W + L.partials);
+    unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
+    a.counter = flags + BF_COUNTER;
+    a.skip = reinterpret_cast<int *>(flags + BF_SKIP);
+    double *scal = reinterpret_cast<double *>(W + L.scal);  // [0..n) ||b||^2, [MAX_BATCH] start clock
+    int *mask_d = reinterpret_cast<int *>(W + L.mask);
+
+    std::vector<CgScalars> hs(n);
+    std::vector<int> mask(n, 1), reliable(n, 0);
+    std::vector<double> bnorm2(n), rtrue2(n, 0.0), t_stop(n, 0.0);
+    auto push = [&](bool state, bool msk) -> hipError_t {
+        hipError_t err = hipSuccess;
+        if (state) {
+            int any = 0;
+            for (int j = 0; j < n; ++j) any |= hs[j].active;
+            const unsigned skip = any ? 0u : 1u;
+            err = hipMemcpyAsync(a.st, hs.data(), sizeof(CgScalars) * n, hipMemcpyHostToDevice, st);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(flags + BF_SKIP, &skip, sizeof skip, hipMemcpyHostToDevice, st);
+        }
+        if (msk && err == hipSuccess)
+            err = hipMemcpyAsync(mask_d, mask.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(st);
+        return err;
+    };
+    auto pull = [&]() -> hipError_t {
+        hipError_t err = hipMemcpyAsync(hs.data(), a.st, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(st);
+        return err;
+    };
+    // true residual of the masked problems: r = b - M x (FP64), rho_new = ||r||^2
+    auto true_residuals = [&](bool copy_p) -> hipError_t {
+        hipError_t err = push(false, true);
+        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_TRUE_DOE, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_TRUE_DEO, lp, st);
+        if (err == hipSuccess)
+            err = launch_batch(a, L.nblocks, copy_p ? BOP_RESIDUAL_COPY_P : BOP_RESIDUAL, lp, st);
+        if (err == hipSuccess) err = pull();
+        return err;
+    };
+
+    e = hipMemcpyAsync(W + L.probs, probs.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(W + L.blk, blk.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_fill_u32(flags, 64, 0u, st);
+    for (int j = 0; j < n; ++j) {
+        CgScalars c{};
+        c.active = 0;
+        hs[j] = c;
+    }
+    if (e == hipSuccess) e = push(true, true);
+    if (e == hipSuccess) e = launch_batch_bnorm(a, L.nblocks, scal, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bnorm2.data(), scal, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = true_residuals(true);
+    if (e != hipSuccess)
+        return device_fail(e, "batch setup");
+    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    bool breakdown = false;
+    for (int j = 0; j < n; ++j) {
+        CgScalars c{};
+        rtrue2[j] = hs[j].rho_new;
+        c.rho = rtrue2[j];
+        c.rmax2 = rtrue2[j];
+        c.target2 = problems[j].tol * problems[j].tol * bnorm2[j];
+        c.delta2 = delta * delta;
+        c.max_iter = max_iter;
+        if (!std::isfinite(bnorm2[j]) || !std::isfinite(rtrue2[j])) {
+            c.flag = FLAG_BREAKDOWN;
+            breakdown = true;
+        } else if (rtrue2[j] <= c.target2) {
+            c.flag = FLAG_DONE;
+        } else {
+            c.flag = FLAG_RUN;
+            c.active = 1;
+        }
+        hs[j] = c;
+    }
+    e = push(true, false);
+    if (e == hipSuccess) e = launch_batch_clock(scal + MAX_BATCH, st);
+    if (e != hipSuccess)
+        return device_fail(e, "batch start");
+
+    // graph of one chunk of batched iterations
+    const int chunk = 16;
+    auto iterate = [&]() -> hipError_t {
+        hipError_t err = launch_batch(a, L.nblocks, BOP_ITER_DOE, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_ITER_DEO, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_XR, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_P, lp, st);
+        return err;
+    };
+    bool use_graph = false;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < chunk && le == hipSuccess; ++k)
+            le = iterate();
+        hipError_t ce = hipStreamEndCapture(st, &cleanup.graph);
+        if (le == hipSuccess && ce == hipSuccess)
+            ce = hipGraphInstantiate(&cleanup.exec, cleanup.graph, nullptr, nullptr, 0);
+        use_graph = le == hipSuccess && ce == hipSuccess;
+    }
+    (void)hipGetLastError();
+
+    for (int round = 0; round < max_iter + 64; ++round) {
+        bool any = false;
+        for (int j = 0; j < n; ++j) any |= hs[j].active != 0;
+        if (!any)
+            break;
+        e = hipSuccess;
+        if (use_graph)
+            e = hipGraphLaunch(cleanup.exec, st);
+        for (int k = 0; !use_graph && k < chunk && e == hipSuccess; ++k)
+            e = iterate();
+        if (e == hipSuccess) e = pull();
+        if (e != hipSuccess)
+            return device_fail(e, "batch chunk");
+        // batched true residual for every problem that raised a flag
+        bool need = false;
+        for (int j = 0; j < n; ++j) {
+            mask[j] = !hs[j].active && (hs[j].flag == FLAG_CONV || hs[j].flag == FLAG_RELIABLE);
+            need |= mask[j] != 0;
+        }
+        if (!need)
+            continue;
+        std::vector<CgScalars> before = hs;
+        if ((e = true_residuals(false)) != hipSuccess)
+            return device_fail(e, "batch reliable update");
+        std::vector<int> restart(n, 0);
+        bool any_restart = false;
+        for (int j = 0; j < n; ++j) {
+            CgScalars c = before[j];
+            if (!mask[j]) {
+                hs[j] = c;
+                continue;
+            }
+            rtrue2[j] = hs[j].rho_new;
+            if (!std::isfinite(rtrue2[j])) {
+                c.flag = FLAG_BREAKDOWN;
+                breakdown = true;
+            } else if (rtrue2[j] <= c.target2) {
+                c.flag = FLAG_DONE;
+                t_stop[j] = c.spare;
+            } else if (c.iters >= c.max_iter) {
+                c.flag = FLAG_MAXIT;
+            } else {
+                reliable[j] += 1;
+                c.beta = rtrue2[j] / c.rho;
+                c.rho = rtrue2[j];
+                c.rmax2 = rtrue2[j];
+                c.flag = FLAG_RUN;
+                restart[j] = 1;
+                any_restart = true;
+            }
+            hs[j] = c;
+        }
+        if (any_restart) {
+            // p = r + beta p for the restarted problems only
+            std::vector<CgScalars> only = hs;
+            for (int j = 0; j < n; ++j) only[j].active = restart[j];
+            std::swap(only, hs);
+            e = push(true, false);
+            if (e == hipSuccess) e = launch_batch(a, L.nblocks, BOP_P, lp, st);
+            std::swap(only, hs);
+            for (int j = 0; j < n; ++j)
+                if (restart[j]) hs[j].active = 1;
+            if (e != hipSuccess)
+                return device_fail(e, "batch restart");
+        }
+        if ((e = push(true, false)) != hipSuccess)
+            return device_fail(e, "batch state");
+    }
+    double clock0 = 0.0;
+    e = hipMemcpyAsync(&clock0, scal + MAX_BATCH, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int rate_khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx ? ctx->device : 0);
+    if (e != hipSuccess)
+        return device_fail(e, "batch clock");
+    // final true residual of unfinished problems
+    bool need = false;
+    for (int j = 0; j < n; ++j) {
+        mask[j] = hs[j].flag != FLAG_DONE;
+        need |= mask[j] != 0;
+    }
+    if (need) {
+        std::vector<CgScalars> before = hs;
+        if ((e = true_residuals(false)) != hipSuccess)
+            return device_fail(e, "batch final residual");
+        for (int j = 0; j < n; ++j) {
+            if (mask[j]) {
+                rtrue2[j] = hs[j].rho_new;
+                before[j].flag = (std::isfinite(rtrue2[j]) && rtrue2[j] <= before[j].target2 &&
+                                  before[j].flag != FLAG_BREAKDOWN) ? FLAG_DONE : before[j].flag;
+            }
+        }
+        hs = before;
+    }
+    hisq_status result = HISQ_OK;
+    const double elapsed = wall_s() - t0;
+    for (int j = 0; j < n; ++j) {
+        if (info) {
+            info[j].iterations = hs[j].iters;
+            info[j].reliable_updates = reliable[j];
+            info[j].true_residual = bnorm2[j] > 0 ? std::sqrt(rtrue2[j] / bnorm2[j]) : std::sqrt(rtrue2[j]);
+            info[j].seconds = elapsed;
+        }
+        if (latency_s)
+            latency_s[j] = (t_stop[j] > 0.0 && rate_khz > 0) ? (t_stop[j] - clock0) / (rate_khz * 1e3) : 0.0;
+        if (hs[j].flag == FLAG_BREAKDOWN)
+            result = HISQ_ERR_BREAKDOWN;
+        else if (hs[j].flag != FLAG_DONE && result == HISQ_OK)
+            result = HISQ_ERR_NOT_CONVERGED;
+    }
+    if (breakdown)
+        result = HISQ_ERR_BREAKDOWN;
+    if (result != HISQ_OK)
+        fail(result, result == HISQ_ERR_BREAKDOWN ? "batch: a problem broke down" : "batch: not all problems converged");
+    return result;
+}
+
+}  // extern "C"

@@ -41,6 +41,12 @@ class hisq_dslash_shape(ctypes.Structure):
         return (self.variant, self.nin, self.block, self.xcd_remap)
 
 
+class hisq_problem(ctypes.Structure):
+    _fields_ = [("lat", hisq_lattice), ("mass", ctypes.c_double), ("links_f64", ctypes.c_void_p),
+                ("links_inner", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("tol", ctypes.c_double)]
+
+
 class hisq_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
@@ -82,6 +88,11 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double), _vp, ctypes.POINTER(_vp),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_size_t,
                                           ctypes.POINTER(hisq_solve_info), _vp]),
+    "hisq_cg_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(hisq_problem),
+                                                        ctypes.c_int]),
+    "hisq_cg_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(hisq_problem), ctypes.c_int,
+                                     ctypes.c_int32, _vp, ctypes.c_size_t, ctypes.POINTER(hisq_solve_info),
+                                     ctypes.POINTER(ctypes.c_double), _vp]),
 }
 
 
@@ -315,6 +326,40 @@ def hisq_multishift_cg(lat, mass: float, links_f64, links_inner, inner, shifts, 
     if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
         _check(st, "hisq_multishift_cg")
     return st, [info[k].as_dict() for k in range(n)]
+
+
+def make_problems(items):
+    """items: list of dicts with lat, mass, links_f64, links_inner, b, x, tol
+    (tensors); returns the ctypes array (keeps no references: hold the tensors)."""
+    arr = (hisq_problem * len(items))()
+    for k, it in enumerate(items):
+        lat = it["lat"]
+        fb = hisq_field_bytes(lat, "fp64", 1)
+        arr[k].lat = lat
+        arr[k].mass = float(it["mass"])
+        arr[k].links_f64 = _ptr(it["links_f64"], "links_f64", hisq_links_bytes(lat, "fp64"))
+        li = it.get("links_inner")
+        arr[k].links_inner = None if li is None else _ptr(li, "links_inner")
+        arr[k].b = _ptr(it["b"], "b", fb)
+        arr[k].x = _ptr(it["x"], "x", fb)
+        arr[k].tol = float(it["tol"])
+    return arr
+
+
+def hisq_cg_batch_workspace_bytes(problems, inner) -> int:
+    return int(load().hisq_cg_batch_workspace_bytes(len(problems), problems, _prec(inner)))
+
+
+def hisq_cg_batch(problems, inner, max_iter: int, ws, ctx=None, stream=None, check: bool = True):
+    """problems: array from make_problems.  Returns (status, infos, latencies)."""
+    n = len(problems)
+    info = (hisq_solve_info * n)()
+    lat_s = (ctypes.c_double * n)()
+    st = load().hisq_cg_batch(_ctx(ctx), n, problems, _prec(inner), int(max_iter), _ptr(ws, "ws"),
+                              ctypes.c_size_t(ws.numel()), info, lat_s, _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_cg_batch")
+    return st, [info[k].as_dict() for k in range(n)], [lat_s[k] for k in range(n)]
 
 
 # ---------------------------------------------------------------------------
