@@ -220,6 +220,65 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
                           int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, double *latency_s,
                           void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner: a parallel-transport convolution (PTC) network.
+ * The paper has no such component; the network follows the gauge-equivariant
+ * PTC layers of Lehner and Wettig (arXiv:2302.05419):
+ *   layer:  out_c(x) = sum_{c'} sum_p w[c][c'][p] (T_p in_{c'})(x),
+ *   paths:  p = 0 identity; 1 + 2mu: (T psi)(x) = X_mu(x) psi(x+mu);
+ *           2 + 2mu: (T psi)(x) = X_mu(x-mu)^+ psi(x-mu), time-boundary sign
+ *           on a hop that wraps (X = the fat links),
+ *   network: channels 1 -> 8 -> 8 -> 1, no bias, no nonlinearity, on the
+ *           whole lattice; input = an even-site field extended by zero,
+ *           output read on the even sites.
+ * Weights: HISQ_PTC_NWEIGHTS complex numbers, layer after layer, each layer
+ * [c_out][c_in][path]; the kernels read them as FP32 (interleaved float2);
+ * training keeps FP64 master weights and Adam moments (double2).
+ * Fields here are packed HISQ_FP32 (links: the packed FP32 links of the
+ * lattice; only X is used).
+ * ------------------------------------------------------------------------- */
+#define HISQ_PTC_NWEIGHTS 720
+
+/* Workspace of the network (activations of one application, gradients). */
+size_t hisq_ptc_workspace_bytes(const hisq_lattice *lat);
+/* out_even = N(in_even).  Keeps the activations in ws for hisq_ptc_backward.
+ * Asynchronous. */
+hisq_status hisq_ptc_forward(hisq_context *ctx, const hisq_lattice *lat, const void *links_f32, const void *weights,
+                             const void *in_even, void *out_even, void *ws, size_t ws_bytes, void *stream);
+/* Backward pass of the last hisq_ptc_forward with this ws: given the gradient
+ * g_out_even = dL/dRe y + i dL/dIm y of a real loss L, adds dL/dRe w + i dL/dIm w
+ * to grad (double2 [HISQ_PTC_NWEIGHTS], FP64 sums over sites in a fixed order)
+ * and writes the input gradient to g_in_even if it is not NULL.  Asynchronous. */
+hisq_status hisq_ptc_backward(hisq_context *ctx, const hisq_lattice *lat, const void *links_f32,
+                              const void *weights, const void *g_out_even, void *g_in_even, void *grad, void *ws,
+                              size_t ws_bytes, void *stream);
+/* One Adam step (real and imaginary parts as separate parameters; step counts
+ * from 1) on FP64 master weights w_master with moments m, v (double2
+ * [HISQ_PTC_NWEIGHTS]); also refreshes the FP32 copy w_f32.  Asynchronous. */
+hisq_status hisq_ptc_adam_step(hisq_context *ctx, void *w_master, void *w_f32, const void *grad, void *m, void *v,
+                               int32_t step, double lr, double beta1, double beta2, double eps, void *stream);
+/* One training step on `batch` pairs: loss L = (1/B) sum_i ||N(b_i) - x_i||^2 /
+ * ||x_i||^2 with src_f32 = packed FP32 sources [batch] and sol_f64 = packed
+ * FP64 solutions [batch]; gradients by hisq_ptc_backward, then one Adam step.
+ * *loss (host) receives L before the update.  Synchronous. */
+hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, const void *links_f32, void *w_master,
+                                void *w_f32, void *m, void *v, int32_t step, int32_t batch, const void *src_f32,
+                                const void *sol_f64, double lr, double beta1, double beta2, double eps,
+                                double *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace of hisq_fcg. */
+size_t hisq_fcg_workspace_bytes(const hisq_lattice *lat);
+/* Flexible CG (Notay, one-vector truncation) for M_e x = b with z = N(r) as
+ * the preconditioner: alpha = <p, r> / <p, A p>, p <- z - (<A p, z> / <p, A p>) p.
+ * FP32 links and iteration vectors, FP64 x, FP64 inner products; when the
+ * iterated residual falls by 10x or meets the target, the FP64 true residual
+ * replaces r and the recurrence restarts from z = N(r).  Stops on the FP64
+ * true residual <= tol ||b||.  b, x: packed HISQ_FP64 even fields; x holds the
+ * initial guess.  Statuses as for hisq_cg.  Synchronous. */
+hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                     const void *links_f32, const void *weights, const void *b, void *x, double tol,
+                     int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, void *stream);
+
 /* Launch shape of hisq_dslash (and of the Dslash inside the solvers).
  *   variant   0: one thread per output site; 1: four lanes per site, one per
  *             direction, combined by wavefront shuffles.

@@ -1,0 +1,147 @@
+// Vector kernels of flexible CG with a (possibly non-symmetric) preconditioner:
+// complex inner products, and updates with complex alpha, beta.
+#include "fcg.hpp"
+#include "reduce.hpp"
+
+namespace hisq {
+
+namespace {
+
+constexpr int FB = 256;
+
+// *out = <a, b> = sum conj(a) b of two FP32 even fields, FP64 sums.
+__global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const void *b, double *partials,
+                                                 unsigned *counter, double2 *out) {
+    __shared__ double lds[8];
+    __shared__ int last_flag;
+    __shared__ double tot[2];
+    const int i = blockIdx.x * FB + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < vh) {
+        cplx<float> x[3], y[3];
+        FieldIO<HISQ_FP32>::template load<float>(a, vh, 0, i, x);
+        FieldIO<HISQ_FP32>::template load<float>(b, vh, 0, i, y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[0] += (double)x[c].re * y[c].re + (double)x[c].im * y[c].im;
+            v[1] += (double)x[c].re * y[c].im - (double)x[c].im * y[c].re;
+        }
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = v[0];
+        partials[gridDim.x + blockIdx.x] = v[1];
+    }
+    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag)) {
+        sum_partials_block(partials, 2, gridDim.x, tot);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *out = make_double2(tot[0], tot[1]);
+    }
+}
+
+// alpha = <p, r> / <p, A p>; x += alpha p (FP64), r -= alpha q, ||r||^2; the
+// last block advances the scalars and raises the flags.
+__global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, const void *q, void *r,
+                                                FcgScalars *s, double *partials, unsigned *counter) {
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot;
+    const FcgScalars st = *s;
+    const bool ok = st.active && st.pq > 0.0 && st.pq < 1e308;
+    const double ar = ok ? st.pr.x / st.pq : 0.0, ai = ok ? st.pr.y / st.pq : 0.0;
+    const int i = blockIdx.x * FB + threadIdx.x;
+    double part[1] = {0.0};
+    if (ok && i < vh) {
+        cplx<float> pv[3], qv[3], rv[3];
+        cplx<double> xv[3];
+        FieldIO<HISQ_FP32>::template load<float>(p, vh, 0, i, pv);
+        FieldIO<HISQ_FP32>::template load<float>(q, vh, 0, i, qv);
+        FieldIO<HISQ_FP32>::template load<float>(r, vh, 0, i, rv);
+        FieldIO<HISQ_FP64>::template load<double>(x, vh, 0, i, xv);
+        const float fr = (float)ar, fi = (float)ai;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cmac(xv[c], ar, ai, cplx<double>{(double)pv[c].re, (double)pv[c].im});
+            cmac(rv[c], -fr, -fi, qv[c]);
+            part[0] += (double)rv[c].re * rv[c].re + (double)rv[c].im * rv[c].im;
+        }
+        FieldIO<HISQ_FP64>::template store<double>(x, vh, 0, i, xv);
+        FieldIO<HISQ_FP32>::template store<float>(r, vh, 0, i, rv);
+    }
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = part[0];
+    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
+        return;
+    sum_partials_block(partials, 1, gridDim.x, &tot);
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    FcgScalars n = *s;
+    if (!n.active)
+        return;
+    if (!ok) {
+        n.flag = FLAG_BREAKDOWN;
+        n.active = 0;
+    } else {
+        n.iters += 1;
+        n.rho = tot;
+        if (!(tot == tot)) {
+            n.flag = FLAG_BREAKDOWN;
+            n.active = 0;
+        } else if (tot <= n.target2) {
+            n.flag = FLAG_CONV;
+            n.active = 0;
+        } else if (n.delta2 > 0.0 && tot < n.delta2 * n.rmax2) {
+            n.flag = FLAG_RELIABLE;
+            n.active = 0;
+        } else if (n.iters >= n.max_iter) {
+            n.flag = FLAG_MAXIT;
+            n.active = 0;
+        } else {
+            n.rmax2 = fmax(n.rmax2, tot);
+        }
+    }
+    *s = n;
+}
+
+// beta = <A p, z> / <p, A p>;  p = z - beta p.
+__global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, const FcgScalars *s) {
+    const FcgScalars st = *s;
+    const int i = blockIdx.x * FB + threadIdx.x;
+    if (!st.active || i >= vh)
+        return;
+    const float br = (float)(st.qz.x / st.pq), bi = (float)(st.qz.y / st.pq);
+    cplx<float> zv[3], pv[3];
+    FieldIO<HISQ_FP32>::template load<float>(z, vh, 0, i, zv);
+    FieldIO<HISQ_FP32>::template load<float>(p, vh, 0, i, pv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<float> o = zv[c];
+        cmac(o, -br, -bi, pv[c]);
+        pv[c] = o;
+    }
+    FieldIO<HISQ_FP32>::template store<float>(p, vh, 0, i, pv);
+}
+
+}  // namespace
+
+hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, unsigned *counter, double2 *out,
+                          hipStream_t st) {
+    dot_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, a, b, partials, counter, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_xr(int vh, void *x, const void *p, const void *q, void *r, FcgScalars *s, double *partials,
+                         unsigned *counter, hipStream_t st) {
+    xr_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, x, p, q, r, s, partials, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_p(int vh, const void *z, void *p, const FcgScalars *s, hipStream_t st) {
+    p_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, z, p, s);
+    return hipGetLastError();
+}
+
+}  // namespace hisq

@@ -1,0 +1,443 @@
+// PTC network kernels: forward layers, backward (input gradient through the
+// adjoint transports, weight gradient as a deterministic reduction over all
+// sites), the training loss and Adam.  FP32 fields, FP64 reductions.
+#include "dslash.hpp"
+#include "ptc.hpp"
+#include "reduce.hpp"
+
+namespace hisq {
+
+namespace {
+
+constexpr int PB = PTC_BLOCK;
+
+struct Hop {
+    int nb;      // half-lattice index of the site read
+    int par;     // its parity
+    int lblk;    // link parity block
+    int lidx;    // link index
+    float sg;    // boundary sign
+    bool back;   // apply the adjoint
+};
+
+// Path p of the layer, at site (par, i): which site and link it reads.
+__device__ __forceinline__ Hop path_hop(const Geom &g, const Site &s, int par, int i, int p) {
+    Hop h;
+    if (p == 0) {
+        h.nb = i;
+        h.par = par;
+        h.lblk = 0;
+        h.lidx = 0;
+        h.sg = 1.f;
+        h.back = false;
+        return h;
+    }
+    const int mu = (p - 1) >> 1;
+    const bool fwd = ((p - 1) & 1) == 0;
+    const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
+    const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
+    const int stride = mu == 1 ? g.hx : mu == 2 ? g.hx * g.ny : g.hx * g.ny * g.nz;
+    neighbour<float>(g, i, c, n, stride, mu, fwd ? +1 : -1, h.nb, h.sg);
+    h.par = 1 - par;
+    h.lblk = fwd ? par : 1 - par;
+    h.lidx = fwd ? i : h.nb;
+    h.back = !fwd;
+    return h;
+}
+
+__device__ __forceinline__ void transport(const float m[18], bool back, float sg, const cplx<float> v[3],
+                                          cplx<float> t[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        t[a].re = t[a].im = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (!back)
+                cmac(t[a], m[6 * a + 2 * b], m[6 * a + 2 * b + 1], v[b]);
+            else
+                cmac_conj(t[a], m[6 * b + 2 * a], m[6 * b + 2 * a + 1], v[b]);
+        }
+        t[a].re *= sg;
+        t[a].im *= sg;
+    }
+}
+
+__device__ __forceinline__ const char *xblock(const char *links, int par, int mu, int vh) {
+    return links + link_block(0, par, mu, vh, 4);
+}
+
+// out_co(x) = sum_ci sum_p w[co][ci][p] (T_p in_ci)(x), one thread per site.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links, const float2 *w, const void *in,
+                                                       void *out) {
+    const int gid = blockIdx.x * PB + threadIdx.x;
+    if (gid >= 2 * g.vh)
+        return;
+    const int par = gid >= g.vh;
+    const int i = gid - par * g.vh;
+    const Site s = site_coords(g, par, i);
+    cplx<float> acc[COUT][3];
+#pragma unroll
+    for (int co = 0; co < COUT; ++co)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            acc[co][a].re = acc[co][a].im = 0.f;
+#pragma unroll
+    for (int p = 0; p < PTC_PATHS; ++p) {
+        const Hop h = path_hop(g, s, par, i, p);
+        float m[18];
+        if (p > 0)
+            LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
+        for (int ci = 0; ci < CIN; ++ci) {
+            cplx<float> v[3], t[3];
+            FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
+            if (p > 0) {
+                transport(m, h.back, h.sg, v, t);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    t[a] = v[a];
+            }
+#pragma unroll
+            for (int co = 0; co < COUT; ++co) {
+                const float2 wv = w[(co * CIN + ci) * PTC_PATHS + p];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    cmac(acc[co][a], wv.x, wv.y, t[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int co = 0; co < COUT; ++co)
+        FieldIO<HISQ_FP32>::template store<float>(out, g.vh, 2 * co + par, i, acc[co]);
+}
+
+// g_in_ci(x) = sum_p T_p^+ (sum_co conj(w[co][ci][p]) g_co)(x); T_{+mu}^+ = T_{-mu}.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *links, const float2 *w,
+                                                          const void *gout, void *gin) {
+    const int gid = blockIdx.x * PB + threadIdx.x;
+    if (gid >= 2 * g.vh)
+        return;
+    const int par = gid >= g.vh;
+    const int i = gid - par * g.vh;
+    const Site s = site_coords(g, par, i);
+    cplx<float> acc[CIN][3];
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            acc[ci][a].re = acc[ci][a].im = 0.f;
+#pragma unroll
+    for (int p = 0; p < PTC_PATHS; ++p) {
+        // adjoint of path p is the opposite hop
+        const int padj = p == 0 ? 0 : (((p - 1) & 1) == 0 ? p + 1 : p - 1);
+        const Hop h = path_hop(g, s, par, i, padj);
+        float m[18];
+        if (p > 0)
+            LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
+        for (int co = 0; co < COUT; ++co) {
+            cplx<float> v[3], t[3];
+            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + h.par, h.nb, v);
+            if (p > 0) {
+                transport(m, h.back, h.sg, v, t);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    t[a] = v[a];
+            }
+#pragma unroll
+            for (int ci = 0; ci < CIN; ++ci) {
+                const float2 wv = w[(co * CIN + ci) * PTC_PATHS + p];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    cmac_conj(acc[ci][a], wv.x, wv.y, t[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci)
+        FieldIO<HISQ_FP32>::template store<float>(gin, g.vh, 2 * ci + par, i, acc[ci]);
+}
+
+// Block partials of dL/dw[co][ci][p] = sum_x <(T_p in_ci)(x), g_co(x)> for
+// the (ci, p) pair blockIdx.y: partials[(pair * nblk + blk) * 2 COUT + k].
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *links, const void *in,
+                                                         const void *gout, double *partials) {
+    const int gid = blockIdx.x * PB + threadIdx.x;
+    const int pair = blockIdx.y;
+    const int ci = pair / PTC_PATHS, p = pair - ci * PTC_PATHS;
+    double acc[2 * COUT];
+#pragma unroll
+    for (int k = 0; k < 2 * COUT; ++k)
+        acc[k] = 0.0;
+    if (gid < 2 * g.vh) {
+        const int par = gid >= g.vh;
+        const int i = gid - par * g.vh;
+        const Site s = site_coords(g, par, i);
+        const Hop h = path_hop(g, s, par, i, p);
+        cplx<float> v[3], t[3];
+        FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
+        if (p > 0) {
+            float m[18];
+            LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
+            transport(m, h.back, h.sg, v, t);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                t[a] = v[a];
+        }
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) {
+            cplx<float> gv[3];
+            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + par, i, gv);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // conj(t) * g
+                acc[2 * co] += (double)t[a].re * gv[a].re + (double)t[a].im * gv[a].im;
+                acc[2 * co + 1] += (double)t[a].re * gv[a].im - (double)t[a].im * gv[a].re;
+            }
+        }
+    }
+    __shared__ double lds[4 * 2 * COUT];
+    block_sum<2 * COUT>(acc, lds);
+    if (threadIdx.x == 0) {
+        double *dst = partials + ((size_t)pair * gridDim.x + blockIdx.x) * 2 * COUT;
+#pragma unroll
+        for (int k = 0; k < 2 * COUT; ++k)
+            dst[k] = acc[k];
+    }
+}
+
+// grad[(co * CIN + ci) * 9 + p] += sum over blocks, one thread per real value,
+// blocks summed in order.
+__global__ void wgrad_reduce_kernel(int cin, int cout, int nblk, const double *partials, double2 *grad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;  // (pair, co, re/im)
+    const int total = cin * PTC_PATHS * cout * 2;
+    if (k >= total)
+        return;
+    const int pair = k / (2 * cout);
+    const int rem = k - pair * 2 * cout;
+    const int co = rem >> 1, part = rem & 1;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b)
+        s += partials[((size_t)pair * nblk + b) * 2 * cout + rem];
+    const int ci = pair / PTC_PATHS, p = pair - ci * PTC_PATHS;
+    double2 *dst = grad + (co * cin + ci) * PTC_PATHS + p;
+    if (part == 0)
+        dst->x += s;
+    else
+        dst->y += s;
+}
+
+// a0 = (in_even, 0 on odd sites), channel 0.
+__global__ void embed_kernel(int vh, const void *in_even, void *a0) {
+    const int gid = blockIdx.x * PB + threadIdx.x;
+    if (gid >= 2 * vh)
+        return;
+    const int par = gid >= vh;
+    const int i = gid - par * vh;
+    cplx<float> v[3];
+    if (par == 0) {
+        FieldIO<HISQ_FP32>::template load<float>(in_even, vh, 0, i, v);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            v[a].re = v[a].im = 0.f;
+    }
+    FieldIO<HISQ_FP32>::template store<float>(a0, vh, par, i, v);
+}
+
+__global__ void extract_kernel(int vh, const void *a3, void *out_even) {
+    const int i = blockIdx.x * PB + threadIdx.x;
+    if (i >= vh)
+        return;
+    cplx<float> v[3];
+    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, v);
+    FieldIO<HISQ_FP32>::template store<float>(out_even, vh, 0, i, v);
+}
+
+__global__ void __launch_bounds__(PB) norm2_even_kernel(int vh, const void *x64, double *partials,
+                                                        unsigned *counter, double *out) {
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    const int i = blockIdx.x * PB + threadIdx.x;
+    double part[1] = {0.0};
+    if (i < vh) {
+        cplx<double> v[3];
+        FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            part[0] += v[a].re * v[a].re + v[a].im * v[a].im;
+    }
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = part[0];
+    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
+        sum_partials_block(partials, 1, gridDim.x, out);
+}
+
+// g3 = (2 / (B ||x||^2)) (y - x) on even sites, 0 on odd sites;
+// *loss_acc += ||y - x||^2 / (B ||x||^2).
+__global__ void __launch_bounds__(PB) loss_kernel(int vh, const void *a3, const void *x64, const double *xnorm2,
+                                                  double inv_batch, void *g3, double *partials,
+                                                  unsigned *counter, double *loss_acc) {
+    __shared__ double lds[4];
+    __shared__ int last_flag;
+    __shared__ double tot;
+    const int gid = blockIdx.x * PB + threadIdx.x;
+    const double xn = *xnorm2;
+    const double coef = 2.0 * inv_batch / xn;
+    double part[1] = {0.0};
+    if (gid < 2 * vh) {
+        const int par = gid >= vh;
+        const int i = gid - par * vh;
+        cplx<float> gv[3];
+        if (par == 0) {
+            cplx<float> y[3];
+            cplx<double> x[3];
+            FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, y);
+            FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double dr = (double)y[a].re - x[a].re, di = (double)y[a].im - x[a].im;
+                part[0] += dr * dr + di * di;
+                gv[a].re = (float)(coef * dr);
+                gv[a].im = (float)(coef * di);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                gv[a].re = gv[a].im = 0.f;
+        }
+        FieldIO<HISQ_FP32>::template store<float>(g3, vh, par, i, gv);
+    }
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = part[0];
+    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag)) {
+        sum_partials_block(partials, 1, gridDim.x, &tot);
+        if (threadIdx.x == 0)
+            *loss_acc += tot * inv_batch / xn;
+    }
+}
+
+// Adam on real and imaginary parts as separate parameters; FP64 master
+// weights and moments, FP32 copy for the kernels.
+__global__ void adam_kernel(double2 *w, float2 *w32, const double2 *g, double2 *m, double2 *v, int step, double lr,
+                            double b1, double b2, double eps) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= PTC_NW)
+        return;
+    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    double2 wk = w[k], gk = g[k], mk = m[k], vk = v[k];
+    mk.x = b1 * mk.x + (1.0 - b1) * gk.x;
+    mk.y = b1 * mk.y + (1.0 - b1) * gk.y;
+    vk.x = b2 * vk.x + (1.0 - b2) * gk.x * gk.x;
+    vk.y = b2 * vk.y + (1.0 - b2) * gk.y * gk.y;
+    wk.x -= lr * (mk.x / c1) / (sqrt(vk.x / c2) + eps);
+    wk.y -= lr * (mk.y / c1) / (sqrt(vk.y / c2) + eps);
+    w[k] = wk;
+    m[k] = mk;
+    v[k] = vk;
+    w32[k] = make_float2((float)wk.x, (float)wk.y);
+}
+
+__global__ void fill_f64_kernel(double *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0.0;
+}
+
+inline unsigned nb(int64_t n) { return (unsigned)((n + PB - 1) / PB); }
+
+}  // namespace
+
+int ptc_blocks(const Geom &g) { return (int)nb(2 * (int64_t)g.vh); }
+
+hipError_t ptc_embed(const Geom &g, const void *in_even, void *a0, hipStream_t st) {
+    embed_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, in_even, a0);
+    return hipGetLastError();
+}
+
+hipError_t ptc_extract(const Geom &g, const void *a3, void *out_even, hipStream_t st) {
+    extract_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, a3, out_even);
+    return hipGetLastError();
+}
+
+hipError_t ptc_layer_fwd(const Geom &g, int cin, int cout, const char *links, const float2 *w, const void *in,
+                         void *out, hipStream_t st) {
+    const dim3 grid(nb(2 * (int64_t)g.vh));
+    if (cin == 1 && cout == PTC_CH)
+        layer_fwd_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, in, out);
+    else if (cin == PTC_CH && cout == PTC_CH)
+        layer_fwd_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, in, out);
+    else if (cin == PTC_CH && cout == 1)
+        layer_fwd_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, w, in, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links, const float2 *w,
+                            const void *g_out, void *g_in, hipStream_t st) {
+    const dim3 grid(nb(2 * (int64_t)g.vh));
+    if (cin == PTC_CH && cout == PTC_CH)
+        layer_bwd_in_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+    else if (cin == PTC_CH && cout == 1)
+        layer_bwd_in_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+    else if (cin == 1 && cout == PTC_CH)
+        layer_bwd_in_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, const void *in, const void *g_out,
+                           double *partials, double2 *grad, hipStream_t st) {
+    const int nblk = ptc_blocks(g);
+    const dim3 grid((unsigned)nblk, (unsigned)(cin * PTC_PATHS));
+    if (cin == 1 && cout == PTC_CH)
+        layer_bwd_w_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
+    else if (cin == PTC_CH && cout == PTC_CH)
+        layer_bwd_w_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
+    else if (cin == PTC_CH && cout == 1)
+        layer_bwd_w_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int total = cin * PTC_PATHS * cout * 2;
+    wgrad_reduce_kernel<<<(total + 255) / 256, 256, 0, st>>>(cin, cout, nblk, partials, grad);
+    return hipGetLastError();
+}
+
+hipError_t ptc_norm2_even(const Geom &g, const void *x64, double *partials, unsigned *counter, double *out,
+                          hipStream_t st) {
+    norm2_even_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, x64, partials, counter, out);
+    return hipGetLastError();
+}
+
+hipError_t ptc_loss(const Geom &g, const void *a3, const void *x64, const double *xnorm2, double inv_batch,
+                    void *g3, double *partials, unsigned *counter, double *loss_acc, hipStream_t st) {
+    loss_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, a3, x64, xnorm2, inv_batch, g3, partials, counter,
+                                                      loss_acc);
+    return hipGetLastError();
+}
+
+hipError_t ptc_adam(double2 *w_master, float2 *w_f32, const double2 *grad, double2 *m, double2 *v, int step,
+                    double lr, double b1, double b2, double eps, hipStream_t st) {
+    adam_kernel<<<(PTC_NW + 255) / 256, 256, 0, st>>>(w_master, w_f32, grad, m, v, step, lr, b1, b2, eps);
+    return hipGetLastError();
+}
+
+hipError_t ptc_fill_f64(double *p, size_t n, hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    fill_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+}  // namespace hisq

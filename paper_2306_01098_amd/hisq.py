@@ -93,6 +93,18 @@ _SIGS = {
     "hisq_cg_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(hisq_problem), ctypes.c_int,
                                      ctypes.c_int32, _vp, ctypes.c_size_t, ctypes.POINTER(hisq_solve_info),
                                      ctypes.POINTER(ctypes.c_double), _vp]),
+    "hisq_ptc_workspace_bytes": (ctypes.c_size_t, [_LAT]),
+    "hisq_ptc_forward": (ctypes.c_int, [_vp, _LAT, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "hisq_ptc_backward": (ctypes.c_int, [_vp, _LAT, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "hisq_ptc_adam_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
+    "hisq_ptc_train_step": (ctypes.c_int, [_vp, _LAT, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                           _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.POINTER(ctypes.c_double), _vp,
+                                           ctypes.c_size_t, _vp]),
+    "hisq_fcg_workspace_bytes": (ctypes.c_size_t, [_LAT]),
+    "hisq_fcg": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_double,
+                                ctypes.c_int32, _vp, ctypes.c_size_t, ctypes.POINTER(hisq_solve_info), _vp]),
 }
 
 
@@ -360,6 +372,99 @@ def hisq_cg_batch(problems, inner, max_iter: int, ws, ctx=None, stream=None, che
     if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
         _check(st, "hisq_cg_batch")
     return st, [info[k].as_dict() for k in range(n)], [lat_s[k] for k in range(n)]
+
+
+HISQ_PTC_NWEIGHTS = 720
+
+
+def hisq_ptc_workspace_bytes(lat) -> int:
+    return int(load().hisq_ptc_workspace_bytes(ctypes.byref(lat)))
+
+
+def hisq_ptc_forward(lat, links_f32, weights, in_even, out_even, ws, ctx=None, stream=None):
+    fb = hisq_field_bytes(lat, "fp32", 1)
+    _check(load().hisq_ptc_forward(_ctx(ctx), ctypes.byref(lat), _ptr(links_f32, "links_f32",
+                                                                      hisq_links_bytes(lat, "fp32")),
+                                   _ptr(weights, "weights", HISQ_PTC_NWEIGHTS * 8), _ptr(in_even, "in_even", fb),
+                                   _ptr(out_even, "out_even", fb), _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()),
+                                   _stream(stream)), "hisq_ptc_forward")
+
+
+def hisq_ptc_backward(lat, links_f32, weights, g_out_even, g_in_even, grad, ws, ctx=None, stream=None):
+    fb = hisq_field_bytes(lat, "fp32", 1)
+    _check(load().hisq_ptc_backward(_ctx(ctx), ctypes.byref(lat),
+                                    _ptr(links_f32, "links_f32", hisq_links_bytes(lat, "fp32")),
+                                    _ptr(weights, "weights", HISQ_PTC_NWEIGHTS * 8),
+                                    _ptr(g_out_even, "g_out_even", fb), _ptr(g_in_even, "g_in_even", fb),
+                                    _ptr(grad, "grad", HISQ_PTC_NWEIGHTS * 16), _ptr(ws, "ws"),
+                                    ctypes.c_size_t(ws.numel()), _stream(stream)), "hisq_ptc_backward")
+
+
+def hisq_ptc_adam_step(w_master, w_f32, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                       ctx=None, stream=None):
+    n16 = HISQ_PTC_NWEIGHTS * 16
+    _check(load().hisq_ptc_adam_step(_ctx(ctx), _ptr(w_master, "w_master", n16),
+                                     _ptr(w_f32, "w_f32", HISQ_PTC_NWEIGHTS * 8), _ptr(grad, "grad", n16),
+                                     _ptr(m, "m", n16), _ptr(v, "v", n16), int(step), float(lr), float(beta1),
+                                     float(beta2), float(eps), _stream(stream)), "hisq_ptc_adam_step")
+
+
+def hisq_ptc_train_step(lat, links_f32, w_master, w_f32, m, v, step, batch, src_f32, sol_f64, ws,
+                        lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ctx=None, stream=None) -> float:
+    n16 = HISQ_PTC_NWEIGHTS * 16
+    loss = ctypes.c_double()
+    _check(load().hisq_ptc_train_step(_ctx(ctx), ctypes.byref(lat),
+                                      _ptr(links_f32, "links_f32", hisq_links_bytes(lat, "fp32")),
+                                      _ptr(w_master, "w_master", n16), _ptr(w_f32, "w_f32", HISQ_PTC_NWEIGHTS * 8),
+                                      _ptr(m, "m", n16), _ptr(v, "v", n16), int(step), int(batch),
+                                      _ptr(src_f32, "src_f32", hisq_field_bytes(lat, "fp32", batch)),
+                                      _ptr(sol_f64, "sol_f64", hisq_field_bytes(lat, "fp64", batch)),
+                                      float(lr), float(beta1), float(beta2), float(eps), ctypes.byref(loss),
+                                      _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)),
+           "hisq_ptc_train_step")
+    return loss.value
+
+
+def hisq_fcg_workspace_bytes(lat) -> int:
+    return int(load().hisq_fcg_workspace_bytes(ctypes.byref(lat)))
+
+
+def hisq_fcg(lat, mass, links_f64, links_f32, weights, b, x, tol, max_iter, ws, ctx=None, stream=None,
+             check: bool = True):
+    info = hisq_solve_info()
+    fb = hisq_field_bytes(lat, "fp64", 1)
+    st = load().hisq_fcg(_ctx(ctx), ctypes.byref(lat), float(mass),
+                         _ptr(links_f64, "links_f64", hisq_links_bytes(lat, "fp64")),
+                         _ptr(links_f32, "links_f32", hisq_links_bytes(lat, "fp32")),
+                         _ptr(weights, "weights", HISQ_PTC_NWEIGHTS * 8), _ptr(b, "b", fb), _ptr(x, "x", fb),
+                         float(tol), int(max_iter), _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()),
+                         ctypes.byref(info), _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_fcg")
+    return st, info.as_dict()
+
+
+def weights_to_device(ws_list):
+    """Oracle-layout weights (list of [c_out][c_in][9] complex arrays) ->
+    (FP64 master double2 tensor, FP32 float2 tensor) on the GPU."""
+    import numpy as np
+    flat = np.concatenate([np.asarray(w, dtype=np.complex128).ravel() for w in ws_list])
+    assert flat.size == HISQ_PTC_NWEIGHTS
+    master = torch.from_numpy(flat.view(np.float64).copy()).cuda()
+    f32 = master.to(torch.float32)
+    return master, f32
+
+
+def weights_from_device(master):
+    import numpy as np
+    flat = master.cpu().numpy().view(np.complex128)
+    shapes = [(8, 1, 9), (8, 8, 9), (1, 8, 9)]
+    out, k = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(flat[k:k + n].reshape(sh))
+        k += n
+    return out
 
 
 # ---------------------------------------------------------------------------
