@@ -61,7 +61,216 @@ def parse():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-solution legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--suite", default="",
+                    help="comma list of extra workload legs to add to the JSON line: "
+                         "w1 (8^4 FP64 CG), w3 (48^3x12 16-rhs Dslash/CG and 14-shift CG), "
+                         "w4 (uneven batch of 64), w5 (32^4 PTC-preconditioned FCG vs mixed CG)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def leg_w1(h, gen, O, torch):
+    """8^4 Haar links, periodic time, m = 0.1: FP64 CG to 1e-10."""
+    w = gen.workload_1()
+    lat = h.lattice(w["dims"], w["t_bc"])
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    b = h.pack_field_from_host(lat, "fp64", w["src"][0])
+    x = h.empty_field(lat, "fp64")
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp64", 1, 0))
+    out = {}
+    for rep in range(2):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = h.hisq_cg(lat, w["mass"], l64, None, "fp64", 1, b, x, 1e-10, 20000, ws)
+        dt = time.perf_counter() - t0
+    xs = h.unpack_field_to_host(lat, "fp64", x)[0]
+    out["fp64_cg"] = {"seconds": round(dt, 5), "status": st, "iterations": info[0]["iterations"],
+                      "true_residual_oracle": O.true_residual(O.lattice_from(w), w["mass"], w["src"][0], xs)}
+    return out
+
+
+def leg_w3(h, gen, O, torch):
+    """48^3x12 smooth links, m = 0.005: 16-rhs FP32 Dslash, 16-rhs CG vs 16
+    single solves, 14-shift CG."""
+    import numpy as np
+    w = gen.workload_3()
+    dims, m = w["dims"], w["mass"]
+    lat = h.lattice(dims, w["t_bc"])
+    vh = int(np.prod(dims)) // 2
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+    out = {}
+    inp = h.pack_field_from_host(lat, "fp32", w["src"])
+    o = h.empty_field(lat, "fp32", 16)
+    for _ in range(3):
+        h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 20
+    byt = vh * (288 + 12 * 16) * 4
+    out["dslash_fp32_16rhs"] = {"us": round(t * 1e6, 1), "GB/s": round(byt / t / 1e9, 1),
+                                "TFLOP/s": round(vh * 16 * DSLASH_FLOP_PER_SITE / t / 1e12, 2)}
+    del inp, o
+    b = h.pack_field_from_host(lat, "fp64", w["src"])
+    x = h.empty_field(lat, "fp64", 16)
+    x.zero_()
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 16, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = h.hisq_cg(lat, m, l64, l32, "fp32", 16, b, x, 1e-10, 40000, ws)
+    t16 = time.perf_counter() - t0
+    out["cg16_batched"] = {"seconds": round(t16, 4), "status": st,
+                           "iterations": [i["iterations"] for i in info],
+                           "max_true_residual": max(i["true_residual"] for i in info)}
+    ws1 = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 1, 0))
+    fb = h.hisq_field_bytes(lat, "fp64", 1)
+    x1 = h.empty_field(lat, "fp64")
+    t0 = time.perf_counter()
+    its = []
+    for j in range(16):
+        x1.zero_()
+        st1, info1 = h.hisq_cg(lat, m, l64, l32, "fp32", 1, b[j * fb:(j + 1) * fb], x1, 1e-10, 40000, ws1)
+        its.append(info1[0]["iterations"])
+    tseq = time.perf_counter() - t0
+    out["cg16_sequential"] = {"seconds": round(tseq, 4), "iterations": its}
+    out["cg16_speedup_batched_vs_sequential"] = round(tseq / t16, 3)
+    shifts = w["shifts"]
+    xs = [h.empty_field(lat, "fp64") for _ in shifts]
+    wsm = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 1, len(shifts)))
+    t0 = time.perf_counter()
+    st, info = h.hisq_multishift_cg(lat, m, l64, l32, "fp32", shifts, b[:fb], xs, 1e-10, 40000, wsm)
+    tms = time.perf_counter() - t0
+    out["multishift14"] = {"seconds": round(tms, 4), "status": st,
+                           "iterations": [i["iterations"] for i in info],
+                           "true_residuals": [i["true_residual"] for i in info]}
+    return out
+
+
+def leg_w4(h, gen, O, torch):
+    """Uneven batch: 64 Haar-link solves, FP32 + FP64 reliable updates."""
+    import numpy as np
+    probs_in = gen.workload_4()
+    items = []
+    for w in probs_in:
+        lat = h.lattice(w["dims"], w["t_bc"])
+        l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+        l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+        b = h.pack_field_from_host(lat, "fp64", w["src"][0])
+        x = h.empty_field(lat, "fp64")
+        x.zero_()
+        items.append(dict(lat=lat, mass=w["mass"], links_f64=l64, links_inner=l32, b=b, x=x, tol=1e-10))
+    probs = h.make_problems(items)
+    ws = h.empty_workspace(h.hisq_cg_batch_workspace_bytes(probs, "fp32"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info, lat_s = h.hisq_cg_batch(probs, "fp32", 40000, ws)
+    tb = time.perf_counter() - t0
+    lat_ms = np.array(lat_s) * 1e3
+    out = {"batch_seconds": round(tb, 4), "status": st,
+           "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 2),
+           "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 2),
+           "iterations_min_max": [min(i["iterations"] for i in info), max(i["iterations"] for i in info)],
+           "max_true_residual": max(i["true_residual"] for i in info)}
+    t0 = time.perf_counter()
+    seq_lat = []
+    for it in items:
+        it["x"].zero_()
+        wsi = h.empty_workspace(h.hisq_cg_workspace_bytes(it["lat"], "fp32", 1, 0))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h.hisq_cg(it["lat"], it["mass"], it["links_f64"], it["links_inner"], "fp32", 1, it["b"], it["x"],
+                  1e-10, 40000, wsi)
+        seq_lat.append(time.perf_counter() - t1)
+    tseq = time.perf_counter() - t0
+    out["sequential_seconds"] = round(tseq, 4)
+    out["sequential_latency_ms_p50"] = round(float(np.percentile(np.array(seq_lat) * 1e3, 50)), 2)
+    out["speedup_batch_vs_sequential"] = round(tseq / tb, 3)
+    return out
+
+
+def leg_w5(h, gen, O, torch, ntrain=256, ntest=4, epochs=12):
+    """32^4 smooth links, m = 0.005: PTC network trained on (source, solution)
+    pairs from the plain solver, then FCG + PTC vs reliable-update mixed CG."""
+    import numpy as np
+    from oracle import ptc as P
+    dims = (32, 32, 32, 32)
+    w = gen.workload_smooth(dims, 5, -1, 0.3, 0)
+    m = 0.005
+    lat = h.lattice(dims, -1)
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+    del w["fat"], w["naik"]
+    out = {}
+    wsc = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 16, 0))
+    fb32, fb64 = h.hisq_field_bytes(lat, "fp32", 1), h.hisq_field_bytes(lat, "fp64", 1)
+    src32 = torch.empty(ntrain * fb32, dtype=torch.uint8, device="cuda")
+    sol64 = torch.empty(ntrain * fb64, dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    gen_iters = []
+    for k in range(0, ntrain, 16):
+        s = gen.gaussian_half_field(gen.rng_for(5000 + k, gen.FIELD_SOURCE), dims, 16)
+        b = h.pack_field_from_host(lat, "fp64", s)
+        x = sol64[k * fb64:(k + 16) * fb64]
+        x.zero_()
+        st, info = h.hisq_cg(lat, m, l64, l32, "fp32", 16, b, x, 1e-8, 40000, wsc)
+        gen_iters += [i["iterations"] for i in info]
+        h.hisq_pack_field(lat, "fp32", 16, torch.as_tensor(s, dtype=torch.complex128).cuda(),
+                          src32[k * fb32:(k + 16) * fb32])
+        log(f"w5: training pairs {k + 16}/{ntrain}")
+    out["pair_generation_seconds"] = round(time.perf_counter() - t0, 2)
+    out["pair_generation_cg_iterations_mean"] = float(np.mean(gen_iters))
+    del wsc
+    master, w32 = h.weights_to_device(P.init_weights(np.random.default_rng(0), scale=0.05))
+    mom, var = torch.zeros_like(master), torch.zeros_like(master)
+    wsp = h.empty_workspace(h.hisq_ptc_workspace_bytes(lat))
+    losses, step = [], 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        for k in range(0, ntrain, 16):
+            step += 1
+            losses.append(h.hisq_ptc_train_step(lat, l32, master, w32, mom, var, step, 16,
+                                                src32[k * fb32:(k + 16) * fb32], sol64[k * fb64:(k + 16) * fb64],
+                                                wsp, lr=3e-3))
+        log(f"w5: epoch {ep + 1}/{epochs} loss {losses[-1]:.4f}")
+    torch.cuda.synchronize()
+    out["training_seconds"] = round(time.perf_counter() - t0, 2)
+    out["training_steps"] = step
+    out["loss_first_last"] = [round(losses[0], 5), round(losses[-1], 5)]
+    del wsp, src32, sol64
+    wsf = h.empty_workspace(h.hisq_fcg_workspace_bytes(lat))
+    ws1 = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 1, 0))
+    test = gen.gaussian_half_field(gen.rng_for(5, gen.FIELD_SOURCE + 1), dims, ntest)
+    fcg, cg = [], []
+    for j in range(ntest):
+        b = h.pack_field_from_host(lat, "fp64", test[j])
+        x = h.empty_field(lat, "fp64")
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = h.hisq_fcg(lat, m, l64, l32, w32, b, x, 1e-10, 40000, wsf)
+        fcg.append((time.perf_counter() - t0, info["iterations"], info["true_residual"], st))
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = h.hisq_cg(lat, m, l64, l32, "fp32", 1, b, x, 1e-10, 40000, ws1)
+        cg.append((time.perf_counter() - t0, info[0]["iterations"], info[0]["true_residual"], st))
+        log(f"w5: held-out {j}: FCG+PTC {fcg[-1][:2]} mixed CG {cg[-1][:2]}")
+    out["fcg_ptc"] = {"seconds": [round(f[0], 4) for f in fcg], "iterations": [f[1] for f in fcg],
+                      "true_residual": [f[2] for f in fcg], "status": [f[3] for f in fcg]}
+    out["mixed_cg"] = {"seconds": [round(c[0], 4) for c in cg], "iterations": [c[1] for c in cg],
+                       "true_residual": [c[2] for c in cg], "status": [c[3] for c in cg]}
+    out["iteration_ratio_cg_over_fcg"] = round(float(np.mean([c[1] for c in cg]) / np.mean([f[1] for f in fcg])), 3)
+    out["time_ratio_cg_over_fcg"] = round(float(np.mean([c[0] for c in cg]) / np.mean([f[0] for f in fcg])), 3)
+    return out
 
 
 def main():
@@ -209,6 +418,19 @@ def main():
             "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{n} FP64 D_oe applications of the C oracle at 32^3x8 in ~10 s (same inputs), "
                       "algorithmic bytes per application / mean time"}
+
+    legs = [x for x in args.suite.split(",") if x]
+    if legs:
+        from oracle import hisq as O
+        result["workloads"] = {}
+        for leg in legs:
+            log(f"leg {leg} ...")
+            fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5}[leg]
+            t0 = time.perf_counter()
+            result["workloads"][leg] = fn(h, gen, O, torch)
+            result["workloads"][leg]["leg_wall_s"] = round(time.perf_counter() - t0, 1)
+            log(f"leg {leg}: {json.dumps(result['workloads'][leg])}")
+            torch.cuda.empty_cache()
 
     print(json.dumps(result), flush=True)
 

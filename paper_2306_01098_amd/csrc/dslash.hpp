@@ -156,15 +156,107 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
         }
 }
 
+// Registers of one hop: the link and the NIN neighbour vectors.
+template <int NIN, typename A> struct HopBuf {
+    A m[18];
+    cplx<A> v[NIN][3];
+};
+
+// Address of hop k (k = 4 mu + {0: +1, 1: -1, 2: +3, 3: -3}) of site s.
+struct HopAddr {
+    const char *blk;
+    int ilink, ipsi;
+    bool back;
+};
+
+template <int RB, typename A>
+__device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *links, int i, const Site &s, int k,
+                                            A &sg) {
+    const int mu = k >> 2, type = k & 3;
+    const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
+    const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
+    const int stride = mu == 1 ? g.hx : mu == 2 ? g.hx * g.ny : g.hx * g.ny * g.nz;
+    const int step = type == 0 ? 1 : type == 1 ? -1 : type == 2 ? 3 : -3;
+    int nb;
+    neighbour<A>(g, i, c, n, stride, mu, step, nb, sg);
+    HopAddr h;
+    h.back = (type & 1) != 0;
+    const int f = type >> 1;            // 0: fat X (one hop), 1: long W (three hops)
+    const int lpar = h.back ? 1 - p : p;
+    h.blk = links + link_block(f, lpar, mu, g.vh, RB);
+    h.ilink = h.back ? nb : i;
+    h.ipsi = nb;
+    return h;
+}
+
 // acc = (D psi)(site i of parity p), all four directions in this thread.
+// The sixteen hops are software-pipelined: the loads of hop k+1 are issued
+// before hop k is computed, so two hops' worth of link and vector loads are in
+// flight per wavefront instead of one.
 template <int LP, int FP, int NIN, typename A>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
                                             int r0, int nr, cplx<A> (&acc)[NIN][3]) {
+    constexpr int RB = Prec<LP>::real_bytes;
     const Site s = site_coords(g, p, i);
     zero<NIN, A>(acc);
+    cplx<A> tmp[NIN][3];
+    zero<NIN, A>(tmp);
+    HopBuf<NIN, A> buf[2];
+    A sgn[2];
+    bool back[2];
+    auto load = [&](int k, int slot) {
+        A sg;
+        const HopAddr h = hop_addr<RB, A>(g, p, links, i, s, k, sg);
+        LinkIO<LP>::load(h.blk, g.vh, h.ilink, buf[slot].m);
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu)
-        dslash_direction<LP, FP, NIN, A>(g, p, links, in, i, s, mu, r0, nr, acc);
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                FieldIO<FP>::template load<A>(in, g.vh, r0 + r, h.ipsi, buf[slot].v[r]);
+        sgn[slot] = sg;
+        back[slot] = h.back;
+    };
+    load(0, 0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int cur = k & 1;
+        if (k + 1 < 16)
+            load(k + 1, cur ^ 1);
+        const HopBuf<NIN, A> &b = buf[cur];
+        const A sg = sgn[cur];
+#pragma unroll
+        for (int r = 0; r < NIN; ++r) {
+            if (r < nr) {
+                cplx<A> v[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    v[c].re = b.v[r][c].re * sg;
+                    v[c].im = b.v[r][c].im * sg;
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (!back[cur])
+                            cmac(tmp[r][a], b.m[6 * a + 2 * c], b.m[6 * a + 2 * c + 1], v[c]);
+                        else
+                            cmac_conj(tmp[r][a], -b.m[6 * c + 2 * a], -b.m[6 * c + 2 * a + 1], v[c]);
+                    }
+            }
+        }
+        if ((k & 3) == 3) {
+            const int mu = k >> 2;
+            const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+            const A eta = (par & 1) ? (A)-1 : (A)1;
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    acc[r][a].re = fma(eta, tmp[r][a].re, acc[r][a].re);
+                    acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
+                    tmp[r][a].re = tmp[r][a].im = (A)0;
+                }
+        }
+    }
 }
 
 // out = ad * acc + ay * y  (EPI_AXPY*) for right-hand side r at site i;

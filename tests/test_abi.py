@@ -78,3 +78,73 @@ def test_dslash_argument_checks(lib):
     assert lib.hisq_dslash(None, lat, 7, 0, p(16), p(32), p(48), 1, None) == h.INVALID_ARG
     assert lib.hisq_apply_m(None, lat, 0, 0.0, p(16), p(32), p(48), p(64), 1, None) == h.INVALID_ARG
     assert b"mass" in lib.hisq_last_error()
+
+
+def test_solver_argument_checks_on_host(lib):
+    """Invalid solver arguments are rejected before any HIP call."""
+    from paper_2306_01098_amd import hisq as h
+    lat = h.lattice((4, 4, 4, 4), -1)
+    p = ctypes.c_void_p
+    info = (h.hisq_solve_info * 2)()
+    # tol outside (0, 1), mass 0, NULL b, aliasing b and x, bad nrhs
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 1, p(32), p(48), 0.0, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.0, p(16), None, 0, 1, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 1, None, p(48), 1e-8, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 1, p(32), p(32), 1e-8, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 17, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    # reduced inner precision needs its links
+    assert lib.hisq_cg(None, ctypes.byref(lat), 0.1, p(16), None, 1, 1, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                       info, None) == h.INVALID_ARG
+    # multi-shift: m^2 + shift <= 0, aliasing solutions
+    sh = (ctypes.c_double * 2)(-0.02, 0.1)
+    tl = (ctypes.c_double * 2)(1e-8, 1e-8)
+    xs = (ctypes.c_void_p * 2)(80, 96)
+    assert lib.hisq_multishift_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 2, sh, p(32), xs, tl, 10, p(64),
+                                  1 << 20, info, None) == h.INVALID_ARG
+    sh = (ctypes.c_double * 2)(0.0, 0.1)
+    xs = (ctypes.c_void_p * 2)(80, 80)
+    assert lib.hisq_multishift_cg(None, ctypes.byref(lat), 0.1, p(16), None, 0, 2, sh, p(32), xs, tl, 10, p(64),
+                                  1 << 20, info, None) == h.INVALID_ARG
+
+
+def test_workspace_queries(lib):
+    from paper_2306_01098_amd import hisq as h
+    lat = h.lattice((8, 8, 8, 8), -1)
+    a = h.hisq_cg_workspace_bytes(lat, "fp64", 1, 0)
+    b = h.hisq_cg_workspace_bytes(lat, "fp32", 16, 0)
+    c = h.hisq_cg_workspace_bytes(lat, "fp32", 1, 14)
+    assert 0 < a < b and a < c
+    assert h.hisq_cg_workspace_bytes(lat, "fp64", 1, 33) == 0
+    assert h.hisq_ptc_workspace_bytes(lat) > 2 * 8 * 4096 * 24   # two 8-channel activations
+    assert h.hisq_fcg_workspace_bytes(lat) > h.hisq_ptc_workspace_bytes(lat)
+    probs = (h.hisq_problem * 2)()
+    probs[0].lat = h.lattice((8, 8, 8, 8), -1)
+    probs[1].lat = h.lattice((4, 4, 4, 6), -1)
+    assert lib.hisq_cg_batch_workspace_bytes(2, probs, 1) > 0
+    probs[1].lat = h.lattice((4, 4, 4, 5), -1)
+    assert lib.hisq_cg_batch_workspace_bytes(2, probs, 1) == 0
+
+
+def test_batch_and_ptc_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    p = ctypes.c_void_p
+    probs = (h.hisq_problem * 1)()
+    probs[0].lat = h.lattice((4, 4, 4, 4), -1)
+    probs[0].mass = 0.1
+    probs[0].tol = 1e-8
+    info = (h.hisq_solve_info * 1)()
+    # NULL links / b / x
+    assert lib.hisq_cg_batch(None, 1, probs, 0, 10, p(16), 1 << 20, info, None, None) == h.INVALID_ARG
+    assert lib.hisq_cg_batch(None, 0, probs, 0, 10, p(16), 1 << 20, info, None, None) == h.INVALID_ARG
+    lat = h.lattice((4, 4, 4, 4), -1)
+    assert lib.hisq_ptc_forward(None, ctypes.byref(lat), None, p(16), p(32), p(48), p(64), 1 << 20,
+                                None) == h.INVALID_ARG
+    assert lib.hisq_ptc_adam_step(None, p(16), p(32), p(48), p(64), p(80), 0, 1e-3, 0.9, 0.999, 1e-8,
+                                  None) == h.INVALID_ARG
+    assert lib.hisq_fcg(None, ctypes.byref(lat), 0.1, p(16), p(24), p(32), p(40), p(40), 1e-8, 10, p(64),
+                        1 << 20, None, None) == h.INVALID_ARG
