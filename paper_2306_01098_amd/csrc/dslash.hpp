@@ -70,37 +70,6 @@ __device__ __forceinline__ int logical_block(int remap) {
     return x * q + min(x, r) + j;
 }
 
-// One hop: load the link once, apply it (BACK: its adjoint) to NIN colour
-// vectors at the neighbour and accumulate into tmp with sign sg.
-template <int LP, int FP, int NIN, bool BACK, typename A>
-__device__ __forceinline__ void hop(const char *blk, int vh, int ilink, const void *in, int ipsi,
-                                    int r0, int nr, A sg, cplx<A> (&tmp)[NIN][3]) {
-    A m[18];
-    LinkIO<LP>::load(blk, vh, ilink, m);
-#pragma unroll
-    for (int r = 0; r < NIN; ++r) {
-        if (r < nr) {
-            cplx<A> v[3];
-            FieldIO<FP>::template load<A>(in, vh, r0 + r, ipsi, v);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                v[c].re *= sg;
-                v[c].im *= sg;
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    if (!BACK)
-                        cmac(tmp[r][a], m[6 * a + 2 * b], m[6 * a + 2 * b + 1], v[b]);
-                    else  // -(U^+)_{ab} v_b = -conj(U_{ba}) v_b
-                        cmac_conj(tmp[r][a], -m[6 * b + 2 * a], -m[6 * b + 2 * a + 1], v[b]);
-                }
-            }
-        }
-    }
-}
-
 template <int NIN, typename A> __device__ __forceinline__ void zero(cplx<A> (&v)[NIN][3]) {
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
@@ -121,8 +90,50 @@ __device__ __forceinline__ void neighbour(const Geom &g, int i, int c, int n, in
     sg = (wrap && mu == 3) ? (A)g.t_bc : (A)1;
 }
 
+// Registers of one hop: the link and the NIN neighbour vectors.
+template <int NIN, typename A> struct HopBuf {
+    A m[18];
+    cplx<A> v[NIN][3];
+};
+
+// tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b).
+template <int NIN, typename A>
+__device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &b, bool back, A sg, int nr, cplx<A> (&tmp)[NIN][3]) {
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        if (r < nr) {
+            cplx<A> v[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c].re = b.v[r][c].re * sg;
+                v[c].im = b.v[r][c].im * sg;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!back)
+                        cmac(tmp[r][a], b.m[6 * a + 2 * c], b.m[6 * a + 2 * c + 1], v[c]);
+                    else  // -(U^+)_{ac} v_c = -conj(U_{ca}) v_c
+                        cmac_conj(tmp[r][a], -b.m[6 * c + 2 * a], -b.m[6 * c + 2 * a + 1], v[c]);
+                }
+        }
+    }
+}
+
+template <int LP, int FP, int NIN, typename A>
+__device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int vh, int ilink, const void *in,
+                                         int ipsi, int r0, int nr) {
+    LinkIO<LP>::load(blk, vh, ilink, b.m);
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+        if (r < nr)
+            FieldIO<FP>::template load<A>(in, vh, r0 + r, ipsi, b.v[r]);
+}
+
 // The four hops along direction mu (runtime) of site s (half index i, parity
-// p), times eta_mu(s), accumulated into acc.
+// p), times eta_mu(s), accumulated into acc.  The loads of the next hop are
+// issued before the current hop is computed.
 template <int LP, int FP, int NIN, typename A>
 __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
                                                  int i, const Site &s, int mu, int r0, int nr,
@@ -141,10 +152,15 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
     cplx<A> tmp[NIN][3];
     zero<NIN, A>(tmp);
     const int q = 1 - p;
-    hop<LP, FP, NIN, false>(links + link_block(0, p, mu, vh, RB), vh, i, in, n1, r0, nr, s1, tmp);
-    hop<LP, FP, NIN, true>(links + link_block(0, q, mu, vh, RB), vh, n2, in, n2, r0, nr, s2, tmp);
-    hop<LP, FP, NIN, false>(links + link_block(1, p, mu, vh, RB), vh, i, in, n3, r0, nr, s3, tmp);
-    hop<LP, FP, NIN, true>(links + link_block(1, q, mu, vh, RB), vh, n4, in, n4, r0, nr, s4, tmp);
+    HopBuf<NIN, A> b0, b1;
+    hop_load<LP, FP, NIN, A>(b0, links + link_block(0, p, mu, vh, RB), vh, i, in, n1, r0, nr);
+    hop_load<LP, FP, NIN, A>(b1, links + link_block(0, q, mu, vh, RB), vh, n2, in, n2, r0, nr);
+    hop_apply<NIN, A>(b0, false, s1, nr, tmp);
+    hop_load<LP, FP, NIN, A>(b0, links + link_block(1, p, mu, vh, RB), vh, i, in, n3, r0, nr);
+    hop_apply<NIN, A>(b1, true, s2, nr, tmp);
+    hop_load<LP, FP, NIN, A>(b1, links + link_block(1, q, mu, vh, RB), vh, n4, in, n4, r0, nr);
+    hop_apply<NIN, A>(b0, false, s3, nr, tmp);
+    hop_apply<NIN, A>(b1, true, s4, nr, tmp);
     const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
     const A eta = (par & 1) ? (A)-1 : (A)1;
 #pragma unroll
@@ -155,12 +171,6 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
             acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
         }
 }
-
-// Registers of one hop: the link and the NIN neighbour vectors.
-template <int NIN, typename A> struct HopBuf {
-    A m[18];
-    cplx<A> v[NIN][3];
-};
 
 // Address of hop k (k = 4 mu + {0: +1, 1: -1, 2: +3, 3: -3}) of site s.
 struct HopAddr {
@@ -221,28 +231,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         const int cur = k & 1;
         if (k + 1 < 16)
             load(k + 1, cur ^ 1);
-        const HopBuf<NIN, A> &b = buf[cur];
-        const A sg = sgn[cur];
-#pragma unroll
-        for (int r = 0; r < NIN; ++r) {
-            if (r < nr) {
-                cplx<A> v[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    v[c].re = b.v[r][c].re * sg;
-                    v[c].im = b.v[r][c].im * sg;
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        if (!back[cur])
-                            cmac(tmp[r][a], b.m[6 * a + 2 * c], b.m[6 * a + 2 * c + 1], v[c]);
-                        else
-                            cmac_conj(tmp[r][a], -b.m[6 * c + 2 * a], -b.m[6 * c + 2 * a + 1], v[c]);
-                    }
-            }
-        }
+        hop_apply<NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp);
         if ((k & 3) == 3) {
             const int mu = k >> 2;
             const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);

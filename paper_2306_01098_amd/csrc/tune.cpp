@@ -31,12 +31,14 @@ DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     return s;
 }
 
-std::vector<DslashShape> candidate_shapes(int nrhs) {
+std::vector<DslashShape> candidate_shapes(int nrhs, int lp) {
     std::vector<DslashShape> out;
     for (int var : {VAR_SITE, VAR_DIR})
         for (int nin : {1, 2, 4, 8}) {
             if (nin > 1 && nin > nrhs)
                 continue;
+            if (var == VAR_SITE && lp == HISQ_FP64 && nin > 4)
+                continue;  // exceeds the register file (spills)
             for (int block : {64, 128, 256})
                 for (int remap : {0, 1})
                     out.push_back(DslashShape{var, nin, block, remap});
@@ -91,7 +93,7 @@ hisq_status tune_dslash(hisq_context *ctx, const Geom &g, int lp, int fp, int nr
     DslashShape best = default_shape(g, lp, fp, nrhs);
     float best_ms = 1e30f;
     hisq_status status = HISQ_OK;
-    for (const DslashShape &s : candidate_shapes(nrhs)) {
+    for (const DslashShape &s : candidate_shapes(nrhs, lp)) {
         hipError_t err = hipSuccess;
         const float ms = time_shape(prm, lp, fp, s, st, 5, e0, e1, &err);
         if (err != hipSuccess) {
