@@ -237,7 +237,7 @@ def leg_w5(h, gen, O, torch, ntrain=256, ntest=4, epochs=12):
     for ep in range(epochs):
         for k in range(0, ntrain, 16):
             step += 1
-            losses.append(h.hisq_ptc_train_step(lat, l32, master, w32, mom, var, step, 16,
+            losses.append(h.hisq_ptc_train_step(lat, m, l32, master, w32, mom, var, step, 16,
                                                 src32[k * fb32:(k + 16) * fb32], sol64[k * fb64:(k + 16) * fb64],
                                                 wsp, lr=3e-3))
         log(f"w5: epoch {ep + 1}/{epochs} loss {losses[-1]:.4f}")

@@ -257,14 +257,18 @@ hisq_status hisq_ptc_backward(hisq_context *ctx, const hisq_lattice *lat, const 
  * [HISQ_PTC_NWEIGHTS]); also refreshes the FP32 copy w_f32.  Asynchronous. */
 hisq_status hisq_ptc_adam_step(hisq_context *ctx, void *w_master, void *w_f32, const void *grad, void *m, void *v,
                                int32_t step, double lr, double beta1, double beta2, double eps, void *stream);
-/* One training step on `batch` pairs: loss L = (1/B) sum_i ||N(b_i) - x_i||^2 /
- * ||x_i||^2 with src_f32 = packed FP32 sources [batch] and sol_f64 = packed
- * FP64 solutions [batch]; gradients by hisq_ptc_backward, then one Adam step.
- * *loss (host) receives L before the update.  Synchronous. */
-hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, const void *links_f32, void *w_master,
-                                void *w_f32, void *m, void *v, int32_t step, int32_t batch, const void *src_f32,
-                                const void *sol_f64, double lr, double beta1, double beta2, double eps,
-                                double *loss, void *ws, size_t ws_bytes, void *stream);
+/* One training step on `batch` (source, solution) pairs of M_e x_i = b_i
+ * (src_f32: packed FP32 sources [batch]; sol_f64: packed FP64 solutions
+ * [batch], e.g. from hisq_cg).  Loss: the error of the network's
+ * approximation in the energy norm that CG minimises,
+ *   L = (1/B) sum_i <e_i, M_e e_i> / <x_i, b_i>,   e_i = N(b_i) - x_i,
+ * with M_e applied in FP32 (mass, FP32 links); gradients by the backward pass
+ * of hisq_ptc_backward, then one Adam step.  *loss (host) receives L before
+ * the update.  Synchronous. */
+hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f32,
+                                void *w_master, void *w_f32, void *m, void *v, int32_t step, int32_t batch,
+                                const void *src_f32, const void *sol_f64, double lr, double beta1, double beta2,
+                                double eps, double *loss, void *ws, size_t ws_bytes, void *stream);
 
 /* Workspace of hisq_fcg. */
 size_t hisq_fcg_workspace_bytes(const hisq_lattice *lat);
@@ -272,8 +276,8 @@ size_t hisq_fcg_workspace_bytes(const hisq_lattice *lat);
  * the preconditioner: alpha = <p, r> / <p, A p>, p <- z - (<A p, z> / <p, A p>) p.
  * FP32 links and iteration vectors, FP64 x, FP64 inner products; when the
  * iterated residual falls by 10x or meets the target, the FP64 true residual
- * replaces r and the recurrence restarts from z = N(r).  Stops on the FP64
- * true residual <= tol ||b||.  b, x: packed HISQ_FP64 even fields; x holds the
+ * replaces r and the recurrence continues from it.  Stops on the FP64 true
+ * residual <= tol ||b||.  b, x: packed HISQ_FP64 even fields; x holds the
  * initial guess.  Statuses as for hisq_cg.  Synchronous. */
 hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
                      const void *links_f32, const void *weights, const void *b, void *x, double tol,

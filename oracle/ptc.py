@@ -160,17 +160,24 @@ def network_backward(dims, t_bc, X, ws, acts, g_out_even):
     return gws, restrict_even(dims, g)
 
 
-def loss_and_grad(dims, t_bc, X, ws, srcs, sols):
-    """L = (1/B) sum_i ||N(b_i) - x_i||^2 / ||x_i||^2 and its weight gradients."""
+def loss_and_grad(dims, t_bc, X, ws, srcs, sols, apply_A):
+    """L = (1/B) sum_i <e_i, A e_i> / <x_i, b_i>,  e_i = N(b_i) - x_i.
+
+    The error of the network's approximation to x_i = A^-1 b_i measured in the
+    A (energy) norm that CG minimises, relative to the energy norm of x_i
+    (<x, A x> = <x, b>).  apply_A is the even-site operator M_e.  Returns the
+    loss and the weight gradients dL/dRe w + i dL/dIm w.
+    """
     B = len(srcs)
     total = 0.0
     gsum = [np.zeros_like(w) for w in ws]
     for b, x in zip(srcs, sols):
         y, acts = network_forward(dims, t_bc, X, ws, b)
-        d = y - x
-        nx2 = np.vdot(x.ravel(), x.ravel()).real
-        total += np.vdot(d.ravel(), d.ravel()).real / nx2
-        gws, _ = network_backward(dims, t_bc, X, ws, acts, 2.0 * d / nx2 / B)
+        e = y - x
+        Ae = apply_A(e)
+        c = np.vdot(x.ravel(), b.ravel()).real
+        total += np.vdot(e.ravel(), Ae.ravel()).real / c
+        gws, _ = network_backward(dims, t_bc, X, ws, acts, 2.0 * Ae / c / B)
         for k in range(len(ws)):
             gsum[k] += gws[k]
     return total / B, gsum

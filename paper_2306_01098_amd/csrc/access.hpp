@@ -10,12 +10,21 @@ namespace hisq {
 // ---------------------------------------------------------------------------
 template <int LP> struct LinkIO;
 
+// Every link is read exactly once per Dslash application, so FP64 and FP32
+// link loads carry the non-temporal hint: they stream through the caches
+// without displacing the neighbour vectors, which are reused up to 16 times.
+// (Measured on MI355X at 32^3x8: ~2 % faster for FP64 and FP32; binary16
+// links are faster with ordinary loads.)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
 template <> struct LinkIO<HISQ_FP64> {
     using A = double;
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const double2 v = reinterpret_cast<const double2 *>(blk + (size_t)vh * 16 * k)[i];
+            const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
             m[2 * k] = v.x;
             m[2 * k + 1] = v.y;
         }
@@ -27,13 +36,13 @@ template <> struct LinkIO<HISQ_FP32> {
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float4 v = reinterpret_cast<const float4 *>(blk + (size_t)vh * 16 * k)[i];
+            const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
             m[4 * k] = v.x;
             m[4 * k + 1] = v.y;
             m[4 * k + 2] = v.z;
             m[4 * k + 3] = v.w;
         }
-        const float2 t = reinterpret_cast<const float2 *>(blk + (size_t)vh * 64)[i];
+        const nt_f2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(blk + (size_t)vh * 64) + i);
         m[16] = t.x;
         m[17] = t.y;
     }

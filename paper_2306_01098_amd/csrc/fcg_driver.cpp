@@ -1,7 +1,7 @@
 // Host driver of flexible CG (Notay's FCG with one-vector truncation) with
 // the PTC network as preconditioner: FP32 iteration vectors and links, FP64
-// solution, FP64 inner products and FP64 reliable updates (a restart of the
-// recurrence from the true residual).
+// solution, FP64 inner products and FP64 reliable updates (residual
+// replacement by the FP64 true residual, the recurrence continuing from it).
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -148,7 +148,7 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
     hs.rho = rtrue2;
     hs.rmax2 = rtrue2;
     hs.target2 = tol * tol * bnorm2;
-    hs.delta2 = 0.01;  // reliable update when the residual fell by 10x
+    hs.delta2 = 0.01;  // replace r by the true residual when it fell by 10x
     hs.max_iter = max_iter;
     int reliable = 0;
     bool done = !(rtrue2 > hs.target2);
@@ -201,7 +201,7 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
             }
             if (hs.flag == FLAG_MAXIT)
                 break;
-            // CONV or RELIABLE: FP64 true residual, then finish or restart
+            // CONV or RELIABLE: FP64 true residual, then finish or go on
             if ((s = true_residual(&rtrue2)) != HISQ_OK)
                 return s;
             if (!std::isfinite(rtrue2)) {
@@ -214,18 +214,17 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
             }
             if (hs.iters >= max_iter)
                 break;
+            // residual replacement: r now holds the FP64 b - A x; the
+            // recurrence goes on from it (q and <p, A p> of this iteration
+            // are kept), as in reliable-update CG
             ++reliable;
             hs.rho = rtrue2;
             hs.rmax2 = rtrue2;
             hs.active = 1;
             hs.flag = FLAG_RUN;
-            if ((s = precondition()) != HISQ_OK)
-                return s;
-            e = launch_copy(g.vh, 1, HISQ_FP32, HISQ_FP32, z, p, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st);
             if (e != hipSuccess)
-                return device_fail(e, "fcg restart");
-            continue;
+                return device_fail(e, "fcg replacement");
         }
         // z = N(r); p = z - (<q, z> / <p, q>) p
         if ((s = precondition()) != HISQ_OK)

@@ -258,18 +258,21 @@ __global__ void extract_kernel(int vh, const void *a3, void *out_even) {
     FieldIO<HISQ_FP32>::template store<float>(out_even, vh, 0, i, v);
 }
 
-__global__ void __launch_bounds__(PB) norm2_even_kernel(int vh, const void *x64, double *partials,
-                                                        unsigned *counter, double *out) {
+// *out = Re <x, b> for the FP64 solution x and FP32 source b (even sites).
+__global__ void __launch_bounds__(PB) xb_kernel(int vh, const void *x64, const void *b32, double *partials,
+                                                unsigned *counter, double *out) {
     __shared__ double lds[4];
     __shared__ int last_flag;
     const int i = blockIdx.x * PB + threadIdx.x;
     double part[1] = {0.0};
     if (i < vh) {
-        cplx<double> v[3];
-        FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, v);
+        cplx<double> x[3];
+        cplx<float> b[3];
+        FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
+        FieldIO<HISQ_FP32>::template load<float>(b32, vh, 0, i, b);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            part[0] += v[a].re * v[a].re + v[a].im * v[a].im;
+            part[0] += x[a].re * (double)b[a].re + x[a].im * (double)b[a].im;
     }
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
@@ -278,49 +281,52 @@ __global__ void __launch_bounds__(PB) norm2_even_kernel(int vh, const void *x64,
         sum_partials_block(partials, 1, gridDim.x, out);
 }
 
-// g3 = (2 / (B ||x||^2)) (y - x) on even sites, 0 on odd sites;
-// *loss_acc += ||y - x||^2 / (B ||x||^2).
-__global__ void __launch_bounds__(PB) loss_kernel(int vh, const void *a3, const void *x64, const double *xnorm2,
-                                                  double inv_batch, void *g3, double *partials,
-                                                  unsigned *counter, double *loss_acc) {
-    __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot;
+// e = y - x on even sites (y: network output, channel 0 of a3; x: FP64).
+__global__ void __launch_bounds__(PB) diff_kernel(int vh, const void *a3, const void *x64, void *e) {
+    const int i = blockIdx.x * PB + threadIdx.x;
+    if (i >= vh)
+        return;
+    cplx<float> y[3], d[3];
+    cplx<double> x[3];
+    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, y);
+    FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d[a].re = (float)((double)y[a].re - x[a].re);
+        d[a].im = (float)((double)y[a].im - x[a].im);
+    }
+    FieldIO<HISQ_FP32>::template store<float>(e, vh, 0, i, d);
+}
+
+// Output gradient of L_i = <e, A e> / c (c = <x, b>), scaled by 1/B:
+// g3 = 2 A e / (B c) on even sites, 0 on odd sites; *loss_acc += <e, A e> / (B c).
+__global__ void __launch_bounds__(PB) energy_grad_kernel(int vh, const void *Ae, const double *eAe,
+                                                         const double *c, double inv_batch, void *g3,
+                                                         double *loss_acc) {
     const int gid = blockIdx.x * PB + threadIdx.x;
-    const double xn = *xnorm2;
-    const double coef = 2.0 * inv_batch / xn;
-    double part[1] = {0.0};
-    if (gid < 2 * vh) {
-        const int par = gid >= vh;
-        const int i = gid - par * vh;
-        cplx<float> gv[3];
-        if (par == 0) {
-            cplx<float> y[3];
-            cplx<double> x[3];
-            FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, y);
-            FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
+    const double cc = *c;
+    if (gid == 0)
+        *loss_acc += *eAe * inv_batch / cc;
+    if (gid >= 2 * vh)
+        return;
+    const int par = gid >= vh;
+    const int i = gid - par * vh;
+    cplx<float> gv[3];
+    if (par == 0) {
+        cplx<float> v[3];
+        FieldIO<HISQ_FP32>::template load<float>(Ae, vh, 0, i, v);
+        const float coef = (float)(2.0 * inv_batch / cc);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double dr = (double)y[a].re - x[a].re, di = (double)y[a].im - x[a].im;
-                part[0] += dr * dr + di * di;
-                gv[a].re = (float)(coef * dr);
-                gv[a].im = (float)(coef * di);
-            }
-        } else {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                gv[a].re = gv[a].im = 0.f;
+        for (int a = 0; a < 3; ++a) {
+            gv[a].re = coef * v[a].re;
+            gv[a].im = coef * v[a].im;
         }
-        FieldIO<HISQ_FP32>::template store<float>(g3, vh, par, i, gv);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            gv[a].re = gv[a].im = 0.f;
     }
-    block_sum<1>(part, lds);
-    if (threadIdx.x == 0)
-        partials[blockIdx.x] = part[0];
-    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag)) {
-        sum_partials_block(partials, 1, gridDim.x, &tot);
-        if (threadIdx.x == 0)
-            *loss_acc += tot * inv_batch / xn;
-    }
+    FieldIO<HISQ_FP32>::template store<float>(g3, vh, par, i, gv);
 }
 
 // Adam on real and imaginary parts as separate parameters; FP64 master
@@ -414,16 +420,20 @@ hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, 
     return hipGetLastError();
 }
 
-hipError_t ptc_norm2_even(const Geom &g, const void *x64, double *partials, unsigned *counter, double *out,
-                          hipStream_t st) {
-    norm2_even_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, x64, partials, counter, out);
+hipError_t ptc_xb(const Geom &g, const void *x64, const void *b32, double *partials, unsigned *counter,
+                  double *out, hipStream_t st) {
+    xb_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, x64, b32, partials, counter, out);
     return hipGetLastError();
 }
 
-hipError_t ptc_loss(const Geom &g, const void *a3, const void *x64, const double *xnorm2, double inv_batch,
-                    void *g3, double *partials, unsigned *counter, double *loss_acc, hipStream_t st) {
-    loss_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, a3, x64, xnorm2, inv_batch, g3, partials, counter,
-                                                      loss_acc);
+hipError_t ptc_diff(const Geom &g, const void *a3, const void *x64, void *e, hipStream_t st) {
+    diff_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, a3, x64, e);
+    return hipGetLastError();
+}
+
+hipError_t ptc_energy_grad(const Geom &g, const void *Ae, const double *eAe, const double *c, double inv_batch,
+                           void *g3, double *loss_acc, hipStream_t st) {
+    energy_grad_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, Ae, eAe, c, inv_batch, g3, loss_acc);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "api_util.hpp"
+#include "dslash.hpp"
 #include "ptc.hpp"
 
 namespace hisq {
@@ -13,7 +14,7 @@ namespace {
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PtcLayout {
-    size_t a0, a1, a2, a3, g3, g2, g1, g0, partials, grad, scal, total;
+    size_t a0, a1, a2, a3, g3, g2, g1, g0, partials, grad, scal, e, t, ae, total;
 };
 
 PtcLayout ptc_layout(const Geom &g) {
@@ -37,6 +38,10 @@ PtcLayout ptc_layout(const Geom &g) {
     L.partials = take(sizeof(double) * per_block * ptc_blocks(g));
     L.grad = take(sizeof(double2) * PTC_NW);
     L.scal = take(sizeof(double) * 64);
+    const size_t h32 = field_bytes(g, HISQ_FP32, 1);
+    L.e = take(h32);
+    L.t = take(h32);
+    L.ae = take(h32);
     L.total = off;
     return L;
 }
@@ -183,34 +188,60 @@ hisq_status hisq_ptc_adam_step(hisq_context *ctx, void *w_master, void *w_f32, c
     return e == hipSuccess ? HISQ_OK : device_fail(e, "ptc adam");
 }
 
-hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, const void *links_f32, void *w_master,
-                                void *w_f32, void *m, void *v, int32_t step, int32_t batch, const void *src_f32,
-                                const void *sol_f64, double lr, double beta1, double beta2, double eps,
-                                double *loss, void *ws, size_t ws_bytes, void *stream) {
+hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f32,
+                                void *w_master, void *w_f32, void *m, void *v, int32_t step, int32_t batch,
+                                const void *src_f32, const void *sol_f64, double lr, double beta1, double beta2,
+                                double eps, double *loss, void *ws, size_t ws_bytes, void *stream) {
     Ptc P;
     hisq_status s = common_checks(lat, links_f32, w_f32, ws, ws_bytes, &P, ctx, stream);
     if (s == HISQ_OK) s = check_ptr(src_f32, "src_f32");
     if (s == HISQ_OK) s = check_ptr(sol_f64, "sol_f64");
     if (s == HISQ_OK && batch < 1)
         s = fail(HISQ_ERR_INVALID_ARG, "batch = %d must be >= 1", batch);
+    if (s == HISQ_OK && (!std::isfinite(mass) || mass * mass <= 0.0))
+        s = fail(HISQ_ERR_INVALID_ARG, "mass^2 must be positive (mass = %g)", mass);
     if (s != HISQ_OK)
         return s;
     const float2 *w = static_cast<const float2 *>(w_f32);
     double2 *grad = P.at<double2>(P.L.grad);
-    double *scal = P.at<double>(P.L.scal);  // [0] ||x||^2, [1] loss
+    double *scal = P.at<double>(P.L.scal);  // [0] <x, b>, [1] loss, [2] <e, A e>
     unsigned *counter = reinterpret_cast<unsigned *>(scal + 8);
+    unsigned *counter2 = counter + 1;
     const size_t c32 = field_bytes(P.g, HISQ_FP32, 1), c64 = field_bytes(P.g, HISQ_FP64, 1);
+    const DslashShape shape = pick_shape(ctx, P.g, HISQ_FP32, HISQ_FP32, 1);
     hipError_t e = ptc_fill_f64(reinterpret_cast<double *>(grad), 2 * PTC_NW, P.st);
-    if (e == hipSuccess) e = ptc_fill_f64(scal, 16, P.st);  // also zeroes the counter
+    if (e == hipSuccess) e = ptc_fill_f64(scal, 16, P.st);  // also zeroes the counters
     for (int k = 0; k < batch && e == hipSuccess; ++k) {
         const char *src = static_cast<const char *>(src_f32) + k * c32;
         const char *sol = static_cast<const char *>(sol_f64) + k * c64;
         e = forward(P, w, src, nullptr);
         if (e == hipSuccess)
-            e = ptc_norm2_even(P.g, sol, P.at<double>(P.L.partials), counter, scal + 0, P.st);
+            e = ptc_xb(P.g, sol, src, P.at<double>(P.L.partials), counter, scal + 0, P.st);
         if (e == hipSuccess)
-            e = ptc_loss(P.g, P.at<void>(P.L.a3), sol, scal + 0, 1.0 / batch, P.at<void>(P.L.g3),
-                         P.at<double>(P.L.partials), counter, scal + 1, P.st);
+            e = ptc_diff(P.g, P.at<void>(P.L.a3), sol, P.at<void>(P.L.e), P.st);
+        // A e = m^2 e - D_eo D_oe e (FP32 links) with <e, A e>
+        DslashParams prm{};
+        prm.g = P.g;
+        prm.nrhs = 1;
+        prm.links = P.links;
+        prm.out_parity = 1;
+        prm.in = P.at<void>(P.L.e);
+        prm.out = P.at<void>(P.L.t);
+        if (e == hipSuccess) e = launch_dslash(prm, HISQ_FP32, HISQ_FP32, EPI_PLAIN, shape, P.st);
+        prm.out_parity = 0;
+        prm.in = P.at<void>(P.L.t);
+        prm.out = P.at<void>(P.L.ae);
+        prm.y = P.at<void>(P.L.e);
+        prm.ad = -1.0;
+        prm.ay = mass * mass;
+        prm.partials = P.at<double>(P.L.partials);
+        prm.counter = counter2;
+        prm.dot_out = scal + 2;
+        prm.dot_stride = 1;
+        if (e == hipSuccess) e = launch_dslash(prm, HISQ_FP32, HISQ_FP32, EPI_AXPY_DOT, shape, P.st);
+        if (e == hipSuccess)
+            e = ptc_energy_grad(P.g, P.at<void>(P.L.ae), scal + 2, scal + 0, 1.0 / batch, P.at<void>(P.L.g3),
+                                scal + 1, P.st);
         if (e == hipSuccess)
             e = backward(P, w, grad, nullptr);
     }

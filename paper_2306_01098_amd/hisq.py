@@ -98,7 +98,8 @@ _SIGS = {
     "hisq_ptc_backward": (ctypes.c_int, [_vp, _LAT, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_ptc_adam_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
-    "hisq_ptc_train_step": (ctypes.c_int, [_vp, _LAT, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+    "hisq_ptc_train_step": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                           ctypes.c_int32,
                                            _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_double), _vp,
                                            ctypes.c_size_t, _vp]),
@@ -409,11 +410,11 @@ def hisq_ptc_adam_step(w_master, w_f32, grad, m, v, step, lr=1e-3, beta1=0.9, be
                                      float(beta2), float(eps), _stream(stream)), "hisq_ptc_adam_step")
 
 
-def hisq_ptc_train_step(lat, links_f32, w_master, w_f32, m, v, step, batch, src_f32, sol_f64, ws,
+def hisq_ptc_train_step(lat, mass, links_f32, w_master, w_f32, m, v, step, batch, src_f32, sol_f64, ws,
                         lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, ctx=None, stream=None) -> float:
     n16 = HISQ_PTC_NWEIGHTS * 16
     loss = ctypes.c_double()
-    _check(load().hisq_ptc_train_step(_ctx(ctx), ctypes.byref(lat),
+    _check(load().hisq_ptc_train_step(_ctx(ctx), ctypes.byref(lat), float(mass),
                                       _ptr(links_f32, "links_f32", hisq_links_bytes(lat, "fp32")),
                                       _ptr(w_master, "w_master", n16), _ptr(w_f32, "w_f32", HISQ_PTC_NWEIGHTS * 8),
                                       _ptr(m, "m", n16), _ptr(v, "v", n16), int(step), int(batch),

@@ -71,7 +71,9 @@ def test_weight_gradient_finite_differences(field):
     ws = ptc.init_weights(rng, scale=0.5)
     srcs = gen.gaussian_half_field(gen.rng_for(31, 50), DIMS, 2)
     sols = gen.gaussian_half_field(gen.rng_for(31, 51), DIMS, 2)
-    L0, gs = ptc.loss_and_grad(DIMS, -1, X, ws, srcs, sols)
+    lat = O.lattice_from(field)
+    A = lambda v: lat.M_e(0.3, v)  # noqa: E731
+    L0, gs = ptc.loss_and_grad(DIMS, -1, X, ws, srcs, sols, A)
     h = 1e-6
     for li, (co, ci, p) in [(0, (3, 0, 2)), (1, (5, 2, 7)), (1, (0, 0, 0)), (2, (0, 6, 8))]:
         for part, unit in (("re", 1.0), ("im", 1j)):
@@ -79,8 +81,8 @@ def test_weight_gradient_finite_differences(field):
             wm = [w.copy() for w in ws]
             wp[li][co, ci, p] += h * unit
             wm[li][co, ci, p] -= h * unit
-            Lp, _ = ptc.loss_and_grad(DIMS, -1, X, wp, srcs, sols)
-            Lm, _ = ptc.loss_and_grad(DIMS, -1, X, wm, srcs, sols)
+            Lp, _ = ptc.loss_and_grad(DIMS, -1, X, wp, srcs, sols, A)
+            Lm, _ = ptc.loss_and_grad(DIMS, -1, X, wm, srcs, sols, A)
             fd = (Lp - Lm) / (2 * h)
             an = gs[li][co, ci, p].real if part == "re" else gs[li][co, ci, p].imag
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (li, co, ci, p, part, fd, an)
@@ -112,3 +114,17 @@ def test_fcg_identity_preconditioner_is_cg(field):
     ref = O.cg(lat, 0.1, b, 1e-10, 1000)
     assert st == O.OK and tr <= 1e-10
     assert abs(it - ref.iterations) <= 1
+
+
+def test_energy_loss_zero_at_exact_inverse_pairs(field):
+    """L = 0 when the network output equals x; L = 1 when it outputs zero."""
+    lat = O.lattice_from(field)
+    A = lambda v: lat.M_e(0.3, v)  # noqa: E731
+    x = gen.gaussian_half_field(gen.rng_for(31, 52), DIMS, 1)
+    b = np.stack([A(x[0])])
+    zero = [np.zeros_like(w) for w in ptc.identity_weights()]
+    L, _ = ptc.loss_and_grad(DIMS, -1, field["fat"], zero, b, x, A)
+    assert abs(L - 1.0) < 1e-12
+    # identity network on b = x (A = identity-like check): e = b - x = 0
+    L2, _ = ptc.loss_and_grad(DIMS, -1, field["fat"], ptc.identity_weights(), x, x, A)
+    assert L2 == 0.0
