@@ -3,8 +3,9 @@
 // One launch covers the sites of every problem: a work list maps each block
 // to (problem, first site), so 64 small solves advance together with four
 // launches per iteration instead of 256, and the sequence is captured once in
-// a HIP graph.  Per-problem Krylov scalars live on the device; the last block
-// of each reducing kernel advances them for all problems in a fixed order.
+// a HIP graph.  Per-problem Krylov scalars live on the device; each reducing
+// kernel stores block partials and a one-block finalize kernel sums them per
+// problem in a fixed order and advances the scalars.
 #include "batch.hpp"
 #include "dslash.hpp"
 #include "reduce.hpp"
@@ -14,6 +15,7 @@ namespace hisq {
 namespace {
 
 constexpr int BB = BATCH_BLOCK;
+enum { FIN_PQ = 0, FIN_XR, FIN_RESID, FIN_BNORM };
 
 template <int FP> struct SloppyT;
 template <> struct SloppyT<HISQ_FP64> { using T = double; };
@@ -26,19 +28,17 @@ __device__ __forceinline__ bool participates(const BatchArgs &a, int j, int role
     return role <= ROLE_ITER_DEO ? a.st[j].active != 0 : a.mask[j] != 0;
 }
 
-// Per-problem totals of block partials (blocks of a problem are contiguous).
+// Per-problem totals of block partials (blocks of a problem are contiguous),
+// one wave per problem (deterministic, see wave_sum_slot).
 __device__ void batch_totals(const BatchArgs &a, double *tot /* shared [MAX_BATCH] */) {
-    __shared__ double lds[4];
-    for (int j = 0; j < a.nprob; ++j) {
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wave; j < a.nprob; j += nw) {
         const BatchProb &P = a.probs[j];
-        double v[1] = {0.0};
-        for (int b = threadIdx.x; b < P.nblk; b += blockDim.x)
-            v[0] += __builtin_nontemporal_load(a.partials + P.first_blk + b);
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0)
-            tot[j] = v[0];
-        __syncthreads();
+        const double v = wave_sum_slot(a.partials + P.first_blk, P.nblk);
+        if ((threadIdx.x & 63) == 0)
+            tot[j] = v;
     }
+    __syncthreads();
 }
 
 // Dslash over all participating problems.
@@ -85,24 +85,13 @@ __global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
     }
     if (!DOT)
         return;
-    __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot[MAX_BATCH];
+    __shared__ double lds[2];
     block_sum<1>(dot, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = dot[0];
-    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
-        return;
-    batch_totals(a, tot);
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-        if (a.st[jj].active)
-            a.st[jj].pq = tot[jj];
 }
 
-// x += alpha p, r -= alpha q, <r, r>; the last block advances every active
-// problem's scalars (and stamps the device clock when a problem's iterated
-// residual meets its target).
+// x += alpha p, r -= alpha q, and block partials of <r, r>.
 template <int FP>
 __global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
@@ -136,16 +125,40 @@ __global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
         FieldIO<HISQ_FP64>::template store<double>(P.x, P.g.vh, 0, i, x);
         FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, r);
     }
-    __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot[MAX_BATCH];
+    __shared__ double lds[2];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
-    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
+}
+
+// Finalize of the reducing batch kernels (one block).
+//  FIN_PQ:    st[j].pq = total for active problems
+//  FIN_XR:    advance every active problem's scalars (and stamp the device
+//             clock when a problem's recurrence stops)
+//  FIN_RESID: st[j].rho_new = total for masked problems
+//  FIN_BNORM: bnorm2[j] = total
+__global__ void __launch_bounds__(1024) batch_finalize_kernel(BatchArgs a, int mode, double *bnorm2) {
+    if ((mode == FIN_PQ || mode == FIN_XR) && *a.skip)
         return;
+    __shared__ double tot[MAX_BATCH];
     batch_totals(a, tot);
-    __syncthreads();
+    if (mode == FIN_PQ) {
+        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+            if (a.st[jj].active)
+                a.st[jj].pq = tot[jj];
+        return;
+    }
+    if (mode == FIN_RESID) {
+        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+            if (a.mask[jj])
+                a.st[jj].rho_new = tot[jj];
+        return;
+    }
+    if (mode == FIN_BNORM) {
+        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
+            bnorm2[jj] = tot[jj];
+        return;
+    }
     if (threadIdx.x != 0)
         return;
     const double now = (double)wall_clock64();
@@ -212,8 +225,8 @@ __global__ void __launch_bounds__(BB) batch_p_kernel(BatchArgs a) {
     FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, p);
 }
 
-// For masked problems: r = b - ax (sloppy copy) and ||b - ax||^2 -> st.rho_new
-// (FP64); with `copy_p` also p = r (start of a solve).
+// For masked problems: r = b - ax (sloppy copy) and block partials of
+// ||b - ax||^2 (FP64); with `copy_p` also p = r (start of a solve).
 template <int FP>
 __global__ void __launch_bounds__(BB) batch_residual_kernel(BatchArgs a, int copy_p) {
     using T = typename SloppyT<FP>::T;
@@ -239,23 +252,14 @@ __global__ void __launch_bounds__(BB) batch_residual_kernel(BatchArgs a, int cop
         if (copy_p)
             FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, rv);
     }
-    __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot[MAX_BATCH];
+    __shared__ double lds[2];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
-    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
-        return;
-    batch_totals(a, tot);
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-        if (a.mask[jj])
-            a.st[jj].rho_new = tot[jj];
 }
 
-// ||b||^2 of every problem -> st.rmax2 (used once, before the solve).
-__global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a, double *bnorm2) {
+// Block partials of ||b||^2 of every problem (used once, before the solve).
+__global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a) {
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
@@ -270,18 +274,10 @@ __global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a, double *bn
             part[0] = fma(bv[c].im, bv[c].im, part[0]);
         }
     }
-    __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot[MAX_BATCH];
+    __shared__ double lds[2];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
-    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, a.counter, gridDim.x, &last_flag))
-        return;
-    batch_totals(a, tot);
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-        bnorm2[jj] = tot[jj];
 }
 
 __global__ void batch_clock_kernel(double *out) {
@@ -325,11 +321,23 @@ hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStre
     }
     default: return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int fin = op == BOP_ITER_DEO ? FIN_PQ : op == BOP_XR ? FIN_XR
+                    : (op == BOP_RESIDUAL || op == BOP_RESIDUAL_COPY_P) ? FIN_RESID : -1;
+    if (fin < 0)
+        return hipSuccess;
+    batch_finalize_kernel<<<1, 1024, 0, st>>>(a, fin, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_bnorm(const BatchArgs &a, int nblocks, double *bnorm2, hipStream_t st) {
-    batch_bnorm_kernel<<<dim3((unsigned)nblocks), BB, 0, st>>>(a, bnorm2);
+    batch_bnorm_kernel<<<dim3((unsigned)nblocks), BB, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    batch_finalize_kernel<<<1, 1024, 0, st>>>(a, FIN_BNORM, bnorm2);
     return hipGetLastError();
 }
 

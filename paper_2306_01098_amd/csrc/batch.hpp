@@ -29,7 +29,6 @@ struct BatchArgs {
     CgScalars *st;        // [nprob]
     const int *mask;      // [nprob] problems taking part in a true-residual pass
     double *partials;     // [nblocks]
-    unsigned *counter;
     int *skip;
 };
 

@@ -64,7 +64,7 @@ double wall_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-enum { BF_SKIP = 0, BF_COUNTER = 8 };
+enum { BF_SKIP = 0 };
 
 }  // namespace
 
@@ -172,7 +172,6 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     a.mask = reinterpret_cast<const int *>(W + L.mask);
     a.partials = reinterpret_cast<double *>(W + L.partials);
     unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
-    a.counter = flags + BF_COUNTER;
     a.skip = reinterpret_cast<int *>(flags + BF_SKIP);
     double *scal = reinterpret_cast<double *>(W + L.scal);  // [0..n) ||b||^2, [MAX_BATCH] start clock
     int *mask_d = reinterpret_cast<int *>(W + L.mask);

@@ -1,7 +1,7 @@
 // Vector kernels of the CG family: fused solution/residual updates with the
 // residual norm, direction updates, true-residual formation, norms, copies.
-// Reductions are FP64 and deterministic (see reduce.hpp); the Krylov scalars
-// are advanced in FP64 by the last block of the reducing kernel.
+// Reductions are FP64 and deterministic (block partials, then a one-block
+// finalize); the Krylov scalars are advanced in FP64 by the finalize kernel.
 #include "internal.hpp"
 #include "reduce.hpp"
 #include "solver.hpp"
@@ -18,17 +18,14 @@ template <> struct Sloppy<HISQ_FP32> { using T = float; };
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e308; }
 
-// x += alpha p (FP64 x), r -= alpha q, and <r, r> for right-hand side
-// blockIdx.y; multi-shift: x_k += alpha_k p_k.  The last block advances the
-// scalars: breakdown check, rho, beta, convergence / reliable-update /
-// iteration-limit flags, and the multi-shift zeta recurrences.
+// x += alpha p (FP64 x), r -= alpha q, and the block partials of <r, r> for
+// right-hand side blockIdx.y; multi-shift: x_k += alpha_k p_k.
 template <int FP>
 __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
     using T = typename Sloppy<FP>::T;
     if (*prm.skip)
         return;
     __shared__ double lds[4];
-    __shared__ int last_flag;
     const int rr = blockIdx.y;
     const int i = blockIdx.x * BLK + threadIdx.x;
     const CgScalars st = prm.st[rr];
@@ -79,16 +76,19 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
         }
     }
     block_sum<1>(part, lds);
-    const int nblk = gridDim.x;
     if (threadIdx.x == 0)
-        prm.partials[(size_t)rr * nblk + blockIdx.x] = part[0];
-    const bool last = publish_and_check_last(nullptr, 0, nullptr, 0, 0, nblk, prm.counter,
-                                             gridDim.x * gridDim.y, &last_flag);
-    if (!last)
+        prm.partials[(size_t)rr * gridDim.x + blockIdx.x] = part[0];
+}
+
+// One block: sums the <r, r> partials of cg_xr_kernel (nblk blocks per
+// right-hand side) and advances the scalars: breakdown check, rho, beta,
+// convergence / reliable-update / iteration-limit flags, and the multi-shift
+// zeta recurrences.
+__global__ void __launch_bounds__(1024) cg_finalize_kernel(CgVecParams prm, int nblk) {
+    if (*prm.skip)
         return;
     __shared__ double tot[HISQ_MAX_RHS];
     sum_partials_block(prm.partials, prm.nrhs, nblk, tot);
-    __syncthreads();
     if (threadIdx.x != 0)
         return;
     int any = 0;
@@ -199,10 +199,9 @@ __global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0) {
 // *out2 = ||b - ax||^2 in FP64 (from the FP64 values).
 template <int FP>
 __global__ void __launch_bounds__(BLK) residual_kernel(int vh, const void *b, const void *ax, void *r,
-                                                       double *partials, unsigned *counter, double *out2) {
+                                                       double *partials) {
     using T = typename Sloppy<FP>::T;
     __shared__ double lds[4];
-    __shared__ int last_flag;
     const int i = blockIdx.x * BLK + threadIdx.x;
     double part[1] = {0.0};
     if (i < vh) {
@@ -223,15 +222,11 @@ __global__ void __launch_bounds__(BLK) residual_kernel(int vh, const void *b, co
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = part[0];
-    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
-        sum_partials_block(partials, 1, gridDim.x, out2);
 }
 
-// *out2 = ||v||^2 of an FP64 field (one column).
-__global__ void __launch_bounds__(BLK) norm2_kernel(int vh, const void *v, double *partials, unsigned *counter,
-                                                    double *out2) {
+// Block partials of ||v||^2 of an FP64 field (one column).
+__global__ void __launch_bounds__(BLK) norm2_kernel(int vh, const void *v, double *partials) {
     __shared__ double lds[4];
-    __shared__ int last_flag;
     const int i = blockIdx.x * BLK + threadIdx.x;
     double part[1] = {0.0};
     if (i < vh) {
@@ -246,8 +241,6 @@ __global__ void __launch_bounds__(BLK) norm2_kernel(int vh, const void *v, doubl
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = part[0];
-    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
-        sum_partials_block(partials, 1, gridDim.x, out2);
 }
 
 // dst = src for n fields, with precision conversion.
@@ -276,10 +269,15 @@ inline dim3 grid_for(int vh, int ny = 1) { return dim3((unsigned)((vh + BLK - 1)
 int blas_blocks(int vh) { return (vh + BLK - 1) / BLK; }
 
 hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st) {
+    const dim3 g = grid_for(p.vh, p.nrhs);
     if (fp == HISQ_FP64)
-        cg_xr_kernel<HISQ_FP64><<<grid_for(p.vh, p.nrhs), BLK, 0, st>>>(p);
+        cg_xr_kernel<HISQ_FP64><<<g, BLK, 0, st>>>(p);
     else
-        cg_xr_kernel<HISQ_FP32><<<grid_for(p.vh, p.nrhs), BLK, 0, st>>>(p);
+        cg_xr_kernel<HISQ_FP32><<<g, BLK, 0, st>>>(p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    cg_finalize_kernel<<<1, 1024, 0, st>>>(p, (int)g.x);
     return hipGetLastError();
 }
 
@@ -292,17 +290,19 @@ hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStre
 }
 
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
-                           unsigned *counter, double *out2, hipStream_t st) {
+                           double *out2, hipStream_t st) {
     if (fp == HISQ_FP64)
-        residual_kernel<HISQ_FP64><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials, counter, out2);
+        residual_kernel<HISQ_FP64><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials);
     else
-        residual_kernel<HISQ_FP32><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials, counter, out2);
-    return hipGetLastError();
+        residual_kernel<HISQ_FP32><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sum_partials(partials, 1, blas_blocks(vh), out2, 1, nullptr, st) : e;
 }
 
-hipError_t launch_norm2(int vh, const void *v, double *partials, unsigned *counter, double *out2, hipStream_t st) {
-    norm2_kernel<<<grid_for(vh), BLK, 0, st>>>(vh, v, partials, counter, out2);
-    return hipGetLastError();
+hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, hipStream_t st) {
+    norm2_kernel<<<grid_for(vh), BLK, 0, st>>>(vh, v, partials);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sum_partials(partials, 1, blas_blocks(vh), out2, 1, nullptr, st) : e;
 }
 
 hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst, hipStream_t st) {

@@ -61,7 +61,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
 }
 
 // flags[] slots
-enum { F_SKIP = 0, F_CNT_DOT = 8, F_CNT_XR = 9, F_CNT_RES = 10, F_CNT_NORM = 11 };
+enum { F_SKIP = 0 };
 // scal[] slots
 enum { S_TMP = 0 };
 
@@ -120,7 +120,7 @@ struct Solver {
 
     // ||v||^2 of an FP64 column.
     hisq_status norm2(const void *v, double *out) {
-        hisq_status s = dev(launch_norm2(g.vh, v, partials(), flags() + F_CNT_NORM, scal() + S_TMP, st), "norm2");
+        hisq_status s = dev(launch_norm2(g.vh, v, partials(), scal() + S_TMP, st), "norm2");
         return s == HISQ_OK ? read_double(scal() + S_TMP, out) : s;
     }
 
@@ -129,8 +129,7 @@ struct Solver {
         hisq_status s = apply_m64(sigma, x, at<void>(L.ax));
         if (s != HISQ_OK)
             return s;
-        s = dev(launch_residual(g.vh, L.fs, b, at<void>(L.ax), r_sloppy, partials(), flags() + F_CNT_RES,
-                                scal() + S_TMP, st),
+        s = dev(launch_residual(g.vh, L.fs, b, at<void>(L.ax), r_sloppy, partials(), scal() + S_TMP, st),
                 "residual");
         return s == HISQ_OK ? read_double(scal() + S_TMP, out2) : s;
     }
@@ -155,7 +154,6 @@ struct Solver {
         prm.ad = -1.0;
         prm.ay = mass * mass + sigma;
         prm.partials = partials();
-        prm.counter = flags() + F_CNT_DOT;
         prm.dot_out = &vp.st[0].pq;
         prm.dot_stride = sizeof(CgScalars) / sizeof(double);
         e = launch_dslash(prm, lp_in, L.fs, EPI_AXPY_DOT, shape_in, st);
@@ -289,14 +287,16 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
     vp.q = S.at<void>(L.q);
     vp.st = dst;
     vp.partials = S.partials();
-    vp.counter = S.flags() + F_CNT_XR;
     vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
     vp.nshift = 0;
 
-    // capture one chunk of iterations
+    // capture one chunk of iterations (only when there is something to iterate)
     GraphChunk gc;
     bool use_graph = false;
-    {
+    bool any_active = false;
+    for (int j = 0; j < nrhs; ++j)
+        any_active |= hs[j].active != 0;
+    if (any_active) {
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             hipError_t le = hipSuccess;
@@ -496,8 +496,7 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
         vp.q = S.at<void>(L.q);
         vp.st = dst;
         vp.partials = S.partials();
-        vp.counter = S.flags() + F_CNT_XR;
-        vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+            vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
         vp.nshift = no;
         vp.sh = dsh;
         vp.ms = dms;

@@ -35,8 +35,7 @@ struct DslashParams {
     double ad, ay;
     const int *skip;     // optional: if *skip != 0 the whole launch does nothing
     double *partials;    // EPI_AXPY_DOT: [nrhs][gridDim.x] block partials
-    unsigned *counter;   // EPI_AXPY_DOT: zero before the first launch; reset by the last block
-    double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride]
+    double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride] (finalize kernel)
     int dot_stride;
 };
 
@@ -270,21 +269,14 @@ __device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i
     return dot;
 }
 
-// Block partials of the NIN dot products, and the last block's totals.
+// Block partials of the NIN dot products (summed by a finalize kernel).
 template <int NIN>
 __device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, double (&dot)[NIN], int r0, int nr) {
     __shared__ double lds[4 * NIN];
-    __shared__ int last_flag;
     block_sum<NIN>(dot, lds);
-    const int nblk = gridDim.x;
-    const int blk = blockIdx.y * nblk + blockIdx.x;
     if (threadIdx.x == 0)
         for (int r = 0; r < nr; ++r)
-            prm.partials[(size_t)(r0 + r) * nblk + blockIdx.x] = dot[r];
-    const bool last = publish_and_check_last(nullptr, 0, nullptr, 0, blk, nblk, prm.counter,
-                                             gridDim.x * gridDim.y, &last_flag);
-    if (last)
-        sum_partials_block(prm.partials, prm.nrhs, nblk, prm.dot_out, prm.dot_stride > 0 ? prm.dot_stride : 1);
+            prm.partials[(size_t)(r0 + r) * gridDim.x + blockIdx.x] = dot[r];
 }
 
 template <int LP, int FP, int NIN, int EPI>

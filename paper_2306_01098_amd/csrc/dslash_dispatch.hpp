@@ -19,7 +19,11 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
         dslash_dir_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
     else
         dslash_site_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && EPI == EPI_AXPY_DOT)
+        e = launch_sum_partials(p.partials, p.nrhs, (int)grid.x, p.dot_out, p.dot_stride > 0 ? p.dot_stride : 1,
+                                p.skip, st);
+    return e;
 }
 
 template <int LP, int FP, int EPI>

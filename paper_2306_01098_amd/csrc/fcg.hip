@@ -1,6 +1,7 @@
 // Vector kernels of flexible CG with a (possibly non-symmetric) preconditioner:
 // complex inner products, and updates with complex alpha, beta.
 #include "fcg.hpp"
+#include "internal.hpp"
 #include "reduce.hpp"
 
 namespace hisq {
@@ -9,12 +10,10 @@ namespace {
 
 constexpr int FB = 256;
 
-// *out = <a, b> = sum conj(a) b of two FP32 even fields, FP64 sums.
-__global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const void *b, double *partials,
-                                                 unsigned *counter, double2 *out) {
+// Block partials of <a, b> = sum conj(a) b of two FP32 even fields (FP64
+// sums): real parts in partials[0 .. nblk), imaginary in [nblk .. 2 nblk).
+__global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const void *b, double *partials) {
     __shared__ double lds[8];
-    __shared__ int last_flag;
-    __shared__ double tot[2];
     const int i = blockIdx.x * FB + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (i < vh) {
@@ -32,21 +31,13 @@ __global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const vo
         partials[blockIdx.x] = v[0];
         partials[gridDim.x + blockIdx.x] = v[1];
     }
-    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag)) {
-        sum_partials_block(partials, 2, gridDim.x, tot);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            *out = make_double2(tot[0], tot[1]);
-    }
 }
 
-// alpha = <p, r> / <p, A p>; x += alpha p (FP64), r -= alpha q, ||r||^2; the
-// last block advances the scalars and raises the flags.
+// alpha = <p, r> / <p, A p>; x += alpha p (FP64), r -= alpha q, and block
+// partials of ||r||^2.
 __global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, const void *q, void *r,
-                                                FcgScalars *s, double *partials, unsigned *counter) {
+                                                const FcgScalars *s, double *partials) {
     __shared__ double lds[4];
-    __shared__ int last_flag;
-    __shared__ double tot;
     const FcgScalars st = *s;
     const bool ok = st.active && st.pq > 0.0 && st.pq < 1e308;
     const double ar = ok ? st.pr.x / st.pq : 0.0, ai = ok ? st.pr.y / st.pq : 0.0;
@@ -72,15 +63,19 @@ __global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, 
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = part[0];
-    if (!publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
-        return;
-    sum_partials_block(partials, 1, gridDim.x, &tot);
-    __syncthreads();
+}
+
+// One block: sums the ||r||^2 partials of xr_kernel, advances the scalars
+// and raises the flags.
+__global__ void __launch_bounds__(FB) xr_finalize_kernel(FcgScalars *s, const double *partials, int nblk) {
+    __shared__ double tot;
+    sum_partials_block(partials, 1, nblk, &tot);
     if (threadIdx.x != 0)
         return;
     FcgScalars n = *s;
     if (!n.active)
         return;
+    const bool ok = n.pq > 0.0 && n.pq < 1e308;
     if (!ok) {
         n.flag = FLAG_BREAKDOWN;
         n.active = 0;
@@ -127,15 +122,22 @@ __global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, c
 
 }  // namespace
 
-hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, unsigned *counter, double2 *out,
-                          hipStream_t st) {
-    dot_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, a, b, partials, counter, out);
-    return hipGetLastError();
+hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, double2 *out, hipStream_t st) {
+    const int nblk = (vh + FB - 1) / FB;
+    dot_kernel<<<nblk, FB, 0, st>>>(vh, a, b, partials);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sum_partials(partials, 2, nblk, reinterpret_cast<double *>(out), 1, nullptr, st)
+                           : e;
 }
 
 hipError_t launch_fcg_xr(int vh, void *x, const void *p, const void *q, void *r, FcgScalars *s, double *partials,
-                         unsigned *counter, hipStream_t st) {
-    xr_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, x, p, q, r, s, partials, counter);
+                         hipStream_t st) {
+    const int nblk = (vh + FB - 1) / FB;
+    xr_kernel<<<nblk, FB, 0, st>>>(vh, x, p, q, r, s, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    xr_finalize_kernel<<<1, FB, 0, st>>>(s, partials, nblk);
     return hipGetLastError();
 }
 

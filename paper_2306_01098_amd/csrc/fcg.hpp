@@ -19,10 +19,9 @@ struct alignas(16) FcgScalars {
     int active, flag, iters, max_iter;
 };
 
-hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, unsigned *counter, double2 *out,
-                          hipStream_t st);
+hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, double2 *out, hipStream_t st);
 hipError_t launch_fcg_xr(int vh, void *x, const void *p, const void *q, void *r, FcgScalars *s, double *partials,
-                         unsigned *counter, hipStream_t st);
+                         hipStream_t st);
 hipError_t launch_fcg_p(int vh, const void *z, void *p, const FcgScalars *s, hipStream_t st);
 
 }  // namespace hisq

@@ -123,7 +123,7 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
             e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, sh64, st);
         }
         if (e == hipSuccess)
-            e = launch_residual(g.vh, HISQ_FP32, b, ax, r, partials, flags + 1, scal + 0, st);
+            e = launch_residual(g.vh, HISQ_FP32, b, ax, r, partials, scal + 0, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(rtrue2, scal + 0, sizeof(double), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
@@ -137,7 +137,7 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
     hipError_t e = launch_fill_u32(flags, 64, 0u, st);
     double bnorm2 = 0.0, rtrue2 = 0.0;
     if (e == hipSuccess)
-        e = launch_norm2(g.vh, b, partials, flags + 2, scal + 1, st);
+        e = launch_norm2(g.vh, b, partials, scal + 1, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&bnorm2, scal + 1, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess)
@@ -184,12 +184,11 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
         pd.ad = -1.0;
         pd.ay = m2;
         pd.partials = partials;
-        pd.counter = flags + 3;
         pd.dot_out = &ds->pq;
         pd.dot_stride = 1;
         if (e == hipSuccess) e = launch_dslash(pd, HISQ_FP32, HISQ_FP32, EPI_AXPY_DOT, sh32, st);
-        if (e == hipSuccess) e = launch_fcg_dot(g.vh, p, r, partials, flags + 4, &ds->pr, st);
-        if (e == hipSuccess) e = launch_fcg_xr(g.vh, x, p, q, r, ds, partials, flags + 5, st);
+        if (e == hipSuccess) e = launch_fcg_dot(g.vh, p, r, partials, &ds->pr, st);
+        if (e == hipSuccess) e = launch_fcg_xr(g.vh, x, p, q, r, ds, partials, st);
         if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess)
@@ -229,7 +228,7 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
         // z = N(r); p = z - (<q, z> / <p, q>) p
         if ((s = precondition()) != HISQ_OK)
             return s;
-        e = launch_fcg_dot(g.vh, q, z, partials, flags + 6, &ds->qz, st);
+        e = launch_fcg_dot(g.vh, q, z, partials, &ds->qz, st);
         if (e == hipSuccess) e = launch_fcg_p(g.vh, z, p, ds, st);
         if (e != hipSuccess)
             return device_fail(e, "fcg direction");

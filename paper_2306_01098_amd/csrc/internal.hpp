@@ -38,8 +38,12 @@ int blas_blocks(int vh);
 hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st);
 hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st);
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
-                           unsigned *counter, double *out2, hipStream_t st);
-hipError_t launch_norm2(int vh, const void *v, double *partials, unsigned *counter, double *out2, hipStream_t st);
+                           double *out2, hipStream_t st);
+hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, hipStream_t st);
+// out[s * stride] = sum over nblk block partials of slot s (one-block kernel);
+// does nothing when skip is non-NULL and *skip != 0.
+hipError_t launch_sum_partials(const double *partials, int nslots, int nblk, double *out, int stride,
+                               const int *skip, hipStream_t st);
 hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t st);
 

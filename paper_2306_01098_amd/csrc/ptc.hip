@@ -2,6 +2,7 @@
 // adjoint transports, weight gradient as a deterministic reduction over all
 // sites), the training loss and Adam.  FP32 fields, FP64 reductions.
 #include "dslash.hpp"
+#include "internal.hpp"
 #include "ptc.hpp"
 #include "reduce.hpp"
 
@@ -258,11 +259,10 @@ __global__ void extract_kernel(int vh, const void *a3, void *out_even) {
     FieldIO<HISQ_FP32>::template store<float>(out_even, vh, 0, i, v);
 }
 
-// *out = Re <x, b> for the FP64 solution x and FP32 source b (even sites).
-__global__ void __launch_bounds__(PB) xb_kernel(int vh, const void *x64, const void *b32, double *partials,
-                                                unsigned *counter, double *out) {
+// Block partials of Re <x, b> for the FP64 solution x and FP32 source b
+// (even sites).
+__global__ void __launch_bounds__(PB) xb_kernel(int vh, const void *x64, const void *b32, double *partials) {
     __shared__ double lds[4];
-    __shared__ int last_flag;
     const int i = blockIdx.x * PB + threadIdx.x;
     double part[1] = {0.0};
     if (i < vh) {
@@ -277,8 +277,6 @@ __global__ void __launch_bounds__(PB) xb_kernel(int vh, const void *x64, const v
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = part[0];
-    if (publish_and_check_last(nullptr, 0, nullptr, 0, 0, gridDim.x, counter, gridDim.x, &last_flag))
-        sum_partials_block(partials, 1, gridDim.x, out);
 }
 
 // e = y - x on even sites (y: network output, channel 0 of a3; x: FP64).
@@ -420,10 +418,10 @@ hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, 
     return hipGetLastError();
 }
 
-hipError_t ptc_xb(const Geom &g, const void *x64, const void *b32, double *partials, unsigned *counter,
-                  double *out, hipStream_t st) {
-    xb_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, x64, b32, partials, counter, out);
-    return hipGetLastError();
+hipError_t ptc_xb(const Geom &g, const void *x64, const void *b32, double *partials, double *out, hipStream_t st) {
+    xb_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, x64, b32, partials);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sum_partials(partials, 1, nb(g.vh), out, 1, nullptr, st) : e;
 }
 
 hipError_t ptc_diff(const Geom &g, const void *a3, const void *x64, void *e, hipStream_t st) {

@@ -32,8 +32,7 @@ hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links,
 hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, const void *in, const void *g_out,
                            double *partials, double2 *grad, hipStream_t st);
 int ptc_blocks(const Geom &g);
-hipError_t ptc_xb(const Geom &g, const void *x64, const void *b32, double *partials, unsigned *counter,
-                  double *out, hipStream_t st);
+hipError_t ptc_xb(const Geom &g, const void *x64, const void *b32, double *partials, double *out, hipStream_t st);
 hipError_t ptc_diff(const Geom &g, const void *a3, const void *x64, void *e, hipStream_t st);
 hipError_t ptc_energy_grad(const Geom &g, const void *Ae, const double *eAe, const double *c, double inv_batch,
                            void *g3, double *loss_acc, hipStream_t st);

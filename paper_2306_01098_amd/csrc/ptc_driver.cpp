@@ -205,18 +205,16 @@ hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, doub
     const float2 *w = static_cast<const float2 *>(w_f32);
     double2 *grad = P.at<double2>(P.L.grad);
     double *scal = P.at<double>(P.L.scal);  // [0] <x, b>, [1] loss, [2] <e, A e>
-    unsigned *counter = reinterpret_cast<unsigned *>(scal + 8);
-    unsigned *counter2 = counter + 1;
     const size_t c32 = field_bytes(P.g, HISQ_FP32, 1), c64 = field_bytes(P.g, HISQ_FP64, 1);
     const DslashShape shape = pick_shape(ctx, P.g, HISQ_FP32, HISQ_FP32, 1);
     hipError_t e = ptc_fill_f64(reinterpret_cast<double *>(grad), 2 * PTC_NW, P.st);
-    if (e == hipSuccess) e = ptc_fill_f64(scal, 16, P.st);  // also zeroes the counters
+    if (e == hipSuccess) e = ptc_fill_f64(scal, 16, P.st);
     for (int k = 0; k < batch && e == hipSuccess; ++k) {
         const char *src = static_cast<const char *>(src_f32) + k * c32;
         const char *sol = static_cast<const char *>(sol_f64) + k * c64;
         e = forward(P, w, src, nullptr);
         if (e == hipSuccess)
-            e = ptc_xb(P.g, sol, src, P.at<double>(P.L.partials), counter, scal + 0, P.st);
+            e = ptc_xb(P.g, sol, src, P.at<double>(P.L.partials), scal + 0, P.st);
         if (e == hipSuccess)
             e = ptc_diff(P.g, P.at<void>(P.L.a3), sol, P.at<void>(P.L.e), P.st);
         // A e = m^2 e - D_eo D_oe e (FP32 links) with <e, A e>
@@ -235,7 +233,6 @@ hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, doub
         prm.ad = -1.0;
         prm.ay = mass * mass;
         prm.partials = P.at<double>(P.L.partials);
-        prm.counter = counter2;
         prm.dot_out = scal + 2;
         prm.dot_stride = 1;
         if (e == hipSuccess) e = launch_dslash(prm, HISQ_FP32, HISQ_FP32, EPI_AXPY_DOT, shape, P.st);

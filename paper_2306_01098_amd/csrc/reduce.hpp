@@ -1,5 +1,8 @@
 // Deterministic grid reductions: wave64 shuffles -> LDS -> one partial per
-// block -> the last block to finish sums the partials in block order.
+// block, stored by the reducing kernel; a one-block finalize kernel launched
+// after it sums the partials in block order.  (A "last block finishes"
+// scheme needs an agent-scope release per block, which on the multi-XCD
+// MI355X writes back the L2 each time and made reducing kernels 3-7x slower.)
 #pragma once
 
 #include "common.hpp"
@@ -33,49 +36,40 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
-// Thread 0 of every block stores its partials (partials[slot * nblk + blk] for
-// slot = slot0 .. slot0+nv-1), then counts the block in *counter.  Returns
-// true, in every thread of the block, iff this block finished last; the
-// counter is then reset to zero for the next launch.  After a true return all
-// partials of all blocks are visible to the block.
-__device__ __forceinline__ bool publish_and_check_last(const double *vals, int nv, double *partials,
-                                                       int slot0, int blk, int nblk,
-                                                       unsigned *counter, unsigned nblocks_total,
-                                                       int *lds_flag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < nv; ++k)
-            partials[(size_t)(slot0 + k) * nblk + blk] = vals[k];
-        const unsigned prev =
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        const int last = prev == nblocks_total - 1;
-        if (last)
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *lds_flag = last;
+// Sum of one slot by one wavefront: lane l adds partials l, l + 64, l + 128,
+// ... in that order (eight loads in flight per step), then the wave adds the
+// lanes in a fixed shuffle tree.  The result is the same whichever wave runs
+// it, so the sum is deterministic.  Returns the total in every lane.
+__device__ __forceinline__ double wave_sum_slot(const double *p, int nblk) {
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    int b = lane;
+    for (; b + 7 * 64 < nblk; b += 8 * 64) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            t[k] = __builtin_nontemporal_load(p + b + k * 64);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            v += t[k];
     }
-    __syncthreads();
-    const bool last = *lds_flag != 0;
-    if (last)
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    return last;
+    for (; b < nblk; b += 64)
+        v += __builtin_nontemporal_load(p + b);
+    return wave_sum(v);
 }
 
-// In the last block (all threads): tot[s] = sum_b partials[s * nblk + b] for
-// s < nslots.  Thread t sums the partials t, t + blockDim, ... in order, then
-// the block sums the threads in a fixed tree: the result is deterministic.
+// In one block (all threads): tot[s * stride] = sum_b partials[s * nblk + b]
+// for s < nslots, slot s summed by wave s mod (blockDim.x / 64).  Ends with a
+// block barrier, so `tot` may be shared memory read by the whole block.
 __device__ __forceinline__ void sum_partials_block(const double *partials, int nslots, int nblk,
                                                    double *tot, int stride = 1) {
-    __shared__ double lds[4];
-    for (int s = 0; s < nslots; ++s) {
-        double v[1] = {0.0};
-        const double *p = partials + (size_t)s * nblk;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-            v[0] += __builtin_nontemporal_load(p + b);
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0)
-            tot[(size_t)s * stride] = v[0];
-        __syncthreads();
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int s = wave; s < nslots; s += nw) {
+        const double v = wave_sum_slot(partials + (size_t)s * nblk, nblk);
+        if ((threadIdx.x & 63) == 0)
+            tot[(size_t)s * stride] = v;
     }
+    __syncthreads();
 }
 
 }  // namespace hisq

@@ -1,8 +1,8 @@
 // Device-resident solver state and the vector kernels of the CG family.
 //
 // All scalars of the Krylov recurrences (rho, <p,Ap>, alpha, beta, the
-// multi-shift zeta's) live in device memory in FP64 and are updated by the
-// last block of the kernel that reduces them, so an iteration needs no host
+// multi-shift zeta's) live in device memory in FP64 and are updated by a
+// one-block finalize kernel after each reduction, so an iteration needs no host
 // round trip; the host reads the state only once per chunk of iterations.
 #pragma once
 
@@ -67,7 +67,6 @@ struct CgVecParams {
     const void *q;      // sloppy A p [nrhs]
     CgScalars *st;      // [nrhs]
     double *partials;   // [nrhs][gridDim.x]
-    unsigned *counter;
     int *skip;          // 1 when no right-hand side is active
     // multi-shift (nshift > 0): per-shift solutions and directions
     int nshift;
