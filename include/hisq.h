@@ -134,6 +134,14 @@ hisq_status hisq_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec pr
                         int32_t out_parity, const void *links, const void *in, void *out,
                         int32_t nrhs, void *stream);
 
+/* Bandwidth reference for the roofline: dst = src for `bytes` bytes with the
+ * library's streaming copy kernel (16-byte loads and stores, four per
+ * thread, non-temporal).  bytes must be a positive multiple of 16 and both
+ * pointers 16-byte aligned device memory that does not overlap; otherwise
+ * HISQ_ERR_INVALID_ARG.  Asynchronous.  Not part of the method: it measures
+ * the copy ceiling the Dslash rates are compared with. */
+hisq_status hisq_stream_copy(hisq_context *ctx, const void *src, void *dst, size_t bytes, void *stream);
+
 /* out_even = (m^2) in_even - D_eo D_oe in_even, using tmp_odd (a packed
  * field of nrhs on the odd sites) as scratch.  Asynchronous. */
 hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,

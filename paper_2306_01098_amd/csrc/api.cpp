@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation (host only, before any HIP call),
 // error reporting and dispatch to the kernels.
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -249,6 +250,22 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
     prm.ay = mass * mass;
     e = launch_dslash(prm, prec, prec, EPI_AXPY, s, st);
     return e == hipSuccess ? HISQ_OK : device_fail(e, "apply_m (D_eo)");
+}
+
+hisq_status hisq_stream_copy(hisq_context *ctx, const void *src, void *dst, size_t bytes, void *stream) {
+    TRY(check_ptr(src, "src"));
+    TRY(check_ptr(dst, "dst"));
+    if (bytes == 0 || bytes % 16 != 0)
+        return fail(HISQ_ERR_INVALID_ARG, "bytes = %zu must be a positive multiple of 16", bytes);
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return fail(HISQ_ERR_INVALID_ARG, "src and dst must be 16-byte aligned");
+    const char *s0 = static_cast<const char *>(src);
+    const char *d0 = static_cast<const char *>(dst);
+    if (s0 < d0 + bytes && d0 < s0 + bytes)
+        return fail(HISQ_ERR_INVALID_ARG, "src and dst overlap");
+    TRY(set_device(ctx));
+    const hipError_t e = launch_stream_copy(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "stream_copy");
 }
 
 }  // extern "C"

@@ -4,8 +4,8 @@
 // to (problem, first site), so 64 small solves advance together with four
 // launches per iteration instead of 256, and the sequence is captured once in
 // a HIP graph.  Per-problem Krylov scalars live on the device; each reducing
-// kernel stores block partials and a one-block finalize kernel sums them per
-// problem in a fixed order and advances the scalars.
+// kernel stores block partials and a finalize kernel (one wavefront per
+// problem) sums them in a fixed order and advances the scalars.
 #include "batch.hpp"
 #include "dslash.hpp"
 #include "reduce.hpp"
@@ -16,6 +16,7 @@ namespace {
 
 constexpr int BB = BATCH_BLOCK;
 enum { FIN_PQ = 0, FIN_XR, FIN_RESID, FIN_BNORM };
+constexpr int FIN_BLOCK = 256;  // four problems per finalize block
 
 template <int FP> struct SloppyT;
 template <> struct SloppyT<HISQ_FP64> { using T = double; };
@@ -28,19 +29,6 @@ __device__ __forceinline__ bool participates(const BatchArgs &a, int j, int role
     return role <= ROLE_ITER_DEO ? a.st[j].active != 0 : a.mask[j] != 0;
 }
 
-// Per-problem totals of block partials (blocks of a problem are contiguous),
-// one wave per problem (deterministic, see wave_sum_slot).
-__device__ void batch_totals(const BatchArgs &a, double *tot /* shared [MAX_BATCH] */) {
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int j = wave; j < a.nprob; j += nw) {
-        const BatchProb &P = a.probs[j];
-        const double v = wave_sum_slot(a.partials + P.first_blk, P.nblk);
-        if ((threadIdx.x & 63) == 0)
-            tot[j] = v;
-    }
-    __syncthreads();
-}
-
 // Dslash over all participating problems.
 //  ROLE_ITER_DOE: t = D_oe p             (sloppy links/fields)
 //  ROLE_ITER_DEO: q = m^2 p - D_eo t, Re<p, q> -> st[j].pq
@@ -49,7 +37,7 @@ __device__ void batch_totals(const BatchArgs &a, double *tot /* shared [MAX_BATC
 template <int LP, int FP, int ROLE>
 __global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
     using A = typename Prec<LP>::acc;
-    if (ROLE <= ROLE_ITER_DEO && *a.skip)  // iterations stop once no problem is active
+    if (ROLE <= ROLE_ITER_DEO && *a.nactive == 0)  // iterations stop once no problem is active
         return;
     constexpr bool DOT = ROLE == ROLE_ITER_DEO;
     constexpr bool AXPY = ROLE == ROLE_ITER_DEO || ROLE == ROLE_TRUE_DEO;
@@ -95,7 +83,7 @@ __global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
 template <int FP>
 __global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
-    if (*a.skip)
+    if (*a.nactive == 0)
         return;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
@@ -131,80 +119,77 @@ __global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
         a.partials[blk] = part[0];
 }
 
-// Finalize of the reducing batch kernels (one block).
-//  FIN_PQ:    st[j].pq = total for active problems
-//  FIN_XR:    advance every active problem's scalars (and stamp the device
-//             clock when a problem's recurrence stops)
-//  FIN_RESID: st[j].rho_new = total for masked problems
+// Finalize of the reducing batch kernels: one wavefront per problem sums the
+// problem's block partials (deterministic, see wave_sum_slot), then its lane 0
+//  FIN_PQ:    st[j].pq = total (active problems)
+//  FIN_XR:    advances the problem's scalars and raises its flags; a problem
+//             that stops is stamped with the device clock and leaves the
+//             active count
+//  FIN_RESID: st[j].rho_new = total (masked problems)
 //  FIN_BNORM: bnorm2[j] = total
-__global__ void __launch_bounds__(1024) batch_finalize_kernel(BatchArgs a, int mode, double *bnorm2) {
-    if ((mode == FIN_PQ || mode == FIN_XR) && *a.skip)
+__global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, int mode, double *bnorm2) {
+    if ((mode == FIN_PQ || mode == FIN_XR) && *a.nactive == 0)
         return;
-    __shared__ double tot[MAX_BATCH];
-    batch_totals(a, tot);
-    if (mode == FIN_PQ) {
-        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-            if (a.st[jj].active)
-                a.st[jj].pq = tot[jj];
+    const int j = blockIdx.x * (FIN_BLOCK / 64) + (threadIdx.x >> 6);
+    if (j >= a.nprob)  // uniform over the wavefront
+        return;
+    const BatchProb &P = a.probs[j];
+    const double tot = wave_sum_slot(a.partials + P.first_blk, P.nblk);
+    if ((threadIdx.x & 63) != 0)
+        return;
+    if (mode == FIN_BNORM) {
+        bnorm2[j] = tot;
         return;
     }
     if (mode == FIN_RESID) {
-        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-            if (a.mask[jj])
-                a.st[jj].rho_new = tot[jj];
+        if (a.mask[j])
+            a.st[j].rho_new = tot;
         return;
     }
-    if (mode == FIN_BNORM) {
-        for (int jj = threadIdx.x; jj < a.nprob; jj += blockDim.x)
-            bnorm2[jj] = tot[jj];
+    CgScalars s = a.st[j];
+    if (!s.active)
+        return;
+    if (mode == FIN_PQ) {
+        a.st[j].pq = tot;
         return;
     }
-    if (threadIdx.x != 0)
-        return;
-    const double now = (double)wall_clock64();
-    int any = 0;
-    for (int jj = 0; jj < a.nprob; ++jj) {
-        CgScalars s = a.st[jj];
-        if (s.active) {
-            if (!pos_finite(s.pq)) {
-                s.flag = FLAG_BREAKDOWN;
-                s.active = 0;
-            } else {
-                const double rho_new = tot[jj];
-                s.iters += 1;
-                s.rho_new = rho_new;
-                if (!(rho_new == rho_new)) {
-                    s.flag = FLAG_BREAKDOWN;
-                    s.active = 0;
-                } else if (rho_new <= s.target2) {
-                    s.flag = FLAG_CONV;
-                    s.active = 0;
-                } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
-                    s.flag = FLAG_RELIABLE;
-                    s.active = 0;
-                } else if (s.iters >= s.max_iter) {
-                    s.flag = FLAG_MAXIT;
-                    s.active = 0;
-                } else {
-                    s.beta = rho_new / s.rho;
-                    s.rho = rho_new;
-                    s.rmax2 = fmax(s.rmax2, rho_new);
-                }
-            }
-            if (!s.active)
-                s.spare = now;  // device clock when the recurrence stopped
-            a.st[jj] = s;
+    if (!pos_finite(s.pq)) {
+        s.flag = FLAG_BREAKDOWN;
+        s.active = 0;
+    } else {
+        const double rho_new = tot;
+        s.iters += 1;
+        s.rho_new = rho_new;
+        if (!(rho_new == rho_new)) {
+            s.flag = FLAG_BREAKDOWN;
+            s.active = 0;
+        } else if (rho_new <= s.target2) {
+            s.flag = FLAG_CONV;
+            s.active = 0;
+        } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
+            s.flag = FLAG_RELIABLE;
+            s.active = 0;
+        } else if (s.iters >= s.max_iter) {
+            s.flag = FLAG_MAXIT;
+            s.active = 0;
+        } else {
+            s.beta = rho_new / s.rho;
+            s.rho = rho_new;
+            s.rmax2 = fmax(s.rmax2, rho_new);
         }
-        any |= s.active;
     }
-    *a.skip = any ? 0 : 1;
+    if (!s.active) {
+        s.spare = (double)wall_clock64();  // device clock when the recurrence stopped
+        atomicSub(a.nactive, 1);
+    }
+    a.st[j] = s;
 }
 
 // p = r + beta p for active problems.
 template <int FP>
 __global__ void __launch_bounds__(BB) batch_p_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
-    if (*a.skip)
+    if (*a.nactive == 0)
         return;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
@@ -328,7 +313,7 @@ hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStre
                     : (op == BOP_RESIDUAL || op == BOP_RESIDUAL_COPY_P) ? FIN_RESID : -1;
     if (fin < 0)
         return hipSuccess;
-    batch_finalize_kernel<<<1, 1024, 0, st>>>(a, fin, nullptr);
+    batch_finalize_kernel<<<(a.nprob + 3) / 4, FIN_BLOCK, 0, st>>>(a, fin, nullptr);
     return hipGetLastError();
 }
 
@@ -337,7 +322,7 @@ hipError_t launch_batch_bnorm(const BatchArgs &a, int nblocks, double *bnorm2, h
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    batch_finalize_kernel<<<1, 1024, 0, st>>>(a, FIN_BNORM, bnorm2);
+    batch_finalize_kernel<<<(a.nprob + 3) / 4, FIN_BLOCK, 0, st>>>(a, FIN_BNORM, bnorm2);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ struct BatchArgs {
     CgScalars *st;        // [nprob]
     const int *mask;      // [nprob] problems taking part in a true-residual pass
     double *partials;     // [nblocks]
-    int *skip;
+    int *nactive;         // problems still iterating: iteration kernels do nothing at 0
 };
 
 enum { ROLE_ITER_DOE = 0, ROLE_ITER_DEO = 1, ROLE_TRUE_DOE = 2, ROLE_TRUE_DEO = 3 };

@@ -64,7 +64,7 @@ double wall_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-enum { BF_SKIP = 0 };
+enum { BF_NACTIVE = 0 };
 
 }  // namespace
 
@@ -172,7 +172,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     a.mask = reinterpret_cast<const int *>(W + L.mask);
     a.partials = reinterpret_cast<double *>(W + L.partials);
     unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
-    a.skip = reinterpret_cast<int *>(flags + BF_SKIP);
+    a.nactive = reinterpret_cast<int *>(flags + BF_NACTIVE);
     double *scal = reinterpret_cast<double *>(W + L.scal);  // [0..n) ||b||^2, [MAX_BATCH] start clock
     int *mask_d = reinterpret_cast<int *>(W + L.mask);
 
@@ -182,12 +182,11 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     auto push = [&](bool state, bool msk) -> hipError_t {
         hipError_t err = hipSuccess;
         if (state) {
-            int any = 0;
-            for (int j = 0; j < n; ++j) any |= hs[j].active;
-            const unsigned skip = any ? 0u : 1u;
+            int nact = 0;
+            for (int j = 0; j < n; ++j) nact += hs[j].active != 0;
             err = hipMemcpyAsync(a.st, hs.data(), sizeof(CgScalars) * n, hipMemcpyHostToDevice, st);
             if (err == hipSuccess)
-                err = hipMemcpyAsync(flags + BF_SKIP, &skip, sizeof skip, hipMemcpyHostToDevice, st);
+                err = hipMemcpyAsync(flags + BF_NACTIVE, &nact, sizeof nact, hipMemcpyHostToDevice, st);
         }
         if (msk && err == hipSuccess)
             err = hipMemcpyAsync(mask_d, mask.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);

@@ -2,14 +2,17 @@
 //
 // Two thread mappings, chosen per problem by the autotuner:
 //  * SITE:  one thread per output site; NIN right-hand sides per thread share
-//           every link load (the N_inner loop of the paper's Sec. 5.1), more
-//           right-hand sides over gridDim.y (N_outer).
+//           every link load (the N_inner loop of the paper's Sec. 5.1); the
+//           N_outer groups of NIN right-hand sides are further blocks.
 //  * DIR:   four consecutive lanes per output site, lane mu handling the four
 //           hops (+-1, +-3) along direction mu; the partial sums are combined
 //           by two butterfly shuffles.  Four times the wavefronts of SITE, so
 //           a 32^3x8 lattice fills all 256 CUs with more loads in flight.
 // Both read every link matrix exactly once per application, as 16-byte
-// coalesced chunks of the structure-of-arrays link layout.
+// coalesced chunks of the structure-of-arrays link layout.  The right-hand
+// side group is the fastest-varying part of the block index, so the N_outer
+// blocks of one range of sites run together (on one XCD when remapped) and
+// its links come from cache after the first of them.
 #pragma once
 
 #include "access.hpp"
@@ -34,7 +37,7 @@ struct DslashParams {
     const void *y;  // EPI_AXPY*: out = ad * D in + ay * y (y on the output parity)
     double ad, ay;
     const int *skip;     // optional: if *skip != 0 the whole launch does nothing
-    double *partials;    // EPI_AXPY_DOT: [nrhs][gridDim.x] block partials
+    double *partials;    // EPI_AXPY_DOT: [nrhs][site blocks] block partials
     double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride] (finalize kernel)
     int dot_stride;
 };
@@ -68,6 +71,20 @@ __device__ __forceinline__ int logical_block(int remap) {
     const int x = b & 7, j = b >> 3;
     return x * q + min(x, r) + j;
 }
+
+// Block coordinates: site block `sb` (of nsb) and first right-hand side r0
+// of the block's group of NIN.
+template <int NIN> struct BlockPos {
+    int sb, nsb, r0, nr;
+    __device__ __forceinline__ BlockPos(const DslashParams &prm) {
+        const int nouter = (prm.nrhs + NIN - 1) / NIN;
+        const int lb = logical_block(prm.xcd_remap);
+        sb = lb / nouter;
+        nsb = gridDim.x / nouter;
+        r0 = (lb - sb * nouter) * NIN;
+        nr = min(NIN, prm.nrhs - r0);
+    }
+};
 
 template <int NIN, typename A> __device__ __forceinline__ void zero(cplx<A> (&v)[NIN][3]) {
 #pragma unroll
@@ -271,12 +288,12 @@ __device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i
 
 // Block partials of the NIN dot products (summed by a finalize kernel).
 template <int NIN>
-__device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, double (&dot)[NIN], int r0, int nr) {
+__device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, double (&dot)[NIN], const BlockPos<NIN> &bp) {
     __shared__ double lds[4 * NIN];
     block_sum<NIN>(dot, lds);
     if (threadIdx.x == 0)
-        for (int r = 0; r < nr; ++r)
-            prm.partials[(size_t)(r0 + r) * gridDim.x + blockIdx.x] = dot[r];
+        for (int r = 0; r < bp.nr; ++r)
+            prm.partials[(size_t)(bp.r0 + r) * bp.nsb + bp.sb] = dot[r];
 }
 
 template <int LP, int FP, int NIN, int EPI>
@@ -284,12 +301,12 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
     using A = typename Prec<LP>::acc;
     if (prm.skip && *prm.skip)
         return;
-    const int i = logical_block(prm.xcd_remap) * blockDim.x + threadIdx.x;
+    const BlockPos<NIN> bp(prm);
+    const int i = bp.sb * blockDim.x + threadIdx.x;
     const bool valid = i < prm.g.vh;
     if (EPI != EPI_AXPY_DOT && !valid)
         return;
-    const int r0 = blockIdx.y * NIN;
-    const int nr = min(NIN, prm.nrhs - r0);
+    const int r0 = bp.r0, nr = bp.nr;
     double dot[NIN];
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
@@ -306,7 +323,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
         }
     }
     if (EPI == EPI_AXPY_DOT)
-        dslash_dot_reduce<NIN>(prm, dot, r0, nr);
+        dslash_dot_reduce<NIN>(prm, dot, bp);
 }
 
 template <int LP, int FP, int NIN, int EPI>
@@ -315,14 +332,14 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
     if (prm.skip && *prm.skip)
         return;
     const int mu = threadIdx.x & 3;
-    const int i = logical_block(prm.xcd_remap) * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    const BlockPos<NIN> bp(prm);
+    const int i = bp.sb * (blockDim.x >> 2) + (threadIdx.x >> 2);
     // a site's four lanes are in one wavefront and share validity, so whole
     // quads drop out together and the shuffles below see only valid partners
     const bool valid = i < prm.g.vh;
     if (EPI != EPI_AXPY_DOT && !valid)
         return;
-    const int r0 = blockIdx.y * NIN;
-    const int nr = min(NIN, prm.nrhs - r0);
+    const int r0 = bp.r0, nr = bp.nr;
     double dot[NIN];
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
@@ -361,7 +378,7 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
     }
     }
     if (EPI == EPI_AXPY_DOT)
-        dslash_dot_reduce<NIN>(prm, dot, r0, nr);
+        dslash_dot_reduce<NIN>(prm, dot, bp);
 }
 
 }  // namespace hisq

@@ -11,8 +11,9 @@ namespace hisq {
 template <int LP, int FP, int NIN, int EPI>
 hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
-    const dim3 grid((unsigned)((prm.g.vh + sites_per_block - 1) / sites_per_block),
-                    (unsigned)((prm.nrhs + NIN - 1) / NIN));
+    const int nsb = (prm.g.vh + sites_per_block - 1) / sites_per_block;
+    const int nouter = (prm.nrhs + NIN - 1) / NIN;
+    const dim3 grid((unsigned)(nsb * nouter));
     DslashParams p = prm;
     p.xcd_remap = s.xcd_remap;
     if (s.variant == VAR_DIR)
@@ -21,8 +22,8 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
         dslash_site_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && EPI == EPI_AXPY_DOT)
-        e = launch_sum_partials(p.partials, p.nrhs, (int)grid.x, p.dot_out, p.dot_stride > 0 ? p.dot_stride : 1,
-                                p.skip, st);
+        e = launch_sum_partials(p.partials, p.nrhs, nsb, p.dot_out, p.dot_stride > 0 ? p.dot_stride : 1, p.skip,
+                                st);
     return e;
 }
 

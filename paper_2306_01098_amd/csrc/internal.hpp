@@ -40,6 +40,8 @@ hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStre
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
                            double *out2, hipStream_t st);
 hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, hipStream_t st);
+// dst = src for n16 16-byte chunks (non-temporal streaming copy).
+hipError_t launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t st);
 // out[s * stride] = sum over nblk block partials of slot s (one-block kernel);
 // does nothing when skip is non-NULL and *skip != 0.
 hipError_t launch_sum_partials(const double *partials, int nslots, int nblk, double *out, int stride,

@@ -15,19 +15,21 @@ namespace hisq {
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     (void)g;
     (void)fp;
+    // measured on 32^3x8 at one right-hand side and 48^3x12 at 4 and 16:
+    // the per-site mapping wins everywhere once the N_outer groups of a site
+    // range run together; more than 4 (FP16N: 2) accumulators per thread cost
+    // more in occupancy than the shared link loads save
     DslashShape s;
+    s.variant = VAR_SITE;
     s.xcd_remap = 1;
     if (nrhs == 1) {
-        s.variant = VAR_SITE;
         s.nin = 1;
         s.block = 128;
         return s;
     }
-    s.variant = VAR_DIR;
-    s.block = 256;
-    s.nin = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : 2;
-    if (lp == HISQ_FP64 && s.nin > 4)
-        s.nin = 4;
+    const int cap = lp == HISQ_FP16N ? 2 : 4;
+    s.nin = nrhs >= cap ? cap : 2;
+    s.block = 64;
     return s;
 }
 

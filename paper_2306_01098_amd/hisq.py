@@ -75,6 +75,7 @@ _SIGS = {
                                    ctypes.c_int32, _vp]),
     "hisq_apply_m": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
                                     ctypes.c_int32, _vp]),
+    "hisq_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_tune_dslash": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "hisq_get_dslash_shape": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32,
                                              ctypes.POINTER(hisq_dslash_shape)]),
@@ -272,6 +273,14 @@ def hisq_apply_m(lat, prec, mass: float, links, in_even, out_even, tmp_odd, nrhs
                                _ptr(in_even, "in_even", fb), _ptr(out_even, "out_even", fb),
                                _ptr(tmp_odd, "tmp_odd", fb), int(nrhs), _stream(stream)),
            "hisq_apply_m")
+
+
+def hisq_stream_copy(src, dst, nbytes: int | None = None, ctx=None, stream=None):
+    """dst = src (first nbytes bytes, default all of src) with the library's
+    streaming copy kernel: the bandwidth reference of the benchmark."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    _check(load().hisq_stream_copy(_ctx(ctx), _ptr(src, "src", n), _ptr(dst, "dst", n), n, _stream(stream)),
+           "hisq_stream_copy")
 
 
 def hisq_tune_dslash(lat, prec, nrhs: int, links, inp, out, ctx, stream=None):

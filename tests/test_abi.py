@@ -148,3 +148,15 @@ def test_batch_and_ptc_argument_checks(lib):
                                   None) == h.INVALID_ARG
     assert lib.hisq_fcg(None, ctypes.byref(lat), 0.1, p(16), p(24), p(32), p(40), p(40), 1e-8, 10, p(64),
                         1 << 20, None, None) == h.INVALID_ARG
+
+
+def test_stream_copy_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    p = ctypes.c_void_p
+    # zero bytes, not a multiple of 16, misaligned, overlapping, NULL
+    assert lib.hisq_stream_copy(None, p(4096), p(1 << 20), 0, None) == h.INVALID_ARG
+    assert lib.hisq_stream_copy(None, p(4096), p(1 << 20), 24, None) == h.INVALID_ARG
+    assert lib.hisq_stream_copy(None, p(4104), p(1 << 20), 32, None) == h.INVALID_ARG
+    assert lib.hisq_stream_copy(None, p(4096), p(4096 + 16), 64, None) == h.INVALID_ARG
+    assert b"overlap" in lib.hisq_last_error()
+    assert lib.hisq_stream_copy(None, None, p(1 << 20), 64, None) == h.INVALID_ARG

@@ -247,3 +247,16 @@ def test_autotuner_picks_a_supported_shape(gpu_lib, fields):
     h.hisq_dslash(lat, "fp64", 0, links, inp, out, ctx=ctx)
     got = h.unpack_field_to_host(lat, "fp64", out)[0]
     assert relerr(got, O.lattice_from(w).D_eo(w["src_o"][0])) <= 1e-13
+
+
+def test_stream_copy_is_exact(gpu_lib):
+    """The bandwidth-reference copy moves every byte, including a ragged tail
+    shorter than one block's 16 KiB."""
+    h = gpu_lib
+    n = 16 * (3 * 1024 + 517)
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
+    h.hisq_stream_copy(src, dst, n)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src)
+    assert int(dst[n:].count_nonzero()) == 0
