@@ -202,3 +202,22 @@ def workload_5(dims=(32, 32, 32, 32), ntrain: int = 256, ntest: int = 16):
     w["train_src"] = gaussian_half_field(rng_for(5, FIELD_SOURCE), dims, ntrain)
     w["test_src"] = gaussian_half_field(rng_for(5, FIELD_SOURCE + 1), dims, ntest)
     return w
+
+
+PTC_CHANNELS = (1, 8, 8, 1)
+PTC_PATHS = 9
+
+
+def ptc_initial_weights(seed: int, scale: float = 0.05):
+    """Seeded starting weights of the 1 -> 8 -> 8 -> 1 PTC network, one
+    (c_out, c_in, 9) complex array per layer: the identity path starts at
+    1/sqrt(c_in c_out), every weight gets complex Gaussian noise of width
+    scale/sqrt(9 c_in).  A random draw only (the network itself is elsewhere)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for cin, cout in zip(PTC_CHANNELS[:-1], PTC_CHANNELS[1:]):
+        g = rng.standard_normal((cout, cin, PTC_PATHS, 2)) * scale / np.sqrt(cin * PTC_PATHS)
+        w = g[..., 0] + 1j * g[..., 1]
+        w[:, :, 0] += 1.0 / np.sqrt(cin * cout)
+        out.append(w)
+    return out

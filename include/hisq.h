@@ -66,8 +66,27 @@ typedef struct {
  *                by a binary32 per-site norm n = max |component| over the 6
  *                reals of the site (packing from complex128: each part v is
  *                stored as binary16(v / binary32(n)), quotient in FP64 rounded
- *                once); arithmetic in FP32. */
-typedef enum { HISQ_FP64 = 0, HISQ_FP32 = 1, HISQ_FP16N = 2 } hisq_prec;
+ *                once); arithmetic in FP32.
+ *   HISQ_FP64R12, HISQ_FP32R12 : compressed links for special-unitary link
+ *                fields (the gauge-field compression types of Sec. 4.4, whose
+ *                missing entries follow from the SU(3) symmetry, Sec. 5): only
+ *                rows 0 and 1 of each matrix are stored (12 reals, rounded as
+ *                for HISQ_FP64 / HISQ_FP32); row 2 is rebuilt in-kernel as the
+ *                complex conjugate of the cross product of rows 0 and 1, which
+ *                is exact for SU(3) and wrong for anything else (the library
+ *                does not check; HISQ fat links are in general not unitary).
+ *                Colour vectors and arithmetic as for HISQ_FP64 / HISQ_FP32,
+ *                so fields of these precisions are HISQ_FP64 / HISQ_FP32
+ *                fields.  Accepted by the pack/unpack calls, hisq_dslash,
+ *                hisq_apply_m, the autotuner, and as the `inner` precision of
+ *                hisq_cg and hisq_multishift_cg (links_inner in this format). */
+typedef enum {
+    HISQ_FP64 = 0,
+    HISQ_FP32 = 1,
+    HISQ_FP16N = 2,
+    HISQ_FP64R12 = 3,
+    HISQ_FP32R12 = 4
+} hisq_prec;
 
 typedef enum {
     HISQ_OK = 0,
@@ -211,12 +230,14 @@ size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *prob
 /* Batched CG: nproblems (1..256) independent systems M_e x = b, each on its
  * own lattice with its own mass, links and tolerance, solved together.  Every
  * launch covers the sites of all problems through a block -> problem work
- * list, so one iteration of all problems is four kernels; chunks of
+ * list, so one iteration of all problems is four kernels (plus the finalize
+ * kernels of the two reductions); chunks of
  * iterations are captured in a HIP graph and replayed; a problem whose
  * iterated residual meets its target stops updating while the others go on.
  * With inner = FP32/FP16N the iterations use that link precision with FP32
  * vectors and FP64 reliable updates (batched over the problems that need
- * one), as in hisq_cg.
+ * one), as in hisq_cg.  The reconstruct-12 precisions are not accepted here
+ * (HISQ_ERR_UNSUPPORTED; the workspace query returns 0).
  *   problems    host array [nproblems]; the structs may be freed on return.
  *   info        host array [nproblems] (seconds = wall time of the batch).
  *   latency_s   host array [nproblems] or NULL: device-clock time from the

@@ -248,6 +248,8 @@ def multishift_reference(lat: Lattice, mass: float, shifts, b, tol, max_iter: in
 # ---------------------------------------------------------------------------
 # Storage formats of the reduced-precision path:
 #   FP32:   each real and imaginary part rounded to binary32 (nearest-even).
+#   R12:    links: rows 0 and 1 rounded as FP64 / FP32, row 2 rebuilt as
+#           conj(row0 x row1); colour vectors as FP64 / FP32.
 #   FP16N:  links: each real part rounded once, from binary64, to binary16
 #           (nearest-even).
 #           colour vectors: per site n = max |component| over the 6 reals,
@@ -277,6 +279,30 @@ def quantize_field_fp16n(psi):
     return out
 
 
+def reconstruct12(U):
+    """Keep rows 0 and 1 of each 3x3 matrix and replace row 2 by the complex
+    conjugate of their cross product.  For U in SU(3) this returns U (the
+    rows are orthonormal and det U = 1, so row 2 = conj(row0 x row1)); any
+    other matrix is changed.  This is the reconstruct-12 link compression
+    (Sec. 4.4 gauge-field compression types; Sec. 5 notes that the dropped
+    entries follow from the SU(3) symmetry)."""
+    U = np.array(U, dtype=np.complex128)
+    a, b = U[..., 0, :], U[..., 1, :]
+    U[..., 2, :] = np.conj(np.cross(a, b))
+    return U
+
+
+def quantize_links_r12(U, prec: str):
+    """Reconstruct-12 storage: rows 0 and 1 rounded to `prec` ("fp64" or
+    "fp32"), row 2 rebuilt from the rounded rows (in FP64)."""
+    U = np.asarray(U, dtype=np.complex128)
+    if prec == "fp32":
+        U = quantize_fp32(U)
+    elif prec != "fp64":
+        raise ValueError(prec)
+    return reconstruct12(U)
+
+
 def quantized_lattice(lat: Lattice, prec: str) -> Lattice:
     if prec == "fp64":
         return lat
@@ -284,10 +310,15 @@ def quantized_lattice(lat: Lattice, prec: str) -> Lattice:
         return Lattice(lat.dims, lat.t_bc, quantize_fp32(lat.X), quantize_fp32(lat.W))
     if prec == "fp16n":
         return Lattice(lat.dims, lat.t_bc, quantize_links_fp16(lat.X), quantize_links_fp16(lat.W))
+    if prec in ("fp64r12", "fp32r12"):
+        base = prec[:4]
+        return Lattice(lat.dims, lat.t_bc, quantize_links_r12(lat.X, base), quantize_links_r12(lat.W, base))
     raise ValueError(prec)
 
 
 def quantize_field(psi, prec: str):
+    if prec in ("fp64r12", "fp32r12"):   # colour vectors as in the base precision
+        prec = prec[:4]
     if prec == "fp64":
         return np.asarray(psi, dtype=np.complex128)
     if prec == "fp32":

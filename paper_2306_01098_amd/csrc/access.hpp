@@ -21,6 +21,7 @@ typedef float nt_f2 __attribute__((ext_vector_type(2)));
 
 template <> struct LinkIO<HISQ_FP64> {
     using A = double;
+    static constexpr bool rebuild = false;
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -33,6 +34,7 @@ template <> struct LinkIO<HISQ_FP64> {
 
 template <> struct LinkIO<HISQ_FP32> {
     using A = float;
+    static constexpr bool rebuild = false;
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -59,6 +61,7 @@ union H2 {
 
 template <> struct LinkIO<HISQ_FP16N> {
     using A = float;
+    static constexpr bool rebuild = false;
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -74,6 +77,53 @@ template <> struct LinkIO<HISQ_FP16N> {
         m[17] = (float)t.h[1];
     }
 };
+
+// Reconstruct-12: load fills m[0..11] (rows 0 and 1); rebuild_row2 computes
+// row 2 at the point of use, so the loads of the next hop stay in flight.
+template <> struct LinkIO<HISQ_FP64R12> {
+    using A = double;
+    static constexpr bool rebuild = true;
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
+            m[2 * k] = v.x;
+            m[2 * k + 1] = v.y;
+        }
+    }
+};
+
+template <> struct LinkIO<HISQ_FP32R12> {
+    using A = float;
+    static constexpr bool rebuild = true;
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
+            m[4 * k] = v.x;
+            m[4 * k + 1] = v.y;
+            m[4 * k + 2] = v.z;
+            m[4 * k + 3] = v.w;
+        }
+    }
+};
+
+// Row 2 of a special-unitary matrix from rows 0 (a) and 1 (b): since
+// det U = 1 and U^+ = U^-1, row 2 = conj(a x b), i.e.
+// c_k = conj(a_{k+1} b_{k+2} - a_{k+2} b_{k+1}) (indices mod 3).
+template <typename A> __device__ __forceinline__ void rebuild_row2(A m[18]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int j = (k + 1) % 3, l = (k + 2) % 3;
+        const A ajr = m[2 * j], aji = m[2 * j + 1], alr = m[2 * l], ali = m[2 * l + 1];
+        const A bjr = m[6 + 2 * j], bji = m[6 + 2 * j + 1], blr = m[6 + 2 * l], bli = m[6 + 2 * l + 1];
+        // a_j b_l - a_l b_j
+        const A re = fma(ajr, blr, fma(-aji, bli, fma(-alr, bjr, ali * bji)));
+        const A im = fma(ajr, bli, fma(aji, blr, fma(-alr, bji, -ali * bjr)));
+        m[12 + 2 * k] = re;
+        m[12 + 2 * k + 1] = -im;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Colour-vector fields on one parity.

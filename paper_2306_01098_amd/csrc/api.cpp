@@ -46,7 +46,8 @@ hisq_status check_lattice(const hisq_lattice *lat) {
 }
 
 hisq_status check_prec(int prec) {
-    if (prec != HISQ_FP64 && prec != HISQ_FP32 && prec != HISQ_FP16N)
+    if (prec != HISQ_FP64 && prec != HISQ_FP32 && prec != HISQ_FP16N && prec != HISQ_FP64R12 &&
+        prec != HISQ_FP32R12)
         return fail(HISQ_ERR_INVALID_ARG, "unknown precision %d", prec);
     return HISQ_OK;
 }
@@ -129,7 +130,7 @@ size_t hisq_links_bytes(const hisq_lattice *lat, hisq_prec prec) {
     if (check_lattice(lat) != HISQ_OK || check_prec(prec) != HISQ_OK)
         return 0;
     const Geom g = make_geom(*lat);
-    return links_bytes(g, prec == HISQ_FP64 ? 8 : prec == HISQ_FP32 ? 4 : 2);
+    return links_bytes(g, link_matrix_bytes(prec));
 }
 
 size_t hisq_field_bytes(const hisq_lattice *lat, hisq_prec prec, int32_t nrhs) {
@@ -173,7 +174,7 @@ hisq_status hisq_pack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_pre
     TRY(check_ptr(packed, "packed"));
     TRY(set_device(ctx));
     const hipError_t e =
-        launch_pack_field(make_geom(*lat), prec, nrhs, half_c128, packed, static_cast<hipStream_t>(stream));
+        launch_pack_field(make_geom(*lat), field_prec_of(prec), nrhs, half_c128, packed, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HISQ_OK : device_fail(e, "pack_field");
 }
 
@@ -186,7 +187,8 @@ hisq_status hisq_unpack_field(hisq_context *ctx, const hisq_lattice *lat, hisq_p
     TRY(check_ptr(half_c128, "half_c128"));
     TRY(set_device(ctx));
     const hipError_t e =
-        launch_unpack_field(make_geom(*lat), prec, nrhs, packed, half_c128, static_cast<hipStream_t>(stream));
+        launch_unpack_field(make_geom(*lat), field_prec_of(prec), nrhs, packed, half_c128,
+                            static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HISQ_OK : device_fail(e, "unpack_field");
 }
 
@@ -210,8 +212,8 @@ hisq_status hisq_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec pr
     prm.links = static_cast<const char *>(links);
     prm.in = in;
     prm.out = out;
-    const DslashShape s = pick_shape(ctx, prm.g, prec, prec, nrhs);
-    const hipError_t e = launch_dslash(prm, prec, prec, EPI_PLAIN, s, static_cast<hipStream_t>(stream));
+    const DslashShape s = pick_shape(ctx, prm.g, prec, field_prec_of(prec), nrhs);
+    const hipError_t e = launch_dslash(prm, prec, field_prec_of(prec), EPI_PLAIN, s, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HISQ_OK : device_fail(e, "dslash");
 }
 
@@ -235,11 +237,11 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
     prm.g = make_geom(*lat);
     prm.nrhs = nrhs;
     prm.links = static_cast<const char *>(links);
-    const DslashShape s = pick_shape(ctx, prm.g, prec, prec, nrhs);
+    const DslashShape s = pick_shape(ctx, prm.g, prec, field_prec_of(prec), nrhs);
     prm.out_parity = 1;
     prm.in = in_even;
     prm.out = tmp_odd;
-    hipError_t e = launch_dslash(prm, prec, prec, EPI_PLAIN, s, st);
+    hipError_t e = launch_dslash(prm, prec, field_prec_of(prec), EPI_PLAIN, s, st);
     if (e != hipSuccess)
         return device_fail(e, "apply_m (D_oe)");
     prm.out_parity = 0;
@@ -248,7 +250,7 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
     prm.y = in_even;
     prm.ad = -1.0;
     prm.ay = mass * mass;
-    e = launch_dslash(prm, prec, prec, EPI_AXPY, s, st);
+    e = launch_dslash(prm, prec, field_prec_of(prec), EPI_AXPY, s, st);
     return e == hipSuccess ? HISQ_OK : device_fail(e, "apply_m (D_eo)");
 }
 

@@ -33,7 +33,7 @@ struct Layout {
 
 Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     Layout L;
-    L.fs = inner == HISQ_FP64 ? HISQ_FP64 : HISQ_FP32;
+    L.fs = field_prec_of(inner) == HISQ_FP64 ? HISQ_FP64 : HISQ_FP32;
     L.nblk_max = std::max(g.vh / 16 + 1, blas_blocks(g.vh));
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -583,7 +583,7 @@ hisq_status setup_solver(Solver &S, hisq_context *ctx, const hisq_lattice *lat, 
     S.shape64 = pick_shape(ctx, S.g, HISQ_FP64, HISQ_FP64, 1);
     S.shape_in = pick_shape(ctx, S.g, S.lp_in, S.L.fs, nrhs);
     // chunk length: ~1 ms of iterations, 8 .. 64
-    const double bytes_per_iter = 2.0 * (double)S.g.vh * 16 * 18 * (inner == HISQ_FP64 ? 8 : inner == HISQ_FP32 ? 4 : 2);
+    const double bytes_per_iter = 2.0 * (double)S.g.vh * 16 * link_matrix_bytes(inner);
     const double est_us = bytes_per_iter / 5.0e6 + 12.0;
     S.chunk = std::max(8, std::min(64, (int)(1000.0 / est_us)));
     return HISQ_OK;
@@ -641,7 +641,7 @@ hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, con
         return s;
     // reliable updates whenever the iterated residual fell by 10x (reduced
     // precision); FP64 CG checks the true residual at convergence only
-    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
     return run_cg(S, 0.0, nrhs, b, x, tol, max_iter, delta, info, nullptr);
 }
 
@@ -680,7 +680,7 @@ hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, doubl
     if ((s = setup_solver(S, ctx, lat, mass, links_f64, links_inner, inner, 1, nshift, ws, ws_bytes, sg.own)) !=
         HISQ_OK)
         return s;
-    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
     return run_multishift(S, nshift, shifts, b, x, tol, max_iter, delta, info);
 }
 

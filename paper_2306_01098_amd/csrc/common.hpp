@@ -42,36 +42,59 @@ inline Geom make_geom(const hisq_lattice &l) {
 // split into 16-byte chunks, structure of arrays: chunk k of all vh sites is
 // contiguous, so a wavefront reading chunk k for 64 consecutive sites issues
 // one fully coalesced 1 KiB request.  The last chunk may be shorter
-// (FP32: 8 bytes, FP16: 4 bytes).
+// (FP32: 8 bytes, FP16: 4 bytes).  Reconstruct-12 formats store only the 12
+// reals of rows 0 and 1 (FP64: 6 chunks, FP32: 3 chunks).
 // ---------------------------------------------------------------------------
 template <int P> struct Prec;
 template <> struct Prec<HISQ_FP64> {
     using store = double;
     using acc = double;
     static constexpr int real_bytes = 8;
+    static constexpr int mat_bytes = 18 * 8;
 };
 template <> struct Prec<HISQ_FP32> {
     using store = float;
     using acc = float;
     static constexpr int real_bytes = 4;
+    static constexpr int mat_bytes = 18 * 4;
 };
 template <> struct Prec<HISQ_FP16N> {
     using store = _Float16;
     using acc = float;
     static constexpr int real_bytes = 2;
+    static constexpr int mat_bytes = 18 * 2;
+};
+// Reconstruct-12 links: rows 0 and 1 stored (12 reals), row 2 rebuilt.
+template <> struct Prec<HISQ_FP64R12> {
+    using store = double;
+    using acc = double;
+    static constexpr int real_bytes = 8;
+    static constexpr int mat_bytes = 12 * 8;
+};
+template <> struct Prec<HISQ_FP32R12> {
+    using store = float;
+    using acc = float;
+    static constexpr int real_bytes = 4;
+    static constexpr int mat_bytes = 12 * 4;
 };
 
-__host__ __device__ constexpr int matrix_bytes(int real_bytes) { return 18 * real_bytes; }
-__host__ __device__ constexpr int full_chunks(int real_bytes) { return (18 * real_bytes) / 16; }
-__host__ __device__ constexpr int tail_bytes(int real_bytes) { return (18 * real_bytes) % 16; }
-
-inline size_t links_bytes(const Geom &g, int real_bytes) {
-    return (size_t)2 * 2 * 4 * (size_t)g.vh * matrix_bytes(real_bytes);
+// Bytes of one stored link matrix, and the precision of the colour-vector
+// fields that go with a link precision.
+__host__ __device__ constexpr int link_matrix_bytes(int prec) {
+    return prec == HISQ_FP64 ? 144 : prec == HISQ_FP32 ? 72 : prec == HISQ_FP16N ? 36
+         : prec == HISQ_FP64R12 ? 96 : 48;
+}
+__host__ __device__ constexpr int field_prec_of(int prec) {
+    return prec == HISQ_FP64R12 ? HISQ_FP64 : prec == HISQ_FP32R12 ? HISQ_FP32 : prec;
 }
 
-// Byte offset of the block (f, p, mu).
-__host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int real_bytes) {
-    return (size_t)((f * 2 + p) * 4 + mu) * (size_t)vh * matrix_bytes(real_bytes);
+inline size_t links_bytes(const Geom &g, int mat_bytes) {
+    return (size_t)2 * 2 * 4 * (size_t)g.vh * mat_bytes;
+}
+
+// Byte offset of the block (f, p, mu) for matrices of mat_bytes bytes.
+__host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int mat_bytes) {
+    return (size_t)((f * 2 + p) * 4 + mu) * (size_t)vh * mat_bytes;
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +104,8 @@ __host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int r
 //                float norm}: one dwordx4 load fetches a whole site.
 // ---------------------------------------------------------------------------
 inline size_t field_bytes(const Geom &g, int prec, int nrhs) {
-    size_t per = prec == HISQ_FP64 ? 48 : prec == HISQ_FP32 ? 24 : 16;
+    const int fp = field_prec_of(prec);
+    size_t per = fp == HISQ_FP64 ? 48 : fp == HISQ_FP32 ? 24 : 16;
     return (size_t)nrhs * (size_t)g.vh * per;
 }
 

@@ -112,9 +112,14 @@ template <int NIN, typename A> struct HopBuf {
     cplx<A> v[NIN][3];
 };
 
-// tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b).
-template <int NIN, typename A>
-__device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &b, bool back, A sg, int nr, cplx<A> (&tmp)[NIN][3]) {
+// tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b); row 2 of a
+// reconstruct-12 link is rebuilt here, after its loads have landed.
+template <int LP, int NIN, typename A>
+__device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, A sg, int nr,
+                                          cplx<A> (&tmp)[NIN][3]) {
+    HopBuf<NIN, A> b = bin;
+    if constexpr (LinkIO<LP>::rebuild)
+        rebuild_row2<A>(b.m);
 #pragma unroll
     for (int r = 0; r < NIN; ++r) {
         if (r < nr) {
@@ -154,7 +159,7 @@ template <int LP, int FP, int NIN, typename A>
 __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
                                                  int i, const Site &s, int mu, int r0, int nr,
                                                  cplx<A> (&acc)[NIN][3]) {
-    constexpr int RB = Prec<LP>::real_bytes;
+    constexpr int MB = Prec<LP>::mat_bytes;
     const int vh = g.vh;
     const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
     const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
@@ -169,14 +174,14 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
     zero<NIN, A>(tmp);
     const int q = 1 - p;
     HopBuf<NIN, A> b0, b1;
-    hop_load<LP, FP, NIN, A>(b0, links + link_block(0, p, mu, vh, RB), vh, i, in, n1, r0, nr);
-    hop_load<LP, FP, NIN, A>(b1, links + link_block(0, q, mu, vh, RB), vh, n2, in, n2, r0, nr);
-    hop_apply<NIN, A>(b0, false, s1, nr, tmp);
-    hop_load<LP, FP, NIN, A>(b0, links + link_block(1, p, mu, vh, RB), vh, i, in, n3, r0, nr);
-    hop_apply<NIN, A>(b1, true, s2, nr, tmp);
-    hop_load<LP, FP, NIN, A>(b1, links + link_block(1, q, mu, vh, RB), vh, n4, in, n4, r0, nr);
-    hop_apply<NIN, A>(b0, false, s3, nr, tmp);
-    hop_apply<NIN, A>(b1, true, s4, nr, tmp);
+    hop_load<LP, FP, NIN, A>(b0, links + link_block(0, p, mu, vh, MB), vh, i, in, n1, r0, nr);
+    hop_load<LP, FP, NIN, A>(b1, links + link_block(0, q, mu, vh, MB), vh, n2, in, n2, r0, nr);
+    hop_apply<LP, NIN, A>(b0, false, s1, nr, tmp);
+    hop_load<LP, FP, NIN, A>(b0, links + link_block(1, p, mu, vh, MB), vh, i, in, n3, r0, nr);
+    hop_apply<LP, NIN, A>(b1, true, s2, nr, tmp);
+    hop_load<LP, FP, NIN, A>(b1, links + link_block(1, q, mu, vh, MB), vh, n4, in, n4, r0, nr);
+    hop_apply<LP, NIN, A>(b0, false, s3, nr, tmp);
+    hop_apply<LP, NIN, A>(b1, true, s4, nr, tmp);
     const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
     const A eta = (par & 1) ? (A)-1 : (A)1;
 #pragma unroll
@@ -195,7 +200,7 @@ struct HopAddr {
     bool back;
 };
 
-template <int RB, typename A>
+template <int MB, typename A>
 __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *links, int i, const Site &s, int k,
                                             A &sg) {
     const int mu = k >> 2, type = k & 3;
@@ -209,7 +214,7 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
     h.back = (type & 1) != 0;
     const int f = type >> 1;            // 0: fat X (one hop), 1: long W (three hops)
     const int lpar = h.back ? 1 - p : p;
-    h.blk = links + link_block(f, lpar, mu, g.vh, RB);
+    h.blk = links + link_block(f, lpar, mu, g.vh, MB);
     h.ilink = h.back ? nb : i;
     h.ipsi = nb;
     return h;
@@ -222,7 +227,7 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
 template <int LP, int FP, int NIN, typename A>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
                                             int r0, int nr, cplx<A> (&acc)[NIN][3]) {
-    constexpr int RB = Prec<LP>::real_bytes;
+    constexpr int MB = Prec<LP>::mat_bytes;
     const Site s = site_coords(g, p, i);
     zero<NIN, A>(acc);
     cplx<A> tmp[NIN][3];
@@ -232,7 +237,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
     bool back[2];
     auto load = [&](int k, int slot) {
         A sg;
-        const HopAddr h = hop_addr<RB, A>(g, p, links, i, s, k, sg);
+        const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
         LinkIO<LP>::load(h.blk, g.vh, h.ilink, buf[slot].m);
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
@@ -247,7 +252,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         const int cur = k & 1;
         if (k + 1 < 16)
             load(k + 1, cur ^ 1);
-        hop_apply<NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp);
+        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp);
         if ((k & 3) == 3) {
             const int mu = k >> 2;
             const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);

@@ -8,7 +8,16 @@ namespace {
 
 template <int LP>
 __device__ __forceinline__ void store_matrix(char *blk, int vh, int i, const double d[18]) {
-    if (LP == HISQ_FP64) {
+    if (LP == HISQ_FP64R12) {  // rows 0 and 1 only
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            reinterpret_cast<double2 *>(blk + (size_t)vh * 16 * k)[i] = make_double2(d[2 * k], d[2 * k + 1]);
+    } else if (LP == HISQ_FP32R12) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            reinterpret_cast<float4 *>(blk + (size_t)vh * 16 * k)[i] =
+                make_float4((float)d[4 * k], (float)d[4 * k + 1], (float)d[4 * k + 2], (float)d[4 * k + 3]);
+    } else if (LP == HISQ_FP64) {
 #pragma unroll
         for (int k = 0; k < 9; ++k)
             reinterpret_cast<double2 *>(blk + (size_t)vh * 16 * k)[i] = make_double2(d[2 * k], d[2 * k + 1]);
@@ -54,21 +63,25 @@ __global__ void __launch_bounds__(256) pack_links_kernel(Geom g, const double *f
     const int t = (int)(rest / g.nz);
     const int p = (x + y + z + t) & 1;
     const int i = (int)(lex >> 1);
-    constexpr int RB = Prec<LP>::real_bytes;
+    constexpr int MB = Prec<LP>::mat_bytes;
     for (int f = 0; f < 2; ++f) {
         const double *src = (f == 0 ? fat : naik) + gid * 18;
         double d[18];
 #pragma unroll
         for (int k = 0; k < 18; ++k)
             d[k] = src[k];
-        store_matrix<LP>(packed + link_block(f, p, mu, g.vh, RB), g.vh, i, d);
+        store_matrix<LP>(packed + link_block(f, p, mu, g.vh, MB), g.vh, i, d);
     }
 }
 
+// Unpacking a reconstruct-12 link returns the rebuilt matrix (row 2 formed in
+// the storage precision, as the Dslash forms it).
 template <int LP>
 __device__ __forceinline__ void load_matrix_f64(const char *blk, int vh, int i, double d[18]) {
     typename LinkIO<LP>::A m[18];
     LinkIO<LP>::load(blk, vh, i, m);
+    if constexpr (LinkIO<LP>::rebuild)
+        rebuild_row2(m);
 #pragma unroll
     for (int k = 0; k < 18; ++k)
         d[k] = (double)m[k];
@@ -92,10 +105,10 @@ __global__ void __launch_bounds__(256) unpack_links_kernel(Geom g, const char *p
     const int t = (int)(rest / g.nz);
     const int p = (x + y + z + t) & 1;
     const int i = (int)(lex >> 1);
-    constexpr int RB = Prec<LP>::real_bytes;
+    constexpr int MB = Prec<LP>::mat_bytes;
     for (int f = 0; f < 2; ++f) {
         double d[18];
-        load_matrix_f64<LP>(packed + link_block(f, p, mu, g.vh, RB), g.vh, i, d);
+        load_matrix_f64<LP>(packed + link_block(f, p, mu, g.vh, MB), g.vh, i, d);
         double *dst = (f == 0 ? fat : naik) + gid * 18;
 #pragma unroll
         for (int k = 0; k < 18; ++k)
@@ -190,6 +203,10 @@ hipError_t launch_pack_links(const Geom &g, int prec, const void *fat, const voi
         pack_links_kernel<HISQ_FP64><<<grid, 256, 0, st>>>(g, f, w, p);
     else if (prec == HISQ_FP32)
         pack_links_kernel<HISQ_FP32><<<grid, 256, 0, st>>>(g, f, w, p);
+    else if (prec == HISQ_FP64R12)
+        pack_links_kernel<HISQ_FP64R12><<<grid, 256, 0, st>>>(g, f, w, p);
+    else if (prec == HISQ_FP32R12)
+        pack_links_kernel<HISQ_FP32R12><<<grid, 256, 0, st>>>(g, f, w, p);
     else
         pack_links_kernel<HISQ_FP16N><<<grid, 256, 0, st>>>(g, f, w, p);
     return hipGetLastError();
@@ -206,6 +223,10 @@ hipError_t launch_unpack_links(const Geom &g, int prec, const void *packed, void
         unpack_links_kernel<HISQ_FP64><<<grid, 256, 0, st>>>(g, p, f, w);
     else if (prec == HISQ_FP32)
         unpack_links_kernel<HISQ_FP32><<<grid, 256, 0, st>>>(g, p, f, w);
+    else if (prec == HISQ_FP64R12)
+        unpack_links_kernel<HISQ_FP64R12><<<grid, 256, 0, st>>>(g, p, f, w);
+    else if (prec == HISQ_FP32R12)
+        unpack_links_kernel<HISQ_FP32R12><<<grid, 256, 0, st>>>(g, p, f, w);
     else
         unpack_links_kernel<HISQ_FP16N><<<grid, 256, 0, st>>>(g, p, f, w);
     return hipGetLastError();

@@ -39,7 +39,7 @@ std::vector<DslashShape> candidate_shapes(int nrhs, int lp) {
         for (int nin : {1, 2, 4, 8}) {
             if (nin > 1 && nin > nrhs)
                 continue;
-            if (var == VAR_SITE && lp == HISQ_FP64 && nin > 4)
+            if (var == VAR_SITE && (lp == HISQ_FP64 || lp == HISQ_FP64R12) && nin > 4)
                 continue;  // exceeds the register file (spills)
             for (int block : {64, 128, 256})
                 for (int remap : {0, 1})
@@ -138,7 +138,7 @@ hisq_status hisq_tune_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_pr
     if (s == HISQ_OK) s = set_device(ctx);
     if (s != HISQ_OK)
         return s;
-    return tune_dslash(ctx, make_geom(*lat), prec, prec, nrhs, links, in, out, static_cast<hipStream_t>(stream),
+    return tune_dslash(ctx, make_geom(*lat), prec, field_prec_of(prec), nrhs, links, in, out, static_cast<hipStream_t>(stream),
                        nullptr);
 }
 
@@ -150,7 +150,7 @@ hisq_status hisq_get_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hi
     if (s == HISQ_OK) s = check_ptr(shape, "shape");
     if (s != HISQ_OK)
         return s;
-    const DslashShape d = pick_shape(ctx, make_geom(*lat), prec, prec, nrhs);
+    const DslashShape d = pick_shape(ctx, make_geom(*lat), prec, field_prec_of(prec), nrhs);
     shape->variant = d.variant;
     shape->nin = d.nin;
     shape->block = d.block;
@@ -172,7 +172,9 @@ hisq_status hisq_set_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hi
     if (!dslash_shape_supported(d))
         return fail(HISQ_ERR_INVALID_ARG, "unsupported shape (variant %d, nin %d, block %d, remap %d)", d.variant,
                     d.nin, d.block, d.xcd_remap);
-    ctx->store(make_geom(*lat), prec, prec, nrhs, d);
+    ctx->store(make_geom(*lat), prec, field_prec_of(prec), nrhs, d);
+    if (prec == HISQ_FP16N)  // also the FP16-link, FP32-field Dslash inside mixed-precision CG
+        ctx->store(make_geom(*lat), prec, HISQ_FP32, nrhs, d);
     return HISQ_OK;
 }
 

@@ -16,8 +16,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhisq.so")
 
-HISQ_FP64, HISQ_FP32, HISQ_FP16N = 0, 1, 2
-PRECS = {"fp64": HISQ_FP64, "fp32": HISQ_FP32, "fp16n": HISQ_FP16N}
+HISQ_FP64, HISQ_FP32, HISQ_FP16N, HISQ_FP64R12, HISQ_FP32R12 = 0, 1, 2, 3, 4
+PRECS = {"fp64": HISQ_FP64, "fp32": HISQ_FP32, "fp16n": HISQ_FP16N, "fp64r12": HISQ_FP64R12,
+         "fp32r12": HISQ_FP32R12}
 HISQ_MAX_RHS = 16
 
 OK, INVALID_ARG, NOT_CONVERGED, BREAKDOWN, DEVICE, WORKSPACE, UNSUPPORTED = range(7)

@@ -64,6 +64,12 @@ def test_sizes(lib):
     assert h.hisq_field_bytes(lat, "fp16n", 1) == (V // 2) * 16
     assert h.hisq_field_bytes(lat, "fp64", 17) == 0
     assert h.hisq_field_bytes(lat, "fp64", 0) == 0
+    # reconstruct-12: rows 0 and 1 of each link; fields as the base precision
+    assert h.hisq_links_bytes(lat, "fp64r12") == 2 * 4 * V * 12 * 8
+    assert h.hisq_links_bytes(lat, "fp32r12") == 2 * 4 * V * 12 * 4
+    assert h.hisq_field_bytes(lat, "fp64r12", 2) == h.hisq_field_bytes(lat, "fp64", 2)
+    assert h.hisq_field_bytes(lat, "fp32r12", 2) == h.hisq_field_bytes(lat, "fp32", 2)
+    assert h.hisq_links_bytes(lat, 5) == 0
 
 
 def test_dslash_argument_checks(lib):
@@ -126,6 +132,7 @@ def test_workspace_queries(lib):
     probs[0].lat = h.lattice((8, 8, 8, 8), -1)
     probs[1].lat = h.lattice((4, 4, 4, 6), -1)
     assert lib.hisq_cg_batch_workspace_bytes(2, probs, 1) > 0
+    assert lib.hisq_cg_batch_workspace_bytes(2, probs, 4) == 0     # no reconstruct-12 in the batch
     probs[1].lat = h.lattice((4, 4, 4, 5), -1)
     assert lib.hisq_cg_batch_workspace_bytes(2, probs, 1) == 0
 

@@ -54,7 +54,7 @@ def test_cg_fp64_8x8x8x8(gpu_lib, t_bc):
     print(f"\n8^4 t_bc={t_bc}: GPU {info[0]['iterations']} iterations, oracle {ref.iterations}")
 
 
-@pytest.mark.parametrize("inner,m", [("fp32", 0.02), ("fp16n", 0.2)])
+@pytest.mark.parametrize("inner,m", [("fp32", 0.02), ("fp16n", 0.2), ("fp32r12", 0.02)])
 def test_mixed_precision_reliable_update_cg(gpu_lib, inner, m):
     """FP16 links perturb M_e by ~2^-12 ||D||^2 ~ 1e-2, far above the lowest
     eigenvalues at m = 0.02 (where FP16 inner iterations barely make progress,
@@ -133,7 +133,7 @@ def test_status_codes(gpu_lib):
         h.hisq_cg(lat, 0.0, l64, None, "fp64", 1, b, x, 1e-10, 100, ws)
 
 
-@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16n"])
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16n", "fp64r12", "fp32r12"])
 def test_cg_32x32x32x8_m001(gpu_lib, inner):
     """The 32^3x8 smooth-link workload at m = 0.01 to true residual 1e-10."""
     h = gpu_lib
@@ -144,3 +144,22 @@ def test_cg_32x32x32x8_m001(gpu_lib, inner):
     res, _ = oracle_residuals(h, w, lat, x, 1, w["mass"], w["src"])
     assert res[0] <= 1e-10
     print(f"\n32^3x8 {inner}: {info[0]}")
+
+
+def test_multishift_with_r12_inner_links(gpu_lib):
+    """Multi-shift CG whose Krylov iterations use reconstruct-12 FP32 links."""
+    h = gpu_lib
+    w = gen.workload_smooth((8, 8, 8, 8), 44, -1, 0.3, 1)
+    lat = h.lattice(w["dims"], w["t_bc"])
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    l12 = h.pack_links_from_host(lat, "fp32r12", w["fat"], w["naik"])
+    b = h.pack_field_from_host(lat, "fp64", w["src"][0])
+    shifts = [0.0, 0.01, 0.1]
+    xs = [h.empty_field(lat, "fp64") for _ in shifts]
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32r12", 1, len(shifts)))
+    st, info = h.hisq_multishift_cg(lat, 0.05, l64, l12, "fp32r12", shifts, b, xs, 1e-10, 20000, ws)
+    assert st == h.OK, info
+    lat_o = O.lattice_from(w)
+    for k, sh in enumerate(shifts):
+        xk = h.unpack_field_to_host(lat, "fp64", xs[k])[0]
+        assert O.true_residual(lat_o, 0.05, w["src"][0], xk, shift=sh) <= 1e-10

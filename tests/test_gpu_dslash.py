@@ -9,6 +9,10 @@ Tolerances:
              output is itself rounded to that format, so each component may
              differ by half a binary16 ulp of its site norm (2^-12 n) plus the
              FP32 accumulation error.
+  R12        reconstruct-12 links (rows 0 and 1 stored, row 2 rebuilt on the
+             GPU in the storage precision): FP64R12 <= 1e-13 against the oracle
+             on the original SU(3) links; FP32R12 <= 1e-6 against the oracle
+             on the FP32-rounded rows with row 2 rebuilt in FP64.
 """
 import numpy as np
 import pytest
@@ -71,6 +75,51 @@ def test_pack_unpack_links_format(gpu_lib, fields, prec):
     ql = O.quantized_lattice(O.lattice_from(w), prec)
     np.testing.assert_array_equal(f.cpu().numpy(), ql.X)
     np.testing.assert_array_equal(n.cpu().numpy(), ql.W)
+
+
+@pytest.mark.parametrize("prec", ["fp64r12", "fp32r12"])
+def test_pack_unpack_links_r12(gpu_lib, fields, prec):
+    """Rows 0 and 1 come back exactly as stored; row 2 is rebuilt from them."""
+    h = gpu_lib
+    w = fields((6, 4, 8, 10), -1, 1, "smooth")
+    lat = h.lattice(w["dims"], w["t_bc"])
+    packed = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    assert packed.numel() * 3 == h.hisq_links_bytes(lat, prec[:4]) * 2
+    f = torch.empty(w["fat"].shape, dtype=torch.complex128, device="cuda")
+    n = torch.empty_like(f)
+    h.hisq_unpack_links(lat, prec, packed, f, n)
+    torch.cuda.synchronize()
+    ql = O.quantized_lattice(O.lattice_from(w), prec)
+    tol = 1e-15 if prec == "fp64r12" else 1e-6
+    for got, ref, orig in ((f.cpu().numpy(), ql.X, w["fat"]), (n.cpu().numpy(), ql.W, w["naik"])):
+        np.testing.assert_array_equal(got[..., :2, :], ref[..., :2, :])
+        assert np.abs(got[..., 2, :] - ref[..., 2, :]).max() <= tol
+        assert np.abs(got - orig).max() <= (1e-14 if prec == "fp64r12" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64r12", "fp32r12"])
+@pytest.mark.parametrize("dims,t_bc", [((8, 8, 8, 8), -1), ((6, 4, 8, 10), +1), ((12, 12, 12, 4), -1)])
+def test_dslash_r12(gpu_lib, fields, prec, dims, t_bc):
+    h = gpu_lib
+    w = fields(dims, t_bc)
+    lat = h.lattice(dims, t_bc)
+    lat_o = O.lattice_from(w)
+    lat_q = O.quantized_lattice(lat_o, prec)
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    for parity in (0, 1):
+        src = w["src_o"][0] if parity == 0 else w["src"][0]
+        inp = h.pack_field_from_host(lat, prec, src)
+        out = h.empty_field(lat, prec)
+        h.hisq_dslash(lat, prec, parity, links, inp, out)
+        got = h.unpack_field_to_host(lat, prec, out)[0]
+        if prec == "fp64r12":
+            ref = lat_o.D_eo(src) if parity == 0 else lat_o.D_oe(src)
+            assert relerr(got, ref) <= 1e-13
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+        else:
+            srcq = O.quantize_field(src, prec)
+            ref = lat_q.D_eo(srcq) if parity == 0 else lat_q.D_oe(srcq)
+            assert relerr(got, ref) <= 1e-6
 
 
 @pytest.mark.parametrize("dims,t_bc", LATTICES)
@@ -152,7 +201,7 @@ def test_dslash_multi_rhs_columns(gpu_lib, fields, prec, nrhs, variant):
         assert relerr(got, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64r12", "fp32r12"])
 def test_apply_m(gpu_lib, fields, prec):
     h = gpu_lib
     dims, t_bc = (8, 8, 8, 8), -1
@@ -166,7 +215,7 @@ def test_apply_m(gpu_lib, fields, prec):
     got = h.unpack_field_to_host(lat, prec, out, 2)
     lat_q = O.quantized_lattice(O.lattice_from(w), prec)
     ref = np.stack([lat_q.M_e(0.1, O.quantize_field(s, prec)) for s in w["src"]])
-    assert relerr(got, ref) <= (1e-13 if prec == "fp64" else 2e-6)
+    assert relerr(got, ref) <= (1e-13 if prec.startswith("fp64") else 2e-6)
 
 
 def test_dslash_32x32x32x8_full_and_deterministic(gpu_lib):
@@ -210,7 +259,7 @@ def _all_shapes(nrhs):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64r12", "fp32r12"])
 def test_every_launch_shape_matches_oracle(gpu_lib, fields, prec):
     """All shapes the autotuner may pick, on a lattice whose site count is not
     a multiple of the block (ragged tail) and nrhs = 3 (partial N_inner)."""
@@ -230,7 +279,7 @@ def test_every_launch_shape_matches_oracle(gpu_lib, fields, prec):
         out.fill_(0xFF)
         h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs, ctx=ctx)
         got = h.unpack_field_to_host(lat, prec, out, nrhs)
-        assert relerr(got, ref) <= (1e-13 if prec == "fp64" else 1e-6), shape
+        assert relerr(got, ref) <= (1e-13 if prec.startswith("fp64") else 1e-6), shape
 
 
 def test_autotuner_picks_a_supported_shape(gpu_lib, fields):

@@ -45,3 +45,15 @@ def test_sources_unit_variance_and_seeded():
     np.testing.assert_array_equal(a, b)
     assert a.shape == (2, 2048, 3)
     assert abs(np.mean(np.abs(a) ** 2) - 1.0) < 0.05
+
+
+def test_ptc_initial_weights_follow_the_oracle_recipe():
+    """The benchmark draws its starting PTC weights from the generator module;
+    the draw equals the oracle's initialisation for the same seed."""
+    import numpy as np
+    from oracle import ptc
+    a = gen.ptc_initial_weights(7, 0.2)
+    b = ptc.init_weights(np.random.default_rng(7), scale=0.2)
+    assert [x.shape for x in a] == [(8, 1, 9), (8, 8, 9), (1, 8, 9)]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
