@@ -161,75 +161,101 @@ __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *li
         FieldIO<HISQ_FP32>::template store<float>(gin, g.vh, 2 * ci + par, i, acc[ci]);
 }
 
-// Block partials of dL/dw[co][ci][p] = sum_x <(T_p in_ci)(x), g_co(x)> for
-// the (ci, p) pair blockIdx.y: partials[(pair * nblk + blk) * 2 COUT + k].
+// Block partials of dL/dw[co][ci][p] = sum_x <(T_p in_ci)(x), g_co(x)>, one
+// thread per site for all (ci, p) pairs: g_out of the site and each path's
+// link are loaded once and reused by every input channel.  Each wave sums
+// its 2 COUT values of a pair (halving exchanges) into LDS without a block
+// barrier; at the end the block adds the waves in order (deterministic) into
+// partials[(pair * 2 COUT + k) * gridDim.x + blockIdx.x], pair = ci * 9 + p.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *links, const void *in,
                                                          const void *gout, double *partials) {
+    constexpr int NV = 2 * COUT;
+    constexpr int NPAIR = CIN * PTC_PATHS;
+    __shared__ double lds[(PB / 64) * NPAIR * NV];  // per wave, per pair, NV totals
     const int gid = blockIdx.x * PB + threadIdx.x;
-    const int pair = blockIdx.y;
-    const int ci = pair / PTC_PATHS, p = pair - ci * PTC_PATHS;
-    double acc[2 * COUT];
+    const bool valid = gid < 2 * g.vh;
+    const int par = valid && gid >= g.vh;
+    const int i = valid ? gid - par * g.vh : 0;
+    const Site s = site_coords(g, par, i);
+    cplx<float> gv[COUT][3];
 #pragma unroll
-    for (int k = 0; k < 2 * COUT; ++k)
-        acc[k] = 0.0;
-    if (gid < 2 * g.vh) {
-        const int par = gid >= g.vh;
-        const int i = gid - par * g.vh;
-        const Site s = site_coords(g, par, i);
-        const Hop h = path_hop(g, s, par, i, p);
-        cplx<float> v[3], t[3];
-        FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
-        if (p > 0) {
-            float m[18];
-            LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
-            transport(m, h.back, h.sg, v, t);
+    for (int co = 0; co < COUT; ++co) {
+        if (valid) {
+            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + par, i, gv[co]);
         } else {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                t[a] = v[a];
-        }
-#pragma unroll
-        for (int co = 0; co < COUT; ++co) {
-            cplx<float> gv[3];
-            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + par, i, gv);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                // conj(t) * g
-                acc[2 * co] += (double)t[a].re * gv[a].re + (double)t[a].im * gv[a].im;
-                acc[2 * co + 1] += (double)t[a].re * gv[a].im - (double)t[a].im * gv[a].re;
-            }
+                gv[co][a].re = gv[co][a].im = 0.f;
         }
     }
-    __shared__ double lds[4 * 2 * COUT];
-    block_sum<2 * COUT>(acc, lds);
-    if (threadIdx.x == 0) {
-        double *dst = partials + ((size_t)pair * gridDim.x + blockIdx.x) * 2 * COUT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int p = 0; p < PTC_PATHS; ++p) {
+        const Hop h = path_hop(g, s, par, i, p);
+        float m[18];
+        if (p > 0 && valid)
+            LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
+        for (int ci = 0; ci < CIN; ++ci) {
+            double acc[NV];
 #pragma unroll
-        for (int k = 0; k < 2 * COUT; ++k)
-            dst[k] = acc[k];
+            for (int k = 0; k < NV; ++k)
+                acc[k] = 0.0;
+            if (valid) {
+                cplx<float> v[3], t[3];
+                FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
+                if (p > 0) {
+                    transport(m, h.back, h.sg, v, t);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        t[a] = v[a];
+                }
+#pragma unroll
+                for (int co = 0; co < COUT; ++co)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        // conj(t) * g
+                        acc[2 * co] += (double)t[a].re * gv[co][a].re + (double)t[a].im * gv[co][a].im;
+                        acc[2 * co + 1] += (double)t[a].re * gv[co][a].im - (double)t[a].im * gv[co][a].re;
+                    }
+            }
+            wave_sum_multi<NV>(acc);
+            if ((lane & (64 / NV - 1)) == 0)
+                lds[(wave * NPAIR + ci * PTC_PATHS + p) * NV + wave_multi_index<NV>(lane)] = acc[0];
+        }
+    }
+    // one barrier per block: the waves' totals of every pair, added in wave order
+    __syncthreads();
+    for (int k = threadIdx.x; k < NPAIR * NV; k += PB) {
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < PB / 64; ++w)
+            tot += lds[w * NPAIR * NV + k];
+        partials[(size_t)k * gridDim.x + blockIdx.x] = tot;
     }
 }
 
-// grad[(co * CIN + ci) * 9 + p] += sum over blocks, one thread per real value,
-// blocks summed in order.
-__global__ void wgrad_reduce_kernel(int cin, int cout, int nblk, const double *partials, double2 *grad) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;  // (pair, co, re/im)
-    const int total = cin * PTC_PATHS * cout * 2;
-    if (k >= total)
+// grad[(co * CIN + ci) * 9 + p] += sum over the nblk block partials, one
+// wavefront per real value (slot = pair * 2 COUT + 2 co + re/im), summed in a
+// fixed order (wave_sum_slot).
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(int cin, int cout, int nblk, const double *partials,
+                                                           double2 *grad) {
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nslots = cin * PTC_PATHS * cout * 2;
+    if (slot >= nslots)  // uniform over the wavefront
         return;
-    const int pair = k / (2 * cout);
-    const int rem = k - pair * 2 * cout;
+    const double sum = wave_sum_slot(partials + (size_t)slot * nblk, nblk);
+    if ((threadIdx.x & 63) != 0)
+        return;
+    const int pair = slot / (2 * cout);
+    const int rem = slot - pair * 2 * cout;
     const int co = rem >> 1, part = rem & 1;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b)
-        s += partials[((size_t)pair * nblk + b) * 2 * cout + rem];
     const int ci = pair / PTC_PATHS, p = pair - ci * PTC_PATHS;
     double2 *dst = grad + (co * cin + ci) * PTC_PATHS + p;
     if (part == 0)
-        dst->x += s;
+        dst->x += sum;
     else
-        dst->y += s;
+        dst->y += sum;
 }
 
 // a0 = (in_even, 0 on odd sites), channel 0.
@@ -401,7 +427,7 @@ hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links,
 hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, const void *in, const void *g_out,
                            double *partials, double2 *grad, hipStream_t st) {
     const int nblk = ptc_blocks(g);
-    const dim3 grid((unsigned)nblk, (unsigned)(cin * PTC_PATHS));
+    const dim3 grid((unsigned)nblk);
     if (cin == 1 && cout == PTC_CH)
         layer_bwd_w_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
     else if (cin == PTC_CH && cout == PTC_CH)
@@ -413,8 +439,8 @@ hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const int total = cin * PTC_PATHS * cout * 2;
-    wgrad_reduce_kernel<<<(total + 255) / 256, 256, 0, st>>>(cin, cout, nblk, partials, grad);
+    const int nslots = cin * PTC_PATHS * cout * 2;
+    wgrad_reduce_kernel<<<(nslots + 3) / 4, 256, 0, st>>>(cin, cout, nblk, partials, grad);
     return hipGetLastError();
 }
 

@@ -36,6 +36,40 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
+// Sums of NV values (NV a power of two <= 64) over the wavefront with
+// log2(NV) halving exchanges: at offset 32, 16, ... each lane gives the
+// partner half of its remaining values and keeps the other half, so NV/2 +
+// NV/4 + ... + 1 shuffles replace NV full trees; the remaining offsets finish
+// one value per lane.  Afterwards v[0] of lane l holds the total of value
+// index wave_multi_index<NV>(l) (the same in every lane of a group of
+// 64 / NV).  The order of additions is fixed: deterministic.
+template <int NV> __device__ __forceinline__ int wave_multi_index(int lane) {
+    int idx = 0;
+#pragma unroll
+    for (int o = 32, n = NV; n > 1; o >>= 1, n >>= 1)
+        idx = 2 * idx + ((lane & o) ? 1 : 0);
+    return idx;
+}
+
+template <int NV> __device__ __forceinline__ void wave_sum_multi(double (&v)[NV]) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+    const int lane = threadIdx.x & 63;
+    int o = 32;
+#pragma unroll
+    for (int n = NV; n > 1; n >>= 1, o >>= 1) {
+        const bool upper = (lane & o) != 0;
+#pragma unroll
+        for (int k = 0; k < n / 2; ++k) {
+            const double give = upper ? v[k] : v[k + n / 2];
+            const double keep = upper ? v[k + n / 2] : v[k];
+            v[k] = keep + __shfl_xor(give, o, 64);
+        }
+    }
+#pragma unroll
+    for (; o > 0; o >>= 1)
+        v[0] += __shfl_xor(v[0], o, 64);
+}
+
 // Sum of one slot by one wavefront: lane l adds partials l, l + 64, l + 128,
 // ... in that order (eight loads in flight per step), then the wave adds the
 // lanes in a fixed shuffle tree.  The result is the same whichever wave runs
