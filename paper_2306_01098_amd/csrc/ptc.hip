@@ -211,13 +211,17 @@ __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *lin
                         t[a] = v[a];
                 }
 #pragma unroll
-                for (int co = 0; co < COUT; ++co)
+                for (int co = 0; co < COUT; ++co) {
+                    // conj(t) . g over the colours in FP32, widened once per value
+                    float re = 0.f, im = 0.f;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        // conj(t) * g
-                        acc[2 * co] += (double)t[a].re * gv[co][a].re + (double)t[a].im * gv[co][a].im;
-                        acc[2 * co + 1] += (double)t[a].re * gv[co][a].im - (double)t[a].im * gv[co][a].re;
+                        re = fmaf(t[a].re, gv[co][a].re, fmaf(t[a].im, gv[co][a].im, re));
+                        im = fmaf(t[a].re, gv[co][a].im, fmaf(-t[a].im, gv[co][a].re, im));
                     }
+                    acc[2 * co] = (double)re;
+                    acc[2 * co + 1] = (double)im;
+                }
             }
             wave_sum_multi<NV>(acc);
             if ((lane & (64 / NV - 1)) == 0)
