@@ -70,7 +70,8 @@ def parse():
                     help="comma list of extra workload legs to add to the JSON line: "
                          "w1 (8^4 FP64 CG), w3 (48^3x12 16-rhs Dslash/CG and 14-shift CG), "
                          "w4 (uneven batch of 64), w5 (32^4 PTC-preconditioned FCG vs mixed CG), "
-                         "ptc (32^4 network forward/backward kernel rates)")
+                         "ptc (32^4 network forward/backward kernel rates), "
+                         "pbp (32^3x8 stochastic chiral condensate, 32 noise vectors)")
     return ap.parse_args()
 
 
@@ -277,6 +278,30 @@ def leg_w5(h, gen, O, torch, ntrain=256, ntest=4, epochs=12):
     out["iteration_ratio_cg_over_fcg"] = round(float(np.mean([c[1] for c in cg]) / np.mean([f[1] for f in fcg])), 3)
     out["time_ratio_cg_over_fcg"] = round(float(np.mean([c[0] for c in cg]) / np.mean([f[0] for f in fcg])), 3)
     return out
+
+
+def leg_pbp(h, gen, O, torch, nnoise=32):
+    """32^3x8 smooth links, m = 0.01: stochastic chiral condensate from 32
+    Gaussian noise vectors, solved as two 16-rhs reliable-update CGs (FP32
+    links) to 1e-10."""
+    import numpy as np
+    w = gen.workload_2()
+    dims, m = w["dims"], w["mass"]
+    lat = h.lattice(dims, w["t_bc"])
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+    noise = h.pack_field_from_host(lat, "fp64", gen.gaussian_half_field(gen.rng_for(2, 60), dims, nnoise))
+    x = h.empty_field(lat, "fp64", nnoise)
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 16, 0))
+    for rep in range(2):      # the first call also loads the code objects
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, pbp, err, smp, info = h.hisq_chiral_condensate(lat, m, l64, l32, "fp32", nnoise, noise, x, 1e-10,
+                                                           40000, ws)
+        dt = time.perf_counter() - t0
+    return {"pbp": pbp, "stat_err": err, "nnoise": nnoise, "seconds": round(dt, 4), "status": st,
+            "iterations_max": max(i["iterations"] for i in info),
+            "max_true_residual": max(i["true_residual"] for i in info)}
 
 
 def ptc_flop_per_site():
@@ -535,7 +560,7 @@ def main():
         result["workloads"] = {}
         for leg in legs:
             log(f"leg {leg} ...")
-            fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc}[leg]
+            fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc, "pbp": leg_pbp}[leg]
             t0 = time.perf_counter()
             result["workloads"][leg] = fn(h, gen, O, torch)
             result["workloads"][leg]["leg_wall_s"] = round(time.perf_counter() - t0, 1)

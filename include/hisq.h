@@ -195,6 +195,31 @@ hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, con
                     const void *links_inner, hisq_prec inner, int32_t nrhs, const void *b, void *x, double tol,
                     int32_t max_iter, void *ws, size_t ws_bytes, hisq_solve_info *info, void *stream);
 
+/* Stochastic chiral condensate (an observable of Sec. 3.3, measured there with
+ * a small number of random vectors):
+ *   pbp = (1/V) Tr (D + m)^-1 = (2 m / V) Tr_e M_e^-1,
+ * (the odd-site block has the spectrum of M_e and D (m^2 - D^2)^-1 is
+ * traceless), estimated as the mean of s_i = (2 m / V) Re <eta_i, M_e^-1 eta_i>
+ * over nnoise caller-drawn noise vectors with E[eta eta^+] = 1 (e.g. complex
+ * Gaussian with E|eta_k|^2 = 1).  The solves run as multi-RHS hisq_cg in
+ * groups of up to HISQ_MAX_RHS; the dot products are FP64 reductions on the
+ * device.
+ *   noise    packed HISQ_FP64 even fields [nnoise]
+ *   x        packed HISQ_FP64 even fields [nnoise] (overwritten with
+ *            M_e^-1 eta_i; initial guess zero); must not alias noise
+ *   samples  host array [nnoise] or NULL: the s_i
+ *   pbp      host pointer: the mean; err host pointer or NULL: its standard
+ *            error (NaN for nnoise = 1)
+ *   ws       workspace of hisq_cg_workspace_bytes(lat, inner, min(nnoise, 16), 0)
+ *   info     host array [nnoise] or NULL
+ * Other arguments and statuses as for hisq_cg (the worst status of the
+ * groups).  Synchronous. */
+hisq_status hisq_chiral_condensate(hisq_context *ctx, const hisq_lattice *lat, double mass,
+                                   const void *links_f64, const void *links_inner, hisq_prec inner,
+                                   int32_t nnoise, const void *noise, void *x, double tol, int32_t max_iter,
+                                   void *ws, size_t ws_bytes, double *samples, double *pbp, double *err,
+                                   hisq_solve_info *info, void *stream);
+
 /* Multi-shift CG (Sec. 3.2): solve (m^2 - D_eo D_oe + shifts[k]) x[k] = b for
  * nshift (1..32) shifts at the cost of one operator application per iteration:
  * the Krylov space of the smallest shift is built and the other shifts follow

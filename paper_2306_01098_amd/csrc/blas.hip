@@ -243,6 +243,27 @@ __global__ void __launch_bounds__(BLK) norm2_kernel(int vh, const void *v, doubl
         partials[blockIdx.x] = part[0];
 }
 
+// Block partials of Re <a_r, b_r> for FP64 fields, column r = blockIdx.y.
+__global__ void __launch_bounds__(BLK) dot_re_kernel(int vh, const void *a, const void *b, double *partials) {
+    __shared__ double lds[4];
+    const int r = blockIdx.y;
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    double part[1] = {0.0};
+    if (i < vh) {
+        cplx<double> u[3], v[3];
+        FieldIO<HISQ_FP64>::template load<double>(a, vh, r, i, u);
+        FieldIO<HISQ_FP64>::template load<double>(b, vh, r, i, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            part[0] = fma(u[c].re, v[c].re, part[0]);
+            part[0] = fma(u[c].im, v[c].im, part[0]);
+        }
+    }
+    block_sum<1>(part, lds);
+    if (threadIdx.x == 0)
+        partials[(size_t)r * gridDim.x + blockIdx.x] = part[0];
+}
+
 // dst = src for n fields, with precision conversion.
 template <int FS, int FD>
 __global__ void __launch_bounds__(BLK) copy_kernel(int vh, int n, const void *src, void *dst) {
@@ -303,6 +324,12 @@ hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, h
     norm2_kernel<<<grid_for(vh), BLK, 0, st>>>(vh, v, partials);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? launch_sum_partials(partials, 1, blas_blocks(vh), out2, 1, nullptr, st) : e;
+}
+
+hipError_t launch_dot_re(int vh, int n, const void *a, const void *b, double *partials, double *out, hipStream_t st) {
+    dot_re_kernel<<<grid_for(vh, n), BLK, 0, st>>>(vh, a, b, partials);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_sum_partials(partials, n, blas_blocks(vh), out, 1, nullptr, st) : e;
 }
 
 hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst, hipStream_t st) {

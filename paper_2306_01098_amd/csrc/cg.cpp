@@ -645,6 +645,77 @@ hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, con
     return run_cg(S, 0.0, nrhs, b, x, tol, max_iter, delta, info, nullptr);
 }
 
+hisq_status hisq_chiral_condensate(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                                   const void *links_inner, hisq_prec inner, int32_t nnoise, const void *noise,
+                                   void *x, double tol, int32_t max_iter, void *ws, size_t ws_bytes,
+                                   double *samples, double *pbp, double *err, hisq_solve_info *info, void *stream) {
+    hisq_status s = check_solver_args(lat, mass, links_f64, links_inner, inner, ws);
+    if (s == HISQ_OK && nnoise < 1)
+        s = fail(HISQ_ERR_INVALID_ARG, "nnoise = %d must be >= 1", nnoise);
+    if (s == HISQ_OK) s = check_ptr(noise, "noise");
+    if (s == HISQ_OK) s = check_ptr(x, "x");
+    if (s == HISQ_OK) s = check_ptr(pbp, "pbp");
+    if (s == HISQ_OK && noise == x)
+        s = fail(HISQ_ERR_INVALID_ARG, "noise and x must not alias");
+    if (s != HISQ_OK)
+        return s;
+    const Geom g = make_geom(*lat);
+    const int group = std::min<int>(nnoise, HISQ_MAX_RHS);
+    const Layout L = make_layout(g, inner, group, 0);
+    if (ws_bytes < L.total)
+        return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, L.total);
+    const size_t fb = field_bytes(g, HISQ_FP64, 1);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    double *partials = reinterpret_cast<double *>(static_cast<char *>(ws) + L.partials);
+    double *dots_d = reinterpret_cast<double *>(static_cast<char *>(ws) + L.scal) + 32;
+    std::vector<double> dots(nnoise);
+    std::vector<hisq_solve_info> inf(HISQ_MAX_RHS);
+    hisq_status worst = HISQ_OK;
+    for (int j0 = 0; j0 < nnoise; j0 += group) {
+        const int n = std::min(group, nnoise - j0);
+        const char *b = static_cast<const char *>(noise) + (size_t)j0 * fb;
+        char *xj = static_cast<char *>(x) + (size_t)j0 * fb;
+        hipError_t e = hipMemsetAsync(xj, 0, (size_t)n * fb, st);
+        if (e != hipSuccess)
+            return device_fail(e, "condensate: zero x");
+        s = hisq_cg(ctx, lat, mass, links_f64, links_inner, inner, n, b, xj, tol, max_iter, ws, ws_bytes,
+                    inf.data(), stream);
+        if (s != HISQ_OK && s != HISQ_ERR_NOT_CONVERGED && s != HISQ_ERR_BREAKDOWN)
+            return s;
+        if (s != HISQ_OK && worst == HISQ_OK)
+            worst = s;
+        if (info)
+            for (int k = 0; k < n; ++k)
+                info[j0 + k] = inf[k];
+        e = launch_dot_re(g.vh, n, b, xj, partials, dots_d, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dots.data() + j0, dots_d, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "condensate: dot products");
+    }
+    // s_i = (2 m / V) Re <eta_i, M_e^-1 eta_i>; mean and standard error
+    const double scale = 2.0 * mass / (2.0 * (double)g.vh);
+    double mean = 0.0;
+    for (int k = 0; k < nnoise; ++k) {
+        const double v = scale * dots[k];
+        if (samples)
+            samples[k] = v;
+        mean += v;
+    }
+    mean /= nnoise;
+    double var = 0.0;
+    for (int k = 0; k < nnoise; ++k) {
+        const double d = scale * dots[k] - mean;
+        var += d * d;
+    }
+    *pbp = mean;
+    if (err)
+        *err = nnoise > 1 ? std::sqrt(var / (nnoise - 1) / nnoise) : std::nan("");
+    return worst;
+}
+
 hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
                                const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
                                const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,

@@ -40,6 +40,8 @@ hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStre
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
                            double *out2, hipStream_t st);
 hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, hipStream_t st);
+// out[r] = Re <a_r, b_r> for n FP64 fields (partials: n * blas_blocks(vh) doubles).
+hipError_t launch_dot_re(int vh, int n, const void *a, const void *b, double *partials, double *out, hipStream_t st);
 // dst = src for n16 16-byte chunks (non-temporal streaming copy).
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t st);
 // out[s * stride] = sum over nblk block partials of slot s (one-block kernel);

@@ -86,6 +86,9 @@ _SIGS = {
     "hisq_cg": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32, _vp, _vp,
                                ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_size_t,
                                ctypes.POINTER(hisq_solve_info), _vp]),
+    "hisq_chiral_condensate": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32,
+                                              _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_size_t,
+                                              _vp, _vp, _vp, _vp, _vp]),
     "hisq_multishift_cg": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double), _vp, ctypes.POINTER(_vp),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_size_t,
@@ -208,7 +211,9 @@ def empty_links(lat, prec, device="cuda") -> torch.Tensor:
 
 
 def empty_field(lat, prec, nrhs: int = 1, device="cuda") -> torch.Tensor:
-    return torch.empty(hisq_field_bytes(lat, prec, nrhs), dtype=torch.uint8, device=device)
+    """Room for nrhs packed fields (any number; the C calls take at most
+    HISQ_MAX_RHS at a time)."""
+    return torch.empty(int(nrhs) * hisq_field_bytes(lat, prec, 1), dtype=torch.uint8, device=device)
 
 
 def hisq_pack_links(lat, prec, fat_c128: torch.Tensor, naik_c128: torch.Tensor, packed: torch.Tensor,
@@ -328,6 +333,25 @@ def hisq_cg(lat, mass: float, links_f64, links_inner, inner, nrhs: int, b, x, to
     if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
         _check(st, "hisq_cg")
     return st, [info[k].as_dict() for k in range(int(nrhs))]
+
+
+def hisq_chiral_condensate(lat, mass: float, links_f64, links_inner, inner, nnoise: int, noise, x, tol: float,
+                           max_iter: int, ws, ctx=None, stream=None, check: bool = True):
+    """Returns (status, pbp, err, samples list, [info dict per noise vector])."""
+    fb = hisq_field_bytes(lat, "fp64", 1)
+    smp = (ctypes.c_double * int(nnoise))()
+    info = (hisq_solve_info * int(nnoise))()
+    pbp, err = ctypes.c_double(), ctypes.c_double()
+    lin = None if links_inner is None else _ptr(links_inner, "links_inner", hisq_links_bytes(lat, inner))
+    st = load().hisq_chiral_condensate(_ctx(ctx), ctypes.byref(lat), float(mass),
+                                       _ptr(links_f64, "links_f64", hisq_links_bytes(lat, "fp64")), lin,
+                                       _prec(inner), int(nnoise), _ptr(noise, "noise", nnoise * fb),
+                                       _ptr(x, "x", nnoise * fb), float(tol), int(max_iter),
+                                       _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), smp, ctypes.byref(pbp),
+                                       ctypes.byref(err), info, _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_chiral_condensate")
+    return st, pbp.value, err.value, list(smp), [info[k].as_dict() for k in range(int(nnoise))]
 
 
 def hisq_multishift_cg(lat, mass: float, links_f64, links_inner, inner, shifts, b, xs, tol, max_iter: int,
@@ -496,12 +520,17 @@ def pack_links_from_host(lat, prec, fat, naik, ctx=None) -> torch.Tensor:
 
 
 def pack_field_from_host(lat, prec, half, ctx=None) -> torch.Tensor:
+    """Any number of fields: packed column by column in groups of HISQ_MAX_RHS
+    (the packed layout of n fields is the n single fields one after another)."""
     half = torch.as_tensor(half, dtype=torch.complex128)
     if half.dim() == 2:
         half = half[None]
     nrhs = half.shape[0]
-    packed = empty_field(lat, prec, nrhs)
-    hisq_pack_field(lat, prec, nrhs, half.contiguous().cuda(), packed, ctx=ctx)
+    one = hisq_field_bytes(lat, prec, 1)
+    packed = torch.empty(nrhs * one, dtype=torch.uint8, device="cuda")
+    for k in range(0, nrhs, HISQ_MAX_RHS):
+        n = min(HISQ_MAX_RHS, nrhs - k)
+        hisq_pack_field(lat, prec, n, half[k:k + n].contiguous().cuda(), packed[k * one:(k + n) * one], ctx=ctx)
     return packed
 
 
@@ -509,7 +538,10 @@ def unpack_field_to_host(lat, prec, packed, nrhs: int = 1, ctx=None):
     vol = 1
     for d in lat.dims:
         vol *= d
+    one = hisq_field_bytes(lat, prec, 1)
     out = torch.empty((nrhs, vol // 2, 3), dtype=torch.complex128, device="cuda")
-    hisq_unpack_field(lat, prec, nrhs, packed, out, ctx=ctx)
+    for k in range(0, nrhs, HISQ_MAX_RHS):
+        n = min(HISQ_MAX_RHS, nrhs - k)
+        hisq_unpack_field(lat, prec, n, packed[k * one:(k + n) * one], out[k:k + n], ctx=ctx)
     torch.cuda.synchronize()
     return out.cpu().numpy()

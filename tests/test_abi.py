@@ -167,3 +167,19 @@ def test_stream_copy_argument_checks(lib):
     assert lib.hisq_stream_copy(None, p(4096), p(4096 + 16), 64, None) == h.INVALID_ARG
     assert b"overlap" in lib.hisq_last_error()
     assert lib.hisq_stream_copy(None, None, p(1 << 20), 64, None) == h.INVALID_ARG
+
+
+def test_condensate_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    lat = ctypes.byref(h.lattice((4, 4, 4, 4), -1))
+    p = ctypes.c_void_p
+    out = ctypes.c_double()
+    # nnoise 0, noise aliasing x, NULL pbp, mass 0
+    assert lib.hisq_chiral_condensate(None, lat, 0.1, p(16), None, 0, 0, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                                      None, ctypes.byref(out), None, None, None) == h.INVALID_ARG
+    assert lib.hisq_chiral_condensate(None, lat, 0.1, p(16), None, 0, 2, p(32), p(32), 1e-8, 10, p(64), 1 << 20,
+                                      None, ctypes.byref(out), None, None, None) == h.INVALID_ARG
+    assert lib.hisq_chiral_condensate(None, lat, 0.1, p(16), None, 0, 2, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                                      None, None, None, None, None) == h.INVALID_ARG
+    assert lib.hisq_chiral_condensate(None, lat, 0.0, p(16), None, 0, 2, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
+                                      None, ctypes.byref(out), None, None, None) == h.INVALID_ARG
