@@ -71,7 +71,8 @@ def parse():
                          "w1 (8^4 FP64 CG), w3 (48^3x12 16-rhs Dslash/CG and 14-shift CG), "
                          "w4 (uneven batch of 64), w5 (32^4 PTC-preconditioned FCG vs mixed CG), "
                          "ptc (32^4 network forward/backward kernel rates), "
-                         "pbp (32^3x8 stochastic chiral condensate, 32 noise vectors)")
+                         "pbp (32^3x8 stochastic chiral condensate, 32 noise vectors), "
+                         "dslash16 (48^3x12 16-rhs FP32 Dslash alone)")
     return ap.parse_args()
 
 
@@ -97,6 +98,33 @@ def leg_w1(h, gen, O, torch):
     out["fp64_cg"] = {"seconds": round(dt, 5), "status": st, "iterations": info[0]["iterations"],
                       "true_residual": info[0]["true_residual"]}
     return out
+
+
+def leg_dslash16(h, gen, O, torch):
+    """48^3x12 smooth links: the 16-rhs FP32 Dslash alone (default shape), 23
+    launches, for kernel timing and hardware counters."""
+    import numpy as np
+    w = gen.workload_3()
+    dims = w["dims"]
+    lat = h.lattice(dims, w["t_bc"])
+    vh = int(np.prod(dims)) // 2
+    l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, "fp32", w["src"])
+    o = h.empty_field(lat, "fp32", 16)
+    for _ in range(3):
+        h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 20
+    byt = vh * (288 + 12 * 16) * 4
+    return {"us": round(t * 1e6, 1), "GB/s": round(byt / t / 1e9, 1),
+            "TFLOP/s": round(vh * 16 * DSLASH_FLOP_PER_SITE / t / 1e12, 2),
+            "shape": list(h.hisq_get_dslash_shape(lat, "fp32", 16, None))}
 
 
 def leg_w3(h, gen, O, torch):
@@ -560,7 +588,8 @@ def main():
         result["workloads"] = {}
         for leg in legs:
             log(f"leg {leg} ...")
-            fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc, "pbp": leg_pbp}[leg]
+            fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc, "pbp": leg_pbp,
+                  "dslash16": leg_dslash16}[leg]
             t0 = time.perf_counter()
             result["workloads"][leg] = fn(h, gen, O, torch)
             result["workloads"][leg]["leg_wall_s"] = round(time.perf_counter() - t0, 1)
