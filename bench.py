@@ -72,7 +72,7 @@ def parse():
                          "w4 (uneven batch of 64), w5 (32^4 PTC-preconditioned FCG vs mixed CG), "
                          "ptc (32^4 network forward/backward kernel rates), "
                          "pbp (32^3x8 stochastic chiral condensate, 32 noise vectors), "
-                         "dslash16 (48^3x12 16-rhs FP32 Dslash alone)")
+                         "dslash16 (48^3x12 16-rhs FP32 Dslash alone), smear (32^4 HISQ link smearing)")
     return ap.parse_args()
 
 
@@ -332,6 +332,27 @@ def leg_pbp(h, gen, O, torch, nnoise=32):
             "max_true_residual": max(i["true_residual"] for i in info)}
 
 
+def leg_smear(h, gen, O, torch):
+    """HISQ link smearing (two levels, U(3) projection, Naik) of 32^4 thin
+    smooth links, FP64."""
+    import numpy as np
+    dims = (32, 32, 32, 32)
+    U = gen.smooth_links(dims, gen.rng_for(6, gen.FIELD_FAT), 0.3)
+    lat = h.lattice(dims, -1)
+    thin = torch.from_numpy(U).cuda()
+    del U
+    fat, naik = torch.empty_like(thin), torch.empty_like(thin)
+    ws = h.empty_workspace(h.hisq_smear_workspace_bytes(lat))
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.hisq_smear_links(lat, thin, fat, naik, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    V = int(np.prod(dims))
+    return {"seconds": round(dt, 4), "lattice": list(dims), "links_per_second": round(4 * V / dt, 1)}
+
+
 def ptc_flop_per_site():
     """Model FLOP per lattice site of one network application and of one
     backward pass (input gradient + weight gradient): a transported colour
@@ -589,7 +610,7 @@ def main():
         for leg in legs:
             log(f"leg {leg} ...")
             fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc, "pbp": leg_pbp,
-                  "dslash16": leg_dslash16}[leg]
+                  "dslash16": leg_dslash16, "smear": leg_smear}[leg]
             t0 = time.perf_counter()
             result["workloads"][leg] = fn(h, gen, O, torch)
             result["workloads"][leg]["leg_wall_s"] = round(time.perf_counter() - t0, 1)

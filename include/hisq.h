@@ -153,6 +153,20 @@ hisq_status hisq_dslash(hisq_context *ctx, const hisq_lattice *lat, hisq_prec pr
                         int32_t out_parity, const void *links, const void *in, void *out,
                         int32_t nrhs, void *stream);
 
+/* HISQ link smearing (the two-level treatment of Sec. 3.1): from thin links
+ * U, level 1 (1-link 1/8, 3-link staples 1/16, 5-link 1/64, 7-link 1/384)
+ * gives V; Y = V (V^+ V)^(-1/2) projects it to U(3); level 2 from Y (1-link
+ * 1, 3-link 1/16, 5-link 1/64, 7-link 1/384, Lepage -1/8) gives the fat links
+ * X, and W_mu(x) = c_Naik Y_mu(x) Y_mu(x+mu) Y_mu(x+2mu) with
+ * c_Naik = -1/24 + naik_eps/8 the Naik links; links periodic.  All three
+ * fields are device complex128 arrays in the canonical layout
+ * (4, Nt, Nz, Ny, Nx, 3, 3) (pass fat and naik to hisq_pack_links).  FP64.
+ *   ws  workspace of hisq_smear_workspace_bytes(lat) bytes (44 matrices per site).
+ * thin, fat and naik must be distinct.  Asynchronous. */
+size_t hisq_smear_workspace_bytes(const hisq_lattice *lat);
+hisq_status hisq_smear_links(hisq_context *ctx, const hisq_lattice *lat, const void *thin_c128, double naik_eps,
+                             void *fat_c128, void *naik_c128, void *ws, size_t ws_bytes, void *stream);
+
 /* Bandwidth reference for the roofline: dst = src for `bytes` bytes with the
  * library's streaming copy kernel (16-byte loads and stores, four per
  * thread, non-temporal).  bytes must be a positive multiple of 16 and both

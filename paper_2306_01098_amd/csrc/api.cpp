@@ -82,12 +82,6 @@ DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrh
 
 }  // namespace hisq
 
-#define TRY(expr)                        \
-    do {                                 \
-        const hisq_status _s = (expr);   \
-        if (_s != HISQ_OK)               \
-            return _s;                   \
-    } while (0)
 
 extern "C" {
 

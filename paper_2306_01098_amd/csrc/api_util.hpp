@@ -42,6 +42,14 @@ hisq_status check_prec(int prec);
 hisq_status check_nrhs(int nrhs);
 hisq_status check_ptr(const void *p, const char *name);
 hisq_status set_device(hisq_context *ctx);
+// Return the status of expr from the calling entry point unless it is HISQ_OK.
+#define TRY(expr)                        \
+    do {                                 \
+        const hisq_status _s = (expr);   \
+        if (_s != HISQ_OK)               \
+            return _s;                   \
+    } while (0)
+
 DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs);
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs);
 

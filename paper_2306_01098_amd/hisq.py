@@ -77,6 +77,8 @@ _SIGS = {
     "hisq_apply_m": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
                                     ctypes.c_int32, _vp]),
     "hisq_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "hisq_smear_workspace_bytes": (ctypes.c_size_t, [_LAT]),
+    "hisq_smear_links": (ctypes.c_int, [_vp, _LAT, _vp, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_tune_dslash": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "hisq_get_dslash_shape": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32,
                                              ctypes.POINTER(hisq_dslash_shape)]),
@@ -287,6 +289,22 @@ def hisq_stream_copy(src, dst, nbytes: int | None = None, ctx=None, stream=None)
     n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     _check(load().hisq_stream_copy(_ctx(ctx), _ptr(src, "src", n), _ptr(dst, "dst", n), n, _stream(stream)),
            "hisq_stream_copy")
+
+
+def hisq_smear_workspace_bytes(lat) -> int:
+    return int(load().hisq_smear_workspace_bytes(ctypes.byref(lat)))
+
+
+def hisq_smear_links(lat, thin_c128, fat_c128, naik_c128, ws, naik_eps: float = 0.0, ctx=None, stream=None):
+    """HISQ fat and Naik links (canonical complex128 layout) from thin links."""
+    n = 1
+    for d in lat.dims:
+        n *= d
+    n *= 4 * 9 * 16
+    _check(load().hisq_smear_links(_ctx(ctx), ctypes.byref(lat), _ptr(thin_c128, "thin_c128", n), float(naik_eps),
+                                   _ptr(fat_c128, "fat_c128", n), _ptr(naik_c128, "naik_c128", n),
+                                   _ptr(ws, "ws", hisq_smear_workspace_bytes(lat)), ctypes.c_size_t(ws.numel()),
+                                   _stream(stream)), "hisq_smear_links")
 
 
 def hisq_tune_dslash(lat, prec, nrhs: int, links, inp, out, ctx, stream=None):

@@ -183,3 +183,14 @@ def test_condensate_argument_checks(lib):
                                       None, None, None, None, None) == h.INVALID_ARG
     assert lib.hisq_chiral_condensate(None, lat, 0.0, p(16), None, 0, 2, p(32), p(48), 1e-8, 10, p(64), 1 << 20,
                                       None, ctypes.byref(out), None, None, None) == h.INVALID_ARG
+
+
+def test_smear_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    lat = ctypes.byref(h.lattice((4, 4, 4, 4), -1))
+    p = ctypes.c_void_p
+    n = h.hisq_smear_workspace_bytes(h.lattice((4, 4, 4, 4), -1))
+    assert n == 256 * 44 * 144
+    assert lib.hisq_smear_links(None, lat, p(16), 0.0, p(16), p(48), p(64), n, None) == h.INVALID_ARG
+    assert lib.hisq_smear_links(None, lat, p(16), 0.0, p(32), p(48), p(64), n - 1, None) == h.WORKSPACE
+    assert lib.hisq_smear_links(None, lat, None, 0.0, p(32), p(48), p(64), n, None) == h.INVALID_ARG
