@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
         FieldIO<FP>::template load<T>(prm.p, prm.vh, rr, i, p);
         FieldIO<FP>::template load<T>(prm.q, prm.vh, rr, i, q);
         FieldIO<FP>::template load<T>(prm.r, prm.vh, rr, i, r);
-        FieldIO<HISQ_FP64>::template load<double>(prm.x, prm.vh, rr, i, x);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[rr], prm.vh, 0, i, x);
         const T a = (T)alpha;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
             part[0] = fma((double)r[c].re, (double)r[c].re, part[0]);
             part[0] = fma((double)r[c].im, (double)r[c].im, part[0]);
         }
-        FieldIO<HISQ_FP64>::template store<double>(prm.x, prm.vh, rr, i, x);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[rr], prm.vh, 0, i, x);
         FieldIO<FP>::template store<T>(prm.r, prm.vh, rr, i, r);
         if (prm.nshift > 0) {
             // shifted solutions: alpha_k = alpha zeta_new / zeta (Jegerlehner)

@@ -46,12 +46,14 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     L.ms = take(sizeof(MsGlobal));
     L.flags = take(64 * sizeof(unsigned));
     L.scal = take(64 * sizeof(double));
-    L.partials = take(sizeof(double) * (size_t)std::max(nrhs, 1) * L.nblk_max);
+    // the multi-shift refinement solves up to HISQ_MAX_RHS shifts as columns
+    const int ncol = std::max(nrhs, std::min(std::max(nshift, 0), (int)HISQ_MAX_RHS));
+    L.partials = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);
     const size_t fb = field_bytes(g, L.fs, 1);
-    L.r = take(fb * nrhs);
-    L.p = take(fb * nrhs);
-    L.q = take(fb * nrhs);
-    L.t = take(fb * nrhs);
+    L.r = take(fb * ncol);
+    L.p = take(fb * ncol);
+    L.q = take(fb * ncol);
+    L.t = take(fb * ncol);
     L.ps = take(fb * std::max(nshift, 0));
     const size_t f64 = field_bytes(g, HISQ_FP64, 1);
     L.ax = take(f64);
@@ -134,8 +136,9 @@ struct Solver {
         return s == HISQ_OK ? read_double(scal() + S_TMP, out2) : s;
     }
 
-    // The four kernels of one iteration for nrhs right-hand sides.
-    hipError_t iteration(const CgVecParams &vp, double sigma, int nrhs) {
+    // The four kernels of one iteration for nrhs right-hand sides, column j
+    // solving (M_e + sigma[j]) x = b.
+    hipError_t iteration(const CgVecParams &vp, const double *sigma, int nrhs) {
         DslashParams prm{};
         prm.g = g;
         prm.nrhs = nrhs;
@@ -152,7 +155,10 @@ struct Solver {
         prm.out = const_cast<void *>(vp.q);
         prm.y = vp.p;
         prm.ad = -1.0;
-        prm.ay = mass * mass + sigma;
+        prm.ay = mass * mass + sigma[0];
+        prm.ay_per_rhs = 1;
+        for (int j = 0; j < nrhs; ++j)
+            prm.ay_rhs[j] = mass * mass + sigma[j];
         prm.partials = partials();
         prm.dot_out = &vp.st[0].pq;
         prm.dot_stride = sizeof(CgScalars) / sizeof(double);
@@ -215,10 +221,18 @@ size_t cg_workspace_bytes(const Geom &g, int inner, int nrhs, int nshift) {
     return make_layout(g, inner, nrhs, nshift).total;
 }
 
-// CG / reliable-update CG on (M_e + sigma) for nrhs columns of b, x (FP64
-// packed).  x holds the initial guess on entry.  info[nrhs] is filled.
-static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void *x, double tol, int max_iter,
-                          double delta, hisq_solve_info *info, const int *prior_iters) {
+// The right-hand sides of one CG run: column j solves (M_e + sigma[j]) x[j] =
+// b[j] to tol[j] (packed FP64 fields; x holds the initial guess on entry).
+struct Columns {
+    const void *b[HISQ_MAX_RHS];
+    void *x[HISQ_MAX_RHS];
+    double sigma[HISQ_MAX_RHS];
+    double tol[HISQ_MAX_RHS];
+};
+
+// CG / reliable-update CG for nrhs columns.  info[nrhs] is filled.
+static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, double delta,
+                          hisq_solve_info *info, const int *prior_iters) {
     const double t0 = now_s();
     const Geom &g = S.g;
     const Layout &L = S.L;
@@ -231,20 +245,19 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
     if (s != HISQ_OK)
         return s;
 
-    const char *bb = static_cast<const char *>(b);
-    char *xb = static_cast<char *>(x);
     char *rs = S.at<char>(L.r);
-    const size_t c64 = S.f64_col(), cs = S.fs_col();
+    const size_t cs = S.fs_col();
+    S.shape_in = pick_shape(S.ctx, g, S.lp_in, L.fs, nrhs);
     bool breakdown = false;
     for (int j = 0; j < nrhs; ++j) {
-        if ((s = S.norm2(bb + j * c64, &bnorm2[j])) != HISQ_OK)
+        if ((s = S.norm2(C.b[j], &bnorm2[j])) != HISQ_OK)
             return s;
-        if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &rtrue2[j])) != HISQ_OK)
+        if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &rtrue2[j])) != HISQ_OK)
             return s;
         CgScalars c{};
         c.rho = rtrue2[j];
         c.rmax2 = rtrue2[j];
-        c.target2 = tol * tol * bnorm2[j];
+        c.target2 = C.tol[j] * C.tol[j] * bnorm2[j];
         c.delta2 = delta * delta;
         c.max_iter = max_iter;
         c.iters = 0;
@@ -281,7 +294,8 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
     CgVecParams vp{};
     vp.vh = g.vh;
     vp.nrhs = nrhs;
-    vp.x = x;
+    for (int j = 0; j < nrhs; ++j)
+        vp.x[j] = C.x[j];
     vp.r = rs;
     vp.p = S.at<void>(L.p);
     vp.q = S.at<void>(L.q);
@@ -301,7 +315,7 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
         if (e == hipSuccess) {
             hipError_t le = hipSuccess;
             for (int k = 0; k < S.chunk && le == hipSuccess; ++k)
-                le = S.iteration(vp, sigma, nrhs);
+                le = S.iteration(vp, C.sigma, nrhs);
             e = hipStreamEndCapture(st, &gc.graph);
             if (le == hipSuccess && e == hipSuccess)
                 e = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
@@ -322,7 +336,7 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
             e = hipGraphLaunch(gc.exec, st);
         } else {
             for (int k = 0; k < S.chunk && e == hipSuccess; ++k)
-                e = S.iteration(vp, sigma, nrhs);
+                e = S.iteration(vp, C.sigma, nrhs);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(hs.data(), dst, sizeof(CgScalars) * nrhs, hipMemcpyDeviceToHost, st);
@@ -336,7 +350,7 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
             if (c.active || c.flag == FLAG_DONE)
                 continue;
             if (c.flag == FLAG_CONV || c.flag == FLAG_RELIABLE) {
-                if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &rtrue2[j])) != HISQ_OK)
+                if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &rtrue2[j])) != HISQ_OK)
                     return s;
                 if (!std::isfinite(rtrue2[j])) {
                     c.flag = FLAG_BREAKDOWN;
@@ -384,7 +398,7 @@ static hisq_status run_cg(Solver &S, double sigma, int nrhs, const void *b, void
         CgScalars &c = hs[j];
         if (c.flag != FLAG_DONE) {
             double r2 = 0.0;
-            if ((s = S.true_residual(sigma, bb + j * c64, xb + j * c64, rs + j * cs, &r2)) != HISQ_OK)
+            if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &r2)) != HISQ_OK)
                 return s;
             rtrue2[j] = r2;
             if (std::isfinite(r2) && r2 <= c.target2 && c.flag != FLAG_BREAKDOWN)
@@ -490,7 +504,7 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
         CgVecParams vp{};
         vp.vh = g.vh;
         vp.nrhs = 1;
-        vp.x = x[base];
+        vp.x[0] = x[base];
         vp.r = rs;
         vp.p = S.at<void>(L.p);
         vp.q = S.at<void>(L.q);
@@ -511,7 +525,7 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
             if (ce == hipSuccess) {
                 hipError_t le = hipSuccess;
                 for (int k = 0; k < S.chunk && le == hipSuccess; ++k)
-                    le = S.iteration(vp, shifts[base], 1);
+                    le = S.iteration(vp, &shifts[base], 1);
                 ce = hipStreamEndCapture(st, &gc.graph);
                 if (le == hipSuccess && ce == hipSuccess)
                     ce = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
@@ -522,7 +536,7 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
         for (int chunk = 0; chunk < max_iter + 64 && c.active; ++chunk) {
             e = use_graph ? hipGraphLaunch(gc.exec, st) : hipSuccess;
             for (int k = 0; !use_graph && k < S.chunk && e == hipSuccess; ++k)
-                e = S.iteration(vp, shifts[base], 1);
+                e = S.iteration(vp, &shifts[base], 1);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(&c, dst, sizeof c, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess)
@@ -543,22 +557,37 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
         if (c.flag == FLAG_BREAKDOWN)
             return fail(HISQ_ERR_BREAKDOWN, "multi-shift CG breakdown");
     }
-    // refinement: each shift to its own FP64 true residual
+    // refinement: every shift to its own FP64 true residual, the shifts as the
+    // columns of one multi-RHS CG (groups of up to HISQ_MAX_RHS), each column
+    // with its own shift and tolerance, starting from its x_k
     hisq_status result = HISQ_OK;
-    for (int k = 0; k < nshift; ++k) {
-        hisq_solve_info one{};
-        const int left = std::max(1, max_iter - krylov_iters[k]);
-        hisq_status rs = run_cg(S, shifts[k], 1, b, x[k], tol[k], left, delta, &one, &krylov_iters[k]);
+    int kmax = 0;
+    for (int k = 0; k < nshift; ++k)
+        kmax = std::max(kmax, krylov_iters[k]);
+    const int group = std::min(nshift, (int)HISQ_MAX_RHS);
+    for (int k0 = 0; k0 < nshift; k0 += group) {
+        const int n = std::min(group, nshift - k0);
+        Columns C{};
+        for (int j = 0; j < n; ++j) {
+            C.b[j] = b;
+            C.x[j] = x[k0 + j];
+            C.sigma[j] = shifts[k0 + j];
+            C.tol[j] = tol[k0 + j];
+        }
+        std::vector<hisq_solve_info> one(n);
+        const int left = std::max(1, max_iter - kmax);
+        hisq_status rs = run_cg(S, C, n, left, delta, one.data(), &krylov_iters[k0]);
         if (rs == HISQ_ERR_DEVICE || rs == HISQ_ERR_INVALID_ARG)
             return rs;
         if (rs == HISQ_ERR_BREAKDOWN)
             result = rs;
         else if (rs == HISQ_ERR_NOT_CONVERGED && result == HISQ_OK)
             result = rs;
-        if (info) {
-            info[k] = one;
-            info[k].seconds = now_s() - t0;
-        }
+        if (info)
+            for (int j = 0; j < n; ++j) {
+                info[k0 + j] = one[j];
+                info[k0 + j].seconds = now_s() - t0;
+            }
     }
     if (result != HISQ_OK)
         fail(result, result == HISQ_ERR_BREAKDOWN ? "multi-shift refinement breakdown"
@@ -642,7 +671,15 @@ hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, con
     // reliable updates whenever the iterated residual fell by 10x (reduced
     // precision); FP64 CG checks the true residual at convergence only
     const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
-    return run_cg(S, 0.0, nrhs, b, x, tol, max_iter, delta, info, nullptr);
+    Columns C{};
+    const size_t c64 = field_bytes(S.g, HISQ_FP64, 1);
+    for (int j = 0; j < nrhs; ++j) {
+        C.b[j] = static_cast<const char *>(b) + j * c64;
+        C.x[j] = static_cast<char *>(x) + j * c64;
+        C.sigma[j] = 0.0;
+        C.tol[j] = tol;
+    }
+    return run_cg(S, C, nrhs, max_iter, delta, info, nullptr);
 }
 
 hisq_status hisq_chiral_condensate(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,

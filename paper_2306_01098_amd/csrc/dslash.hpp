@@ -36,6 +36,8 @@ struct DslashParams {
     void *out;
     const void *y;  // EPI_AXPY*: out = ad * D in + ay * y (y on the output parity)
     double ad, ay;
+    int ay_per_rhs;                 // EPI_AXPY*: use ay_rhs[r] instead of ay
+    double ay_rhs[HISQ_MAX_RHS];
     const int *skip;     // optional: if *skip != 0 the whole launch does nothing
     double *partials;    // EPI_AXPY_DOT: [nrhs][site blocks] block partials
     double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride] (finalize kernel)
@@ -277,7 +279,7 @@ __device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i
     if (EPI != EPI_PLAIN) {
         cplx<A> yv[3];
         FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r, i, yv);
-        const A ad = (A)prm.ad, ay = (A)prm.ay;
+        const A ad = (A)prm.ad, ay = (A)(prm.ay_per_rhs ? prm.ay_rhs[r] : prm.ay);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             v[a].re = fma(ad, v[a].re, ay * yv[a].re);

@@ -61,7 +61,7 @@ constexpr int MAX_SHIFTS = 32;
 struct CgVecParams {
     int vh;
     int nrhs;
-    void *x;            // FP64 solution [nrhs]
+    void *x[HISQ_MAX_RHS];  // FP64 solution of each right-hand side (one column each)
     void *r;            // sloppy residual [nrhs]
     void *p;            // sloppy direction [nrhs]
     const void *q;      // sloppy A p [nrhs]
