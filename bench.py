@@ -602,6 +602,17 @@ def main():
             "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{n} FP64 D_oe applications of the C oracle at 32^3x8 in ~10 s (same inputs), "
                       "algorithmic bytes per application / mean time"}
+        # the oracle's textbook FP64 CG to the same 1e-10 true residual, for the
+        # time-to-solution comparison (32^3x8 and the 8^4 Haar workload)
+        cgcpu = {}
+        c0 = time.perf_counter()
+        r = O.cg(O.lattice_from(w), mass, s0, 1e-10, 40000)
+        cgcpu["32^3x8_m0.01"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
+        w1 = gen.workload_1()
+        c0 = time.perf_counter()
+        r = O.cg(O.lattice_from(w1), w1["mass"], w1["src"][0], 1e-10, 40000)
+        cgcpu["8^4_m0.1"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
+        result["cpu_baseline"]["cg_time_to_solution_1e-10"] = cgcpu
 
     legs = [x for x in args.suite.split(",") if x]
     if legs:
