@@ -269,8 +269,9 @@ size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *prob
 /* Batched CG: nproblems (1..256) independent systems M_e x = b, each on its
  * own lattice with its own mass, links and tolerance, solved together.  Every
  * launch covers the sites of all problems through a block -> problem work
- * list, so one iteration of all problems is four kernels (plus the finalize
- * kernels of the two reductions); chunks of
+ * list (its sites per block, 64, 128 or 256, chosen per call by timing one
+ * batch-wide Dslash launch of each), so one iteration of all problems is four
+ * kernels (plus the finalize kernels of the two reductions); chunks of
  * iterations are captured in a HIP graph and replayed; a problem whose
  * iterated residual meets its target stops updating while the others go on.
  * With inner = FP32/FP16N the iterations use that link precision with FP32

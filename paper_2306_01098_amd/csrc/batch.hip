@@ -14,7 +14,6 @@ namespace hisq {
 
 namespace {
 
-constexpr int BB = BATCH_BLOCK;
 enum { FIN_PQ = 0, FIN_XR, FIN_RESID, FIN_BNORM };
 constexpr int FIN_BLOCK = 256;  // four problems per finalize block
 
@@ -34,8 +33,8 @@ __device__ __forceinline__ bool participates(const BatchArgs &a, int j, int role
 //  ROLE_ITER_DEO: q = m^2 p - D_eo t, Re<p, q> -> st[j].pq
 //  ROLE_TRUE_DOE: t64 = D_oe x           (FP64)
 //  ROLE_TRUE_DEO: ax = m^2 x - D_eo t64  (FP64)
-template <int LP, int FP, int ROLE>
-__global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
+template <int LP, int FP, int ROLE, int TB>
+__global__ void __launch_bounds__(TB) batch_dslash_kernel(BatchArgs a) {
     using A = typename Prec<LP>::acc;
     if (ROLE <= ROLE_ITER_DEO && *a.nactive == 0)  // iterations stop once no problem is active
         return;
@@ -45,7 +44,7 @@ __global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
-    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const int i = (blk - P.first_blk) * TB + threadIdx.x;
     const bool go = participates(a, j, ROLE) && i < P.g.vh;
     double dot[1] = {0.0};
     if (go) {
@@ -73,22 +72,22 @@ __global__ void __launch_bounds__(BB) batch_dslash_kernel(BatchArgs a) {
     }
     if (!DOT)
         return;
-    __shared__ double lds[2];
+    __shared__ double lds[TB / 64];
     block_sum<1>(dot, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = dot[0];
 }
 
 // x += alpha p, r -= alpha q, and block partials of <r, r>.
-template <int FP>
-__global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
+template <int FP, int TB>
+__global__ void __launch_bounds__(TB) batch_xr_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
     if (*a.nactive == 0)
         return;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
-    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const int i = (blk - P.first_blk) * TB + threadIdx.x;
     const CgScalars st = a.st[j];
     const bool go = st.active && pos_finite(st.pq) && i < P.g.vh;
     double part[1] = {0.0};
@@ -113,7 +112,7 @@ __global__ void __launch_bounds__(BB) batch_xr_kernel(BatchArgs a) {
         FieldIO<HISQ_FP64>::template store<double>(P.x, P.g.vh, 0, i, x);
         FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, r);
     }
-    __shared__ double lds[2];
+    __shared__ double lds[TB / 64];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
@@ -186,15 +185,15 @@ __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, 
 }
 
 // p = r + beta p for active problems.
-template <int FP>
-__global__ void __launch_bounds__(BB) batch_p_kernel(BatchArgs a) {
+template <int FP, int TB>
+__global__ void __launch_bounds__(TB) batch_p_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
     if (*a.nactive == 0)
         return;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
-    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const int i = (blk - P.first_blk) * TB + threadIdx.x;
     const CgScalars st = a.st[j];
     if (!st.active || i >= P.g.vh)
         return;
@@ -212,13 +211,13 @@ __global__ void __launch_bounds__(BB) batch_p_kernel(BatchArgs a) {
 
 // For masked problems: r = b - ax (sloppy copy) and block partials of
 // ||b - ax||^2 (FP64); with `copy_p` also p = r (start of a solve).
-template <int FP>
-__global__ void __launch_bounds__(BB) batch_residual_kernel(BatchArgs a, int copy_p) {
+template <int FP, int TB>
+__global__ void __launch_bounds__(TB) batch_residual_kernel(BatchArgs a, int copy_p) {
     using T = typename SloppyT<FP>::T;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
-    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const int i = (blk - P.first_blk) * TB + threadIdx.x;
     double part[1] = {0.0};
     if (a.mask[j] && i < P.g.vh) {
         cplx<double> bv[3], av[3];
@@ -237,18 +236,19 @@ __global__ void __launch_bounds__(BB) batch_residual_kernel(BatchArgs a, int cop
         if (copy_p)
             FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, rv);
     }
-    __shared__ double lds[2];
+    __shared__ double lds[TB / 64];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
 }
 
 // Block partials of ||b||^2 of every problem (used once, before the solve).
-__global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a) {
+template <int TB>
+__global__ void __launch_bounds__(TB) batch_bnorm_kernel(BatchArgs a) {
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
-    const int i = (blk - P.first_blk) * BB + threadIdx.x;
+    const int i = (blk - P.first_blk) * TB + threadIdx.x;
     double part[1] = {0.0};
     if (i < P.g.vh) {
         cplx<double> bv[3];
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(BB) batch_bnorm_kernel(BatchArgs a) {
             part[0] = fma(bv[c].im, bv[c].im, part[0]);
         }
     }
-    __shared__ double lds[2];
+    __shared__ double lds[TB / 64];
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
         a.partials[blk] = part[0];
@@ -270,43 +270,52 @@ __global__ void batch_clock_kernel(double *out) {
         *out = (double)wall_clock64();
 }
 
-}  // namespace
-
-hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st) {
+template <int TB>
+hipError_t launch_batch_tb(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st) {
     const dim3 g((unsigned)nblocks);
     const bool f64 = lp == HISQ_FP64;
     const bool f16 = lp == HISQ_FP16N;
     switch (op) {
     case BOP_ITER_DOE:
-        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
-        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
-        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DOE><<<g, BB, 0, st>>>(a);
+        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DOE, TB><<<g, TB, 0, st>>>(a);
+        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DOE, TB><<<g, TB, 0, st>>>(a);
+        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DOE, TB><<<g, TB, 0, st>>>(a);
         break;
     case BOP_ITER_DEO:
-        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
-        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
-        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DEO><<<g, BB, 0, st>>>(a);
+        if (f64) batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_ITER_DEO, TB><<<g, TB, 0, st>>>(a);
+        else if (f16) batch_dslash_kernel<HISQ_FP16N, HISQ_FP32, ROLE_ITER_DEO, TB><<<g, TB, 0, st>>>(a);
+        else batch_dslash_kernel<HISQ_FP32, HISQ_FP32, ROLE_ITER_DEO, TB><<<g, TB, 0, st>>>(a);
         break;
-    case BOP_TRUE_DOE: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DOE><<<g, BB, 0, st>>>(a); break;
-    case BOP_TRUE_DEO: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DEO><<<g, BB, 0, st>>>(a); break;
+    case BOP_TRUE_DOE: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DOE, TB><<<g, TB, 0, st>>>(a); break;
+    case BOP_TRUE_DEO: batch_dslash_kernel<HISQ_FP64, HISQ_FP64, ROLE_TRUE_DEO, TB><<<g, TB, 0, st>>>(a); break;
     case BOP_XR:
-        if (f64) batch_xr_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a);
-        else batch_xr_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a);
+        if (f64) batch_xr_kernel<HISQ_FP64, TB><<<g, TB, 0, st>>>(a);
+        else batch_xr_kernel<HISQ_FP32, TB><<<g, TB, 0, st>>>(a);
         break;
     case BOP_P:
-        if (f64) batch_p_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a);
-        else batch_p_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a);
+        if (f64) batch_p_kernel<HISQ_FP64, TB><<<g, TB, 0, st>>>(a);
+        else batch_p_kernel<HISQ_FP32, TB><<<g, TB, 0, st>>>(a);
         break;
     case BOP_RESIDUAL:
     case BOP_RESIDUAL_COPY_P: {
         const int cp = op == BOP_RESIDUAL_COPY_P;
-        if (f64) batch_residual_kernel<HISQ_FP64><<<g, BB, 0, st>>>(a, cp);
-        else batch_residual_kernel<HISQ_FP32><<<g, BB, 0, st>>>(a, cp);
+        if (f64) batch_residual_kernel<HISQ_FP64, TB><<<g, TB, 0, st>>>(a, cp);
+        else batch_residual_kernel<HISQ_FP32, TB><<<g, TB, 0, st>>>(a, cp);
         break;
     }
+    case BOP_BNORM: batch_bnorm_kernel<TB><<<g, TB, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st) {
+    hipError_t e = a.block == 64    ? launch_batch_tb<64>(a, nblocks, op, lp, st)
+                   : a.block == 128 ? launch_batch_tb<128>(a, nblocks, op, lp, st)
+                   : a.block == 256 ? launch_batch_tb<256>(a, nblocks, op, lp, st)
+                                    : hipErrorInvalidValue;
     if (e != hipSuccess)
         return e;
     const int fin = op == BOP_ITER_DEO ? FIN_PQ : op == BOP_XR ? FIN_XR
@@ -318,8 +327,10 @@ hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStre
 }
 
 hipError_t launch_batch_bnorm(const BatchArgs &a, int nblocks, double *bnorm2, hipStream_t st) {
-    batch_bnorm_kernel<<<dim3((unsigned)nblocks), BB, 0, st>>>(a);
-    hipError_t e = hipGetLastError();
+    hipError_t e = a.block == 64    ? launch_batch_tb<64>(a, nblocks, BOP_BNORM, HISQ_FP64, st)
+                   : a.block == 128 ? launch_batch_tb<128>(a, nblocks, BOP_BNORM, HISQ_FP64, st)
+                   : a.block == 256 ? launch_batch_tb<256>(a, nblocks, BOP_BNORM, HISQ_FP64, st)
+                                    : hipErrorInvalidValue;
     if (e != hipSuccess)
         return e;
     batch_finalize_kernel<<<(a.nprob + 3) / 4, FIN_BLOCK, 0, st>>>(a, FIN_BNORM, bnorm2);

@@ -6,7 +6,9 @@
 
 namespace hisq {
 
-constexpr int BATCH_BLOCK = 128;  // threads (sites) per block of every batch kernel
+// Sites (threads) per block of the batch kernels: 64, 128 or 256, chosen per
+// batch by timing one Dslash launch of each (the work list depends on it).
+constexpr int BATCH_BLOCK_MIN = 64;
 constexpr int MAX_BATCH = 256;    // problems per batch
 
 // One problem of the batch, as the kernels see it.
@@ -30,12 +32,13 @@ struct BatchArgs {
     const int *mask;      // [nprob] problems taking part in a true-residual pass
     double *partials;     // [nblocks]
     int *nactive;         // problems still iterating: iteration kernels do nothing at 0
+    int block;            // sites per block (64, 128, 256)
 };
 
 enum { ROLE_ITER_DOE = 0, ROLE_ITER_DEO = 1, ROLE_TRUE_DOE = 2, ROLE_TRUE_DEO = 3 };
 enum {
     BOP_ITER_DOE = 0, BOP_ITER_DEO, BOP_TRUE_DOE, BOP_TRUE_DEO, BOP_XR, BOP_P, BOP_RESIDUAL,
-    BOP_RESIDUAL_COPY_P
+    BOP_RESIDUAL_COPY_P, BOP_BNORM
 };
 
 hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st);

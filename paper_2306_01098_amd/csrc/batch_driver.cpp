@@ -19,7 +19,6 @@ struct BatchLayout {
     int nblocks;
     size_t probs, blk, state, mask, partials, flags, scal, fields, total;
     std::vector<size_t> r, p, q, t, ax, t64;
-    std::vector<int> first_blk, nblk;
 };
 
 BatchLayout batch_layout(int n, const hisq_problem *pr, int inner) {
@@ -31,13 +30,10 @@ BatchLayout batch_layout(int n, const hisq_problem *pr, int inner) {
         off = al256(off + b);
         return o;
     };
-    L.nblocks = 0;
+    L.nblocks = 0;  // at the smallest block size: the most blocks any choice needs
     for (int j = 0; j < n; ++j) {
         const Geom g = make_geom(pr[j].lat);
-        const int nb = (g.vh + BATCH_BLOCK - 1) / BATCH_BLOCK;
-        L.first_blk.push_back(L.nblocks);
-        L.nblk.push_back(nb);
-        L.nblocks += nb;
+        L.nblocks += (g.vh + BATCH_BLOCK_MIN - 1) / BATCH_BLOCK_MIN;
     }
     L.probs = take(sizeof(BatchProb) * n);
     L.blk = take(sizeof(int) * L.nblocks);
@@ -46,6 +42,7 @@ BatchLayout batch_layout(int n, const hisq_problem *pr, int inner) {
     L.partials = take(sizeof(double) * L.nblocks);
     L.flags = take(64 * sizeof(unsigned));
     L.scal = take(sizeof(double) * (MAX_BATCH + 8));
+    L.fields = off;
     for (int j = 0; j < n; ++j) {
         const Geom g = make_geom(pr[j].lat);
         const size_t fb = field_bytes(g, L.fs, 1), f64 = field_bytes(g, HISQ_FP64, 1);
@@ -147,6 +144,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     // problem table and work list
     std::vector<BatchProb> probs(n);
     std::vector<int> blk(L.nblocks);
+    int nblocks = 0;  // blocks of the chosen work list
     for (int j = 0; j < n; ++j) {
         const hisq_problem &P = problems[j];
         BatchProb &B = probs[j];
@@ -162,11 +160,21 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         B.t = W + L.t[j];
         B.ax = W + L.ax[j];
         B.t64 = W + L.t64[j];
-        B.first_blk = L.first_blk[j];
-        B.nblk = L.nblk[j];
-        for (int b = 0; b < L.nblk[j]; ++b)
-            blk[L.first_blk[j] + b] = j;
     }
+    // work list for `bb` sites per block: problem j owns blocks
+    // [first_blk, first_blk + nblk); returns the number of blocks
+    auto assign = [&](int bb) -> int {
+        int total = 0;
+        for (int j = 0; j < n; ++j) {
+            const int nb = (probs[j].g.vh + bb - 1) / bb;
+            probs[j].first_blk = total;
+            probs[j].nblk = nb;
+            for (int b = 0; b < nb; ++b)
+                blk[total + b] = j;
+            total += nb;
+        }
+        return total;
+    };
     BatchArgs a{};
     a.probs = reinterpret_cast<const BatchProb *>(W + L.probs);
     a.nprob = n;
@@ -176,6 +184,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     a.partials = reinterpret_cast<double *>(W + L.partials);
     unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
     a.nactive = reinterpret_cast<int *>(flags + BF_NACTIVE);
+    a.block = 128;
     double *scal = reinterpret_cast<double *>(W + L.scal);  // [0..n) ||b||^2, [MAX_BATCH] start clock
     int *mask_d = reinterpret_cast<int *>(W + L.mask);
 
@@ -206,25 +215,69 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     // true residual of the masked problems: r = b - M x (FP64), rho_new = ||r||^2
     auto true_residuals = [&](bool copy_p) -> hipError_t {
         hipError_t err = push(false, true);
-        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_TRUE_DOE, lp, st);
-        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_TRUE_DEO, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_TRUE_DOE, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_TRUE_DEO, lp, st);
         if (err == hipSuccess)
-            err = launch_batch(a, L.nblocks, copy_p ? BOP_RESIDUAL_COPY_P : BOP_RESIDUAL, lp, st);
+            err = launch_batch(a, nblocks, copy_p ? BOP_RESIDUAL_COPY_P : BOP_RESIDUAL, lp, st);
         if (err == hipSuccess) err = pull();
         return err;
     };
 
-    e = hipMemcpyAsync(W + L.probs, probs.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(W + L.blk, blk.data(), sizeof(int) * L.nblocks, hipMemcpyHostToDevice, st);
+    auto upload = [&]() -> hipError_t {
+        hipError_t err = hipMemcpyAsync(W + L.probs, probs.data(), sizeof(BatchProb) * n, hipMemcpyHostToDevice, st);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(W + L.blk, blk.data(), sizeof(int) * nblocks, hipMemcpyHostToDevice, st);
+        return err;
+    };
     if (e == hipSuccess) e = launch_fill_u32(flags, 64, 0u, st);
+    // tile autotuning: time one iteration Dslash of the whole batch at 64, 128
+    // and 256 sites per block (vectors zeroed, every problem active) and keep
+    // the fastest work list
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<unsigned *>(W + L.fields), (L.total - L.fields) / 4, 0u, st);
+    for (int j = 0; j < n; ++j) {
+        CgScalars c{};
+        c.active = 1;
+        hs[j] = c;
+    }
+    if (e == hipSuccess) e = push(true, false);
+    {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        float best_ms = 1e30f;
+        int best = 128;
+        for (int bb : {64, 128, 256}) {
+            if (e != hipSuccess)
+                break;
+            a.block = bb;
+            nblocks = assign(bb);
+            e = upload();
+            if (e == hipSuccess) e = launch_batch(a, nblocks, BOP_ITER_DOE, lp, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int k = 0; k < 3 && e == hipSuccess; ++k)
+                e = launch_batch(a, nblocks, BOP_ITER_DOE, lp, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = bb;
+            }
+        }
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        a.block = best;
+        nblocks = assign(best);
+        if (e == hipSuccess) e = upload();
+    }
     for (int j = 0; j < n; ++j) {
         CgScalars c{};
         c.active = 0;
         hs[j] = c;
     }
     if (e == hipSuccess) e = push(true, true);
-    if (e == hipSuccess) e = launch_batch_bnorm(a, L.nblocks, scal, st);
+    if (e == hipSuccess) e = launch_batch_bnorm(a, nblocks, scal, st);
     if (e == hipSuccess) e = hipMemcpyAsync(bnorm2.data(), scal, sizeof(double) * n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = true_residuals(true);
     if (e != hipSuccess)
@@ -258,10 +311,10 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     // graph of one chunk of batched iterations
     const int chunk = 16;
     auto iterate = [&]() -> hipError_t {
-        hipError_t err = launch_batch(a, L.nblocks, BOP_ITER_DOE, lp, st);
-        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_ITER_DEO, lp, st);
-        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_XR, lp, st);
-        if (err == hipSuccess) err = launch_batch(a, L.nblocks, BOP_P, lp, st);
+        hipError_t err = launch_batch(a, nblocks, BOP_ITER_DOE, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_ITER_DEO, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_XR, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_P, lp, st);
         return err;
     };
     bool use_graph = false;
@@ -334,7 +387,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
             for (int j = 0; j < n; ++j) only[j].active = restart[j];
             std::swap(only, hs);
             e = push(true, false);
-            if (e == hipSuccess) e = launch_batch(a, L.nblocks, BOP_P, lp, st);
+            if (e == hipSuccess) e = launch_batch(a, nblocks, BOP_P, lp, st);
             std::swap(only, hs);
             for (int j = 0; j < n; ++j)
                 if (restart[j]) hs[j].active = 1;
