@@ -194,3 +194,12 @@ def test_smear_argument_checks(lib):
     assert lib.hisq_smear_links(None, lat, p(16), 0.0, p(16), p(48), p(64), n, None) == h.INVALID_ARG
     assert lib.hisq_smear_links(None, lat, p(16), 0.0, p(32), p(48), p(64), n - 1, None) == h.WORKSPACE
     assert lib.hisq_smear_links(None, lat, None, 0.0, p(32), p(48), p(64), n, None) == h.INVALID_ARG
+
+
+def test_largest_volume_is_enforced(lib):
+    from paper_2306_01098_amd import hisq as h
+    ok = h.lattice((1024, 1024, 256, 4), -1)          # 2^30 sites: the limit
+    big = h.lattice((1024, 1024, 512, 4), -1)         # 2^31 sites
+    assert h.hisq_field_bytes(ok, "fp64", 1) == (1 << 29) * 48
+    assert h.hisq_links_bytes(big, "fp64") == 0
+    assert h.hisq_field_bytes(big, "fp32", 1) == 0

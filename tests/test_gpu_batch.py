@@ -86,3 +86,23 @@ def test_workload_uneven_batch_64(gpu_lib):
     print(f"\nbatch of 64: wall {info[0]['seconds']:.3f} s, latency p50 {np.percentile(lat_ms, 50):.1f} ms "
           f"p99 {np.percentile(lat_ms, 99):.1f} ms, iterations {min(i['iterations'] for i in info)}.."
           f"{max(i['iterations'] for i in info)}")
+
+
+def test_batch_with_a_zero_source(gpu_lib):
+    """A problem whose source is zero is done before the first iteration (x = 0)
+    while the others iterate to their tolerance."""
+    h = gpu_lib
+    ws_list = [gen.workload_haar(d, 95 + k, -1) for k, d in enumerate([(4, 4, 4, 4), (4, 4, 6, 4), (6, 4, 4, 4)])]
+    for w in ws_list:
+        w["mass"] = 0.1
+    ws_list[1]["src"] = np.zeros_like(ws_list[1]["src"])
+    items, probs, ws, keep = build(h, ws_list, "fp32")
+    st, info, lat_s = h.hisq_cg_batch(probs, "fp32", 20000, ws)
+    assert st == h.OK, info
+    assert info[1]["iterations"] == 0
+    x1 = h.unpack_field_to_host(items[1]["lat"], "fp64", items[1]["x"])[0]
+    assert np.all(x1 == 0)
+    for j in (0, 2):
+        w = ws_list[j]
+        xj = h.unpack_field_to_host(items[j]["lat"], "fp64", items[j]["x"])[0]
+        assert O.true_residual(O.lattice_from(w), 0.1, w["src"][0], xj) <= 1e-10

@@ -61,3 +61,19 @@ def test_free_field_estimate_matches_closed_form(gpu_lib):
     print(f"\nfree 8^4 pbp {pbp:.6f} +- {err:.6f}, closed form {exact:.6f}, V = {V}")
     assert abs(pbp - exact) <= 4 * err
     assert err < 0.05 * exact
+
+
+def test_single_noise_vector(gpu_lib):
+    """One noise vector: the estimate is that sample and the error is NaN."""
+    h = gpu_lib
+    dims, m = (4, 4, 4, 6), 0.2
+    w = gen.workload_haar(dims, 62, -1)
+    lat = h.lattice(dims, -1)
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    noise = gen.gaussian_half_field(gen.rng_for(62, 50), dims, 1)
+    nz = h.pack_field_from_host(lat, "fp64", noise)
+    x = h.empty_field(lat, "fp64", 1)
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp64", 1, 0))
+    st, pbp, err, smp, _ = h.hisq_chiral_condensate(lat, m, l64, None, "fp64", 1, nz, x, 1e-10, 20000, ws)
+    assert st == h.OK and np.isnan(err) and pbp == smp[0]
+    assert abs(pbp - C.samples(O.lattice_from(w), m, noise)[0]) <= 1e-8 * abs(pbp)

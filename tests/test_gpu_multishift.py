@@ -111,3 +111,27 @@ def test_workload_48x48x48x12_multi_rhs_and_multishift(gpu_lib):
         sol = h.unpack_field_to_host(lat, "fp64", xk[k])[0]
         assert O.true_residual(lat_o, m, w["src"][0], sol, shift=s) <= 1e-10, k
     print(f"48^3x12 multishift: iterations {[i['iterations'] for i in info]}, {info[0]['seconds']:.3f} s")
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_multishift_32_shifts_refined_in_two_groups(gpu_lib, inner):
+    """The maximum of 32 shifts: the refinement solves them as two 16-column
+    multi-RHS groups, each column with its own shift and tolerance."""
+    h = gpu_lib
+    w = gen.workload_smooth((4, 4, 6, 8), 47, -1, 0.3, 1)
+    shifts = list(10.0 ** (-4.0 + 4.0 * np.arange(32) / 31.0))
+    tols = [1e-10 if k % 2 == 0 else 1e-8 for k in range(32)]
+    st, info, sols, _ = run(h, w, inner, shifts, 0.05, tol=tols)
+    assert st == h.OK, info
+    lat_o = O.lattice_from(w)
+    for k in (0, 1, 15, 16, 17, 30, 31):
+        assert O.true_residual(lat_o, 0.05, w["src"][0], sols[k], shift=shifts[k]) <= tols[k], k
+
+
+def test_multishift_zero_source(gpu_lib):
+    h = gpu_lib
+    w = gen.workload_smooth((4, 4, 4, 4), 48, -1, 0.3, 1)
+    st, info, sols, _ = run(h, w, "fp32", [0.0, 0.1, 1.0], 0.1, src=np.zeros_like(w["src"][0]))
+    assert st == h.OK
+    for s in sols:
+        assert np.all(s == 0)
