@@ -177,6 +177,16 @@ def leg_w3(h, gen, O, torch):
     tseq = time.perf_counter() - t0
     out["cg16_sequential"] = {"seconds": round(tseq, 4), "iterations": its}
     out["cg16_speedup_batched_vs_sequential"] = round(tseq / t16, 3)
+    # the same 16-rhs solve with reconstruct-12 FP32 links (SU(3) links here)
+    l12 = h.pack_links_from_host(lat, "fp32r12", w["fat"], w["naik"])
+    ws12 = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32r12", 16, 0))
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = h.hisq_cg(lat, m, l64, l12, "fp32r12", 16, b, x, 1e-10, 40000, ws12)
+    out["cg16_batched_fp32r12_links"] = {"seconds": round(time.perf_counter() - t0, 4), "status": st,
+                                         "max_true_residual": max(i["true_residual"] for i in info)}
+    del l12, ws12
     shifts = w["shifts"]
     xs = [h.empty_field(lat, "fp64") for _ in shifts]
     wsm = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 1, len(shifts)))
