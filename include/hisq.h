@@ -359,7 +359,12 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
  *             the remaining right-hand sides run as further blocks: the
  *             N_inner x N_outer split of the paper's Sec. 5.1).
  *   block     threads per block (64, 128, 256).
- *   xcd_remap 1: consecutive blocks of one XCD take neighbouring sites. */
+ *   xcd_remap block order.  0: blocks in site order (dealt round-robin over
+ *             the 8 XCDs); 1: each XCD takes one contiguous 1/8 of the sites
+ *             (a range in t); 2: each XCD takes one z-slab of N_z / 8 planes
+ *             for every t, so only the hops in z cross XCDs (needs N_z
+ *             divisible by 8; HISQ_ERR_INVALID_ARG from hisq_set_dslash_shape
+ *             otherwise). */
 typedef struct {
     int32_t variant;
     int32_t nin;

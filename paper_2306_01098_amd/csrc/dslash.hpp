@@ -62,8 +62,9 @@ __device__ __forceinline__ Site site_coords(const Geom &g, int p, int i) {
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip.  With
-// remapping, XCD k works on one contiguous range of logical blocks (nearby
-// sites), so neighbour colour vectors are shared within that XCD's L2.
+// remapping (block order 1 or 2), XCD k works on one contiguous range of
+// logical blocks (nearby sites), so neighbour colour vectors are shared within
+// that XCD's L2.
 __device__ __forceinline__ int logical_block(int remap) {
     const int b = blockIdx.x;
     if (!remap)
@@ -76,8 +77,26 @@ __device__ __forceinline__ int logical_block(int remap) {
 
 // Block coordinates: site block `sb` (of nsb) and first right-hand side r0
 // of the block's group of NIN.
+// Traversal position ip -> site index when the XCDs take z-slabs (block
+// order 2): ip runs over (slab, t, z within the slab, y, x/2) with 8 slabs of
+// N_z / 8 planes, so the contiguous range of XCD k is slab k for every t;
+// its hops in t stay inside the slab and only the +-1/+-3 hops in z reach
+// other XCDs' sites.  Requires N_z divisible by 8.
+__device__ __forceinline__ int zslab_site(const Geom &g, int ip) {
+    const int plane = g.ny * g.hx;  // sites of one (t, z) plane of this parity
+    const int zw = g.nz >> 3;
+    const int q = ip / plane, r = ip - q * plane;
+    const int zl = q % zw, st = q / zw;
+    const int t = st % g.nt, slab = st / g.nt;
+    return (t * g.nz + slab * zw + zl) * plane + r;
+}
+
 template <int NIN> struct BlockPos {
     int sb, nsb, r0, nr;
+    // site index of traversal position ip (ip < vh)
+    __device__ __forceinline__ int site(const DslashParams &prm, int ip) const {
+        return prm.xcd_remap == 2 && ip < prm.g.vh ? zslab_site(prm.g, ip) : ip;
+    }
     __device__ __forceinline__ BlockPos(const DslashParams &prm) {
         const int nouter = (prm.nrhs + NIN - 1) / NIN;
         const int lb = logical_block(prm.xcd_remap);
@@ -309,7 +328,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
     if (prm.skip && *prm.skip)
         return;
     const BlockPos<NIN> bp(prm);
-    const int i = bp.sb * blockDim.x + threadIdx.x;
+    const int i = bp.site(prm, bp.sb * blockDim.x + threadIdx.x);
     const bool valid = i < prm.g.vh;
     if (EPI != EPI_AXPY_DOT && !valid)
         return;
@@ -340,7 +359,7 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
         return;
     const int mu = threadIdx.x & 3;
     const BlockPos<NIN> bp(prm);
-    const int i = bp.sb * (blockDim.x >> 2) + (threadIdx.x >> 2);
+    const int i = bp.site(prm, bp.sb * (blockDim.x >> 2) + (threadIdx.x >> 2));
     // a site's four lanes are in one wavefront and share validity, so whole
     // quads drop out together and the shuffles below see only valid partners
     const bool valid = i < prm.g.vh;

@@ -15,13 +15,17 @@ bool dslash_shape_supported(DslashShape s) {
     const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR;
     const bool nin_ok = s.nin == 1 || s.nin == 2 || s.nin == 4 || s.nin == 8;
     const bool blk_ok = s.block == 64 || s.block == 128 || s.block == 256;
-    const bool remap_ok = s.xcd_remap == 0 || s.xcd_remap == 1;
+    const bool remap_ok = s.xcd_remap == 0 || s.xcd_remap == 1 || s.xcd_remap == 2;
     return var_ok && nin_ok && blk_ok && remap_ok;
 }
+
+bool dslash_shape_fits(DslashShape s, const Geom &g) { return s.xcd_remap != 2 || g.nz % 8 == 0; }
 
 hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape s, hipStream_t st) {
     if (!dslash_shape_supported(s))
         return hipErrorInvalidValue;
+    if (!dslash_shape_fits(s, prm.g))
+        s.xcd_remap = 1;  // z-slab order needs N_z divisible by 8
     if (lp == HISQ_FP64 && fp == HISQ_FP64)
         return dslash_launch_f64(prm, epi, s, st);
     if (lp == HISQ_FP32 && fp == HISQ_FP32)

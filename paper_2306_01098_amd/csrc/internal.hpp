@@ -28,6 +28,8 @@ struct DslashParams;
 hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape shape,
                          hipStream_t st);
 bool dslash_shape_supported(DslashShape s);
+// Block order 2 (XCDs take z-slabs) needs N_z divisible by 8.
+bool dslash_shape_fits(DslashShape s, const Geom &g);
 
 }  // namespace hisq
 

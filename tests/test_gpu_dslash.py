@@ -254,7 +254,7 @@ def _all_shapes(nrhs):
             if nin > 1 and nin > nrhs:
                 continue
             for block in (64, 128, 256):
-                for remap in (0, 1):
+                for remap in (0, 1, 2):
                     out.append((var, nin, block, remap))
     return out
 
@@ -280,6 +280,14 @@ def test_every_launch_shape_matches_oracle(gpu_lib, fields, prec):
         h.hisq_dslash(lat, prec, 0, links, inp, out, nrhs, ctx=ctx)
         got = h.unpack_field_to_host(lat, prec, out, nrhs)
         assert relerr(got, ref) <= (1e-13 if prec.startswith("fp64") else 1e-6), shape
+
+
+def test_zslab_block_order_needs_nz_divisible_by_8(gpu_lib):
+    h = gpu_lib
+    ctx = h.Context(0)
+    with pytest.raises(h.HisqError):
+        h.hisq_set_dslash_shape(h.lattice((8, 8, 12, 8), -1), "fp64", 1, (0, 1, 128, 2), ctx)
+    h.hisq_set_dslash_shape(h.lattice((8, 8, 16, 8), -1), "fp64", 1, (0, 1, 128, 2), ctx)
 
 
 def test_autotuner_picks_a_supported_shape(gpu_lib, fields):
