@@ -77,15 +77,25 @@ def test_multi_rhs_cg(gpu_lib, inner, nrhs):
     m = 0.05
     src = w["src"] * (10.0 ** np.arange(nrhs) % 7 + 1)[:, None, None]  # uneven norms
     lat, l64, lin, b, x, ws = setup(h, w, inner, nrhs, src=src)
-    st, info = h.hisq_cg(lat, m, l64, lin, inner, nrhs, b, x, 1e-10, 20000, ws)
+    # one right-hand side per thread and the same block size for the batched
+    # and the single solve: the same summation order in every reduction
+    ctx = h.Context(0)
+    h.hisq_set_dslash_shape(lat, inner, nrhs, (0, 1, 128, 1), ctx)
+    h.hisq_set_dslash_shape(lat, inner, 1, (0, 1, 128, 1), ctx)
+    st, info = h.hisq_cg(lat, m, l64, lin, inner, nrhs, b, x, 1e-10, 20000, ws, ctx=ctx)
     assert st == h.OK, info
-    res, _ = oracle_residuals(h, w, lat, x, nrhs, m, src)
+    res, xs = oracle_residuals(h, w, lat, x, nrhs, m, src)
     assert max(res) <= 1e-10, res
-    # each column is an independent solve: same result as solving it alone
+    # each column is an independent solve: the same result as solving it alone
     lat1, l64b, linb, b1, x1, ws1 = setup(h, w, inner, 1, src=src[nrhs - 1:])
-    st1, info1 = h.hisq_cg(lat1, m, l64b, linb, inner, 1, b1, x1, 1e-10, 20000, ws1)
+    st1, info1 = h.hisq_cg(lat1, m, l64b, linb, inner, 1, b1, x1, 1e-10, 20000, ws1, ctx=ctx)
     assert st1 == h.OK
     assert info1[0]["iterations"] == info[nrhs - 1]["iterations"]
+    np.testing.assert_array_equal(h.unpack_field_to_host(lat1, "fp64", x1)[0], xs[nrhs - 1])
+    # with the built-in shapes the columns still reach the tolerance
+    x.zero_()
+    st, info = h.hisq_cg(lat, m, l64, lin, inner, nrhs, b, x, 1e-10, 20000, ws)
+    assert st == h.OK and max(oracle_residuals(h, w, lat, x, nrhs, m, src)[0]) <= 1e-10
 
 
 def test_initial_guess_and_determinism(gpu_lib):
