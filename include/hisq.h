@@ -364,7 +364,8 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
  *             (a range in t); 2: each XCD takes one z-slab of N_z / 8 planes
  *             for every t, so only the hops in z cross XCDs (needs N_z
  *             divisible by 8; HISQ_ERR_INVALID_ARG from hisq_set_dslash_shape
- *             otherwise). */
+ *             otherwise); with several right-hand sides and N_y divisible by
+ *             8 the slab is swept in bands of 8 y-rows. */
 typedef struct {
     int32_t variant;
     int32_t nin;

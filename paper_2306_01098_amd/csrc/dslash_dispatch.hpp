@@ -16,6 +16,7 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     const dim3 grid((unsigned)(nsb * nouter));
     DslashParams p = prm;
     p.xcd_remap = s.xcd_remap;
+    p.band = zslab_band(prm.g, prm.nrhs);
     if (s.variant == VAR_DIR)
         dslash_dir_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
     else
