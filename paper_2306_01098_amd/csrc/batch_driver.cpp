@@ -125,13 +125,13 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         ~Cleanup() {
-            if (exec) hipGraphExecDestroy(exec);
-            if (graph) hipGraphDestroy(graph);
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
             if (*st) {
-                hipStreamSynchronize(*st);
-                hipStreamDestroy(*st);
+                (void)hipStreamSynchronize(*st);
+                (void)hipStreamDestroy(*st);
             }
-            if (*ev) hipEventDestroy(*ev);
+            if (*ev) (void)hipEventDestroy(*ev);
         }
     } cleanup{&st, &ev};
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -265,8 +265,8 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
                 best = bb;
             }
         }
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
         a.block = best;
         nblocks = assign(best);
         if (e == hipSuccess) e = upload();

@@ -18,27 +18,46 @@ template <> struct Sloppy<HISQ_FP32> { using T = float; };
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e308; }
 
-// x += alpha p (FP64 x), r -= alpha q, and the block partials of <r, r> for
-// right-hand side blockIdx.y; multi-shift: x_k += alpha_k p_k.
+// <p, A p> of column rr from the D_eo kernel's block partials: wave 0 sums
+// them (wave_sum_slot: the order cg_finalize_kernel uses too) and the block
+// reads the total from LDS.
+__device__ __forceinline__ double block_pq(const CgVecParams &prm, int rr, double *lds1) {
+    if (threadIdx.x < 64) {
+        const double v = wave_sum_slot<false>(prm.pq_part + (size_t)rr * prm.pq_nblk, prm.pq_nblk);
+        if (threadIdx.x == 0)
+            *lds1 = v;
+    }
+    __syncthreads();
+    return *lds1;
+}
+
+// x += alpha p (FP64 x), r -= alpha q with alpha = rho / <p, A p>, and the
+// block partials of <r, r> for right-hand side blockIdx.y; multi-shift:
+// x_k += alpha_k p_k.
 template <int FP>
 __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
     using T = typename Sloppy<FP>::T;
     if (*prm.skip)
         return;
     __shared__ double lds[4];
+    __shared__ double pq_s;
     const int rr = blockIdx.y;
     const int i = blockIdx.x * BLK + threadIdx.x;
     const CgScalars st = prm.st[rr];
-    const bool go = st.active && finite_pos(st.pq);
-    const double alpha = go ? st.rho / st.pq : 0.0;
-    double part[1] = {0.0};
-    if (go && i < prm.vh) {
-        cplx<T> p[3], q[3], r[3];
-        cplx<double> x[3];
+    const bool mine = st.active && i < prm.vh;
+    cplx<T> p[3], q[3], r[3];
+    cplx<double> x[3];
+    if (mine) {  // issued before the <p, A p> sum so the loads overlap it
         FieldIO<FP>::template load<T>(prm.p, prm.vh, rr, i, p);
         FieldIO<FP>::template load<T>(prm.q, prm.vh, rr, i, q);
         FieldIO<FP>::template load<T>(prm.r, prm.vh, rr, i, r);
         FieldIO<HISQ_FP64>::template load<double>(prm.x[rr], prm.vh, 0, i, x);
+    }
+    const double pq = block_pq(prm, rr, &pq_s);
+    const bool go = st.active && finite_pos(pq);
+    const double alpha = go ? st.rho / pq : 0.0;
+    double part[1] = {0.0};
+    if (go && mine) {
         const T a = (T)alpha;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -81,20 +100,29 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
 }
 
 // One block: sums the <r, r> partials of cg_xr_kernel (nblk blocks per
-// right-hand side) and advances the scalars: breakdown check, rho, beta,
+// right-hand side) and the <p, A p> partials of the D_eo kernel (in the order
+// cg_xr_kernel summed them) and advances the scalars: breakdown check, rho, beta,
 // convergence / reliable-update / iteration-limit flags, and the multi-shift
 // zeta recurrences.
 __global__ void __launch_bounds__(1024) cg_finalize_kernel(CgVecParams prm, int nblk) {
     if (*prm.skip)
         return;
     __shared__ double tot[HISQ_MAX_RHS];
+    __shared__ double totpq[HISQ_MAX_RHS];
     sum_partials_block(prm.partials, prm.nrhs, nblk, tot);
+    for (int j = threadIdx.x >> 6; j < prm.nrhs; j += blockDim.x >> 6) {
+        const double v = wave_sum_slot<false>(prm.pq_part + (size_t)j * prm.pq_nblk, prm.pq_nblk);
+        if ((threadIdx.x & 63) == 0)
+            totpq[j] = v;
+    }
+    __syncthreads();
     if (threadIdx.x != 0)
         return;
     int any = 0;
     for (int j = 0; j < prm.nrhs; ++j) {
         CgScalars s = prm.st[j];
         if (s.active) {
+            s.pq = totpq[j];
             if (!finite_pos(s.pq)) {
                 s.flag = FLAG_BREAKDOWN;
                 s.active = 0;
@@ -136,9 +164,11 @@ __global__ void __launch_bounds__(1024) cg_finalize_kernel(CgVecParams prm, int 
                 } else if (rho_new <= s.target2) {
                     s.flag = FLAG_CONV;
                     s.active = 0;
+                    prm.tr_skip[j] = 0;
                 } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
                     s.flag = FLAG_RELIABLE;
                     s.active = 0;
+                    prm.tr_skip[j] = 0;
                 } else if (s.iters >= s.max_iter) {
                     s.flag = FLAG_MAXIT;
                     s.active = 0;
@@ -155,17 +185,68 @@ __global__ void __launch_bounds__(1024) cg_finalize_kernel(CgVecParams prm, int 
     *prm.skip = any ? 0 : 1;
 }
 
-// p = r + beta p for right-hand side rhs0 + blockIdx.y (if active);
+// The true-residual check of the columns that raised FLAG_CONV or
+// FLAG_RELIABLE (tr_skip[j] == 0), after r_j = b_j - A x_j and the block
+// partials of ||r_j||^2 (nblk per column in trpart) were formed: the FP64
+// norm decides DONE (target met), MAXIT, or a residual replacement, which
+// restarts the recurrence with beta = ||r||^2 / rho, rho = rmax2 = ||r||^2
+// (p = r + beta p follows in cg_p_kernel's restart mode).  One block.
+__global__ void __launch_bounds__(1024) cg_restart_kernel(CgVecParams prm, const double *trpart, int nblk) {
+    __shared__ double tot[HISQ_MAX_RHS];
+    for (int j = threadIdx.x >> 6; j < prm.nrhs; j += blockDim.x >> 6)
+        if (prm.tr_skip[j] == 0) {
+            const double v = wave_sum_slot<true>(trpart + (size_t)j * nblk, nblk);
+            if ((threadIdx.x & 63) == 0)
+                tot[j] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    int any = 0;
+    for (int j = 0; j < prm.nrhs; ++j) {
+        CgScalars s = prm.st[j];
+        s.restart = 0;
+        if (prm.tr_skip[j] == 0) {
+            const double r2 = tot[j];
+            prm.tr_skip[j] = 1;
+            s.rtrue2 = r2;
+            if (!(r2 >= 0.0 && r2 < 1.0e308)) {
+                s.flag = FLAG_BREAKDOWN;
+                s.active = 0;
+            } else if (r2 <= s.target2) {
+                s.flag = FLAG_DONE;
+                s.active = 0;
+            } else if (s.iters >= s.max_iter) {
+                s.flag = FLAG_MAXIT;
+                s.active = 0;
+            } else {
+                s.nrel += 1;
+                s.beta = r2 / s.rho;
+                s.rho = r2;
+                s.rmax2 = r2;
+                s.flag = FLAG_RUN;
+                s.active = 1;
+                s.restart = 1;
+            }
+        }
+        prm.st[j] = s;
+        any |= s.active;
+    }
+    *prm.skip = any ? 0 : 1;
+}
+
+// p = r + beta p for right-hand side rhs0 + blockIdx.y (if active; in restart
+// mode only for a column just restarted by cg_restart_kernel);
 // multi-shift: p_k = zeta_k r + beta_k p_k.
 template <int FP>
-__global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0) {
+__global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0, int restart_only) {
     using T = typename Sloppy<FP>::T;
     if (*prm.skip)
         return;
     const int rr = rhs0 + blockIdx.y;
     const int i = blockIdx.x * BLK + threadIdx.x;
     const CgScalars st = prm.st[rr];
-    if (!st.active || i >= prm.vh)
+    if (!(restart_only ? st.restart : st.active) || i >= prm.vh)
         return;
     cplx<T> p[3], r[3];
     FieldIO<FP>::template load<T>(prm.p, prm.vh, rr, i, p);
@@ -199,8 +280,10 @@ __global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0) {
 // *out2 = ||b - ax||^2 in FP64 (from the FP64 values).
 template <int FP>
 __global__ void __launch_bounds__(BLK) residual_kernel(int vh, const void *b, const void *ax, void *r,
-                                                       double *partials) {
+                                                       double *partials, const int *skip) {
     using T = typename Sloppy<FP>::T;
+    if (skip && *skip)
+        return;
     __shared__ double lds[4];
     const int i = blockIdx.x * BLK + threadIdx.x;
     double part[1] = {0.0};
@@ -302,21 +385,32 @@ hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st) {
+hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st, bool restart_only) {
+    const int mode = restart_only ? 1 : 0;
     if (fp == HISQ_FP64)
-        cg_p_kernel<HISQ_FP64><<<grid_for(p.vh, nrhs), BLK, 0, st>>>(p, rhs0);
+        cg_p_kernel<HISQ_FP64><<<grid_for(p.vh, nrhs), BLK, 0, st>>>(p, rhs0, mode);
     else
-        cg_p_kernel<HISQ_FP32><<<grid_for(p.vh, nrhs), BLK, 0, st>>>(p, rhs0);
+        cg_p_kernel<HISQ_FP32><<<grid_for(p.vh, nrhs), BLK, 0, st>>>(p, rhs0, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStream_t st) {
+    cg_restart_kernel<<<1, 1024, 0, st>>>(p, trpart, blas_blocks(p.vh));
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_parts(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
+                                 const int *skip, hipStream_t st) {
+    if (fp == HISQ_FP64)
+        residual_kernel<HISQ_FP64><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials, skip);
+    else
+        residual_kernel<HISQ_FP32><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
                            double *out2, hipStream_t st) {
-    if (fp == HISQ_FP64)
-        residual_kernel<HISQ_FP64><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials);
-    else
-        residual_kernel<HISQ_FP32><<<grid_for(vh), BLK, 0, st>>>(vh, b, ax, r, partials);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_residual_parts(vh, fp, b, ax, r, partials, nullptr, st);
     return e == hipSuccess ? launch_sum_partials(partials, 1, blas_blocks(vh), out2, 1, nullptr, st) : e;
 }
 

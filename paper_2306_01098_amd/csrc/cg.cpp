@@ -3,9 +3,10 @@
 // mixed-precision CG, and multi-shift CG with per-shift refinement, all for
 // the even-site operator M_e = m^2 - D_eo D_oe (+ shift).
 //
-// One CG iteration is four kernels on the device: D_oe p -> t;
-// q = (m^2 + sigma) p - D_eo t with Re<p, q>; x += alpha p, r -= alpha q with
-// <r, r> and the scalar update; p = r + beta p.  Chunks of iterations are
+// One CG iteration is five kernels on the device: D_oe p -> t;
+// q = (m^2 + sigma) p - D_eo t with the block partials of Re<p, q>;
+// x += alpha p, r -= alpha q with the <r, r> partials (each block sums the
+// Re<p, q> partials itself); the one-block scalar update; p = r + beta p.  Chunks of iterations are
 // captured once into a HIP graph and replayed; kernels of converged
 // right-hand sides do nothing, and the host looks at the device state only
 // between chunks (to run a reliable update or to stop).
@@ -13,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "api_util.hpp"
@@ -28,7 +30,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     int fs;  // sloppy field precision (FP64 or FP32)
     int nblk_max;
-    size_t state, shifts, ms, flags, scal, partials, r, p, q, t, ps, ax, t64, total;
+    size_t state, shifts, ms, flags, scal, partials, dpart, r, p, q, t, ps, ax, t64, total;
 };
 
 Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
@@ -49,6 +51,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     // the multi-shift refinement solves up to HISQ_MAX_RHS shifts as columns
     const int ncol = std::max(nrhs, std::min(std::max(nshift, 0), (int)HISQ_MAX_RHS));
     L.partials = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);
+    L.dpart = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);  // <p, A p> partials
     const size_t fb = field_bytes(g, L.fs, 1);
     L.r = take(fb * ncol);
     L.p = take(fb * ncol);
@@ -63,7 +66,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
 }
 
 // flags[] slots
-enum { F_SKIP = 0 };
+enum { F_SKIP = 0, F_TR0 = 16 };  // F_TR0 + j: tr_skip of column j
 // scal[] slots
 enum { S_TMP = 0 };
 
@@ -80,6 +83,7 @@ struct Solver {
     DslashShape shape64{};
     DslashShape shape_in{};
     int chunk = 16;
+    double iter_us = 100.0;  // estimated time of one iteration
 
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     unsigned *flags() const { return at<unsigned>(L.flags); }
@@ -92,26 +96,29 @@ struct Solver {
         return e == hipSuccess ? HISQ_OK : device_fail(e, where);
     }
 
-    // out = (m^2 + sigma) in - D_eo D_oe in, FP64, one column.
-    hisq_status apply_m64(double sigma, const void *in, void *out) {
+    // out = (m^2 + sigma) in - D_eo D_oe in, FP64, one column; both launches
+    // do nothing while skip (nullable) points to a nonzero value.
+    hipError_t m64(double sigma, const void *in, void *out, const int *skip) {
         DslashParams prm{};
         prm.g = g;
         prm.nrhs = 1;
         prm.links = links64;
+        prm.skip = skip;
         prm.out_parity = 1;
         prm.in = in;
         prm.out = at<void>(L.t64);
         hipError_t e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_PLAIN, shape64, st);
         if (e != hipSuccess)
-            return device_fail(e, "M_e (D_oe)");
+            return e;
         prm.out_parity = 0;
         prm.in = at<void>(L.t64);
         prm.out = out;
         prm.y = in;
         prm.ad = -1.0;
         prm.ay = mass * mass + sigma;
-        return dev(launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, shape64, st), "M_e (D_eo)");
+        return launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, shape64, st);
     }
+    hisq_status apply_m64(double sigma, const void *in, void *out) { return dev(m64(sigma, in, out, nullptr), "M_e"); }
 
     hisq_status read_double(const double *d, double *h) {
         hipError_t e = hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -136,7 +143,7 @@ struct Solver {
         return s == HISQ_OK ? read_double(scal() + S_TMP, out2) : s;
     }
 
-    // The four kernels of one iteration for nrhs right-hand sides, column j
+    // The five kernels of one iteration for nrhs right-hand sides, column j
     // solving (M_e + sigma[j]) x = b.
     hipError_t iteration(const CgVecParams &vp, const double *sigma, int nrhs) {
         DslashParams prm{};
@@ -159,13 +166,17 @@ struct Solver {
         prm.ay_per_rhs = 1;
         for (int j = 0; j < nrhs; ++j)
             prm.ay_rhs[j] = mass * mass + sigma[j];
-        prm.partials = partials();
-        prm.dot_out = &vp.st[0].pq;
-        prm.dot_stride = sizeof(CgScalars) / sizeof(double);
+        // the <p, A p> partials are summed inside the x/r update and the
+        // finalize kernel (no reduction launch of their own)
+        prm.partials = at<double>(L.dpart);
+        prm.dot_out = nullptr;
         e = launch_dslash(prm, lp_in, L.fs, EPI_AXPY_DOT, shape_in, st);
         if (e != hipSuccess)
             return e;
-        e = launch_cg_xr(vp, L.fs, st);
+        CgVecParams v2 = vp;
+        v2.pq_part = at<double>(L.dpart);
+        v2.pq_nblk = dslash_partial_blocks(g, shape_in);
+        e = launch_cg_xr(v2, L.fs, st);
         if (e != hipSuccess)
             return e;
         return launch_cg_p(vp, L.fs, 0, nrhs, st);
@@ -196,11 +207,11 @@ struct StreamGuard {
     }
     ~StreamGuard() {
         if (own) {
-            hipStreamSynchronize(own);
-            hipStreamDestroy(own);
+            (void)hipStreamSynchronize(own);
+            (void)hipStreamDestroy(own);
         }
         if (ev)
-            hipEventDestroy(ev);
+            (void)hipEventDestroy(ev);
     }
 };
 
@@ -209,9 +220,9 @@ struct GraphChunk {
     hipGraph_t graph = nullptr;
     ~GraphChunk() {
         if (exec)
-            hipGraphExecDestroy(exec);
+            (void)hipGraphExecDestroy(exec);
         if (graph)
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
     }
 };
 
@@ -230,7 +241,56 @@ struct Columns {
     double tol[HISQ_MAX_RHS];
 };
 
+// Pinned host slots for reading the solver state back without stalling the
+// stream; kept for the life of the process and reused by later solves.
+class PinnedSlots {
+  public:
+    static constexpr int N = 2;
+    PinnedSlots() {
+        std::lock_guard<std::mutex> lk(mu());
+        if (!pool().empty()) {
+            buf_ = pool().back();
+            pool().pop_back();
+        } else if (hipHostMalloc(reinterpret_cast<void **>(&buf_), sizeof(CgScalars) * HISQ_MAX_RHS * N,
+                                 hipHostMallocDefault) != hipSuccess) {
+            buf_ = nullptr;
+        }
+    }
+    ~PinnedSlots() {
+        if (buf_) {
+            std::lock_guard<std::mutex> lk(mu());
+            pool().push_back(buf_);
+        }
+    }
+    bool ok() const { return buf_ != nullptr; }
+    CgScalars *slot(int k) const { return buf_ + (size_t)(k % N) * HISQ_MAX_RHS; }
+
+  private:
+    CgScalars *buf_ = nullptr;
+    static std::mutex &mu() {
+        static std::mutex m;
+        return m;
+    }
+    static std::vector<CgScalars *> &pool() {
+        static std::vector<CgScalars *> p;
+        return p;
+    }
+};
+
+bool terminal(const CgScalars &c) {
+    return !c.active && (c.flag == FLAG_DONE || c.flag == FLAG_BREAKDOWN || c.flag == FLAG_MAXIT);
+}
+
 // CG / reliable-update CG for nrhs columns.  info[nrhs] is filled.
+//
+// The device runs the whole recurrence: every `check` iterations a
+// true-residual block forms r_j = b_j - A x_j in FP64 for each column that
+// raised FLAG_CONV or FLAG_RELIABLE since the last block (the kernels of the
+// other columns do nothing) and cg_restart_kernel decides DONE / MAXIT /
+// residual replacement, so a reliable update needs no host round trip.
+// Chunks of iterations (a multiple of `check`, each ending with a block) are
+// replayed from one HIP graph; the host keeps a second chunk queued while it
+// reads the state of the previous one, and stops when every column is done.
 static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, double delta,
                           hisq_solve_info *info, const int *prior_iters) {
     const double t0 = now_s();
@@ -240,7 +300,6 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     CgScalars *dst = S.at<CgScalars>(L.state);
     std::vector<CgScalars> hs(nrhs);
     std::vector<double> bnorm2(nrhs), rtrue2(nrhs);
-    std::vector<int> reliable(nrhs, 0);
     hisq_status s = S.dev(launch_fill_u32(S.flags(), 64, 0u, st), "fill");
     if (s != HISQ_OK)
         return s;
@@ -257,6 +316,7 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         CgScalars c{};
         c.rho = rtrue2[j];
         c.rmax2 = rtrue2[j];
+        c.rtrue2 = rtrue2[j];
         c.target2 = C.tol[j] * C.tol[j] * bnorm2[j];
         c.delta2 = delta * delta;
         c.max_iter = max_iter;
@@ -276,20 +336,21 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     // p = r
     if ((s = S.dev(launch_copy(g.vh, nrhs, L.fs, L.fs, rs, S.at<void>(L.p), st), "copy")) != HISQ_OK)
         return s;
-    auto push_state = [&]() -> hisq_status {
+    int *trf = reinterpret_cast<int *>(S.flags() + F_TR0);
+    {
         int any = 0;
         for (int j = 0; j < nrhs; ++j)
             any |= hs[j].active;
-        unsigned skip = any ? 0u : 1u;
+        std::vector<unsigned> fl(F_TR0 + HISQ_MAX_RHS, 1u);
+        fl[F_SKIP] = any ? 0u : 1u;
         hipError_t e = hipMemcpyAsync(dst, hs.data(), sizeof(CgScalars) * nrhs, hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(S.flags() + F_SKIP, &skip, sizeof(unsigned), hipMemcpyHostToDevice, st);
+            e = hipMemcpyAsync(S.flags(), fl.data(), sizeof(unsigned) * fl.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
             e = hipStreamSynchronize(st);
-        return S.dev(e, "push state");
-    };
-    if ((s = push_state()) != HISQ_OK)
-        return s;
+        if ((s = S.dev(e, "push state")) != HISQ_OK)
+            return s;
+    }
 
     CgVecParams vp{};
     vp.vh = g.vh;
@@ -302,20 +363,47 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     vp.st = dst;
     vp.partials = S.partials();
     vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+    vp.tr_skip = trf;
     vp.nshift = 0;
 
-    // capture one chunk of iterations (only when there is something to iterate)
-    GraphChunk gc;
-    bool use_graph = false;
+    // true-residual block: columns that wait for one get r = b - A x and the
+    // FP64 partials of ||r||^2 (column j's in partials + j * nb)
+    const int nb = blas_blocks(g.vh);
+    auto tr_block = [&]() -> hipError_t {
+        for (int j = 0; j < nrhs; ++j) {
+            hipError_t e = S.m64(C.sigma[j], C.x[j], S.at<void>(L.ax), trf + j);
+            if (e == hipSuccess)
+                e = launch_residual_parts(g.vh, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
+                                          S.partials() + (size_t)j * nb, trf + j, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        hipError_t e = launch_cg_restart(vp, S.partials(), st);
+        return e == hipSuccess ? launch_cg_p(vp, L.fs, 0, nrhs, st, true) : e;
+    };
+    // iterations between blocks: a flagged column idles until the next one;
+    // FP64 iterations flag only at convergence
+    const int check = delta > 0.0 ? 4 : 8;
+    const int chunk = check * std::max(1, (int)std::lround(500.0 / (check * S.iter_us)));
+    auto chunk_eager = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < chunk && e == hipSuccess; ++k) {
+            e = S.iteration(vp, C.sigma, nrhs);
+            if (e == hipSuccess && (k + 1) % check == 0)
+                e = tr_block();
+        }
+        return e;
+    };
+
     bool any_active = false;
     for (int j = 0; j < nrhs; ++j)
         any_active |= hs[j].active != 0;
+    GraphChunk gc;
+    bool use_graph = false;
     if (any_active) {
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = hipSuccess;
-            for (int k = 0; k < S.chunk && le == hipSuccess; ++k)
-                le = S.iteration(vp, C.sigma, nrhs);
+            const hipError_t le = chunk_eager();
             e = hipStreamEndCapture(st, &gc.graph);
             if (le == hipSuccess && e == hipSuccess)
                 e = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
@@ -324,79 +412,91 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         (void)hipGetLastError();
     }
 
-    const int max_chunks = max_iter + 64;
-    for (int chunk = 0; chunk < max_chunks; ++chunk) {
-        bool any = false;
-        for (int j = 0; j < nrhs; ++j)
-            any |= hs[j].active != 0;
-        if (!any)
-            break;
-        hipError_t e = hipSuccess;
-        if (use_graph) {
-            e = hipGraphLaunch(gc.exec, st);
-        } else {
-            for (int k = 0; k < S.chunk && e == hipSuccess; ++k)
-                e = S.iteration(vp, C.sigma, nrhs);
+    PinnedSlots pin;
+    if (any_active && !pin.ok())
+        return fail(HISQ_ERR_DEVICE, "hipHostMalloc of the state read-back slots failed");
+    hipEvent_t ev[PinnedSlots::N] = {};
+    struct EventsGuard {
+        hipEvent_t *e;
+        ~EventsGuard() {
+            for (int k = 0; k < PinnedSlots::N; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
         }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hs.data(), dst, sizeof(CgScalars) * nrhs, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e != hipSuccess)
-            return device_fail(e, "cg chunk");
-        std::vector<int> restart;
-        for (int j = 0; j < nrhs; ++j) {
-            CgScalars &c = hs[j];
-            if (c.active || c.flag == FLAG_DONE)
-                continue;
-            if (c.flag == FLAG_CONV || c.flag == FLAG_RELIABLE) {
-                if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &rtrue2[j])) != HISQ_OK)
-                    return s;
-                if (!std::isfinite(rtrue2[j])) {
-                    c.flag = FLAG_BREAKDOWN;
-                    breakdown = true;
-                } else if (rtrue2[j] <= c.target2) {
-                    c.flag = FLAG_DONE;
-                } else if (c.iters >= c.max_iter) {
-                    c.flag = FLAG_MAXIT;
-                } else {
-                    // residual replacement: r = b - A x (already in r), then
-                    // beta = <r,r>_true / rho and p = r + beta p
-                    reliable[j] += 1;
-                    c.beta = rtrue2[j] / c.rho;
-                    c.rho = rtrue2[j];
-                    c.rmax2 = rtrue2[j];
-                    c.flag = FLAG_RUN;
-                    c.active = 1;
-                    restart.push_back(j);
-                }
-            } else if (c.flag == FLAG_BREAKDOWN) {
-                breakdown = true;
-            }
-        }
-        if (!restart.empty()) {
-            // only the restarted columns are active while their p is updated
-            std::vector<CgScalars> tmp = hs;
-            for (int j = 0; j < nrhs; ++j)
-                tmp[j].active = 0;
-            for (int j : restart)
-                tmp[j].active = 1;
-            std::swap(tmp, hs);
-            if ((s = push_state()) != HISQ_OK)
-                return s;
-            for (int j : restart)
-                if ((s = S.dev(launch_cg_p(vp, L.fs, j, 1, st), "p update")) != HISQ_OK)
-                    return s;
-            std::swap(tmp, hs);
-        }
-        if ((s = push_state()) != HISQ_OK)
+    } evg{ev};
+    for (int k = 0; any_active && k < PinnedSlots::N; ++k)
+        if ((s = S.dev(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming), "event")) != HISQ_OK)
             return s;
+
+    long launched = 0, read = 0;
+    auto launch_chunk = [&]() -> hipError_t {
+        hipError_t e = use_graph ? hipGraphLaunch(gc.exec, st) : chunk_eager();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pin.slot((int)launched), dst, sizeof(CgScalars) * nrhs, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[launched % PinnedSlots::N], st);
+        if (e == hipSuccess)
+            ++launched;
+        return e;
+    };
+    // every real iteration advances some column's count, and a column that
+    // keeps failing its true-residual check still advances once per block
+    const long max_chunks = (long)max_iter * check / chunk + 4;
+    std::vector<double> prev_rho(nrhs, 0.0);
+    std::vector<int> prev_it(nrhs, 0);
+    bool near_end = false;
+    hipError_t e = hipSuccess;
+    if (any_active)
+        e = launch_chunk();
+    bool finished = !any_active;
+    while (!finished && e == hipSuccess) {
+        // queue the next chunk while this one runs, unless this one may be the last
+        if (launched == read + 1 && launched < max_chunks && !near_end)
+            e = launch_chunk();
+        if (e == hipSuccess)
+            e = hipEventSynchronize(ev[read % PinnedSlots::N]);
+        if (e != hipSuccess)
+            break;
+        std::memcpy(hs.data(), pin.slot((int)read), sizeof(CgScalars) * nrhs);
+        ++read;
+        finished = true;
+        double worst = 0.0;  // most iterations any column still needs (estimate)
+        for (int j = 0; j < nrhs; ++j) {
+            const CgScalars &c = hs[j];
+            if (terminal(c))
+                continue;
+            finished = false;
+            const int dit = c.iters - prev_it[j];
+            if (dit > 0 && prev_rho[j] > c.rho && c.rho > 0.0 && c.target2 > 0.0) {
+                const double rate = std::log(prev_rho[j] / c.rho) / dit;
+                worst = std::max(worst, std::log(c.rho / c.target2) / rate);
+            } else {
+                worst = 1e30;
+            }
+            prev_rho[j] = c.rho;
+            prev_it[j] = c.iters;
+        }
+        near_end = worst < chunk;
+        if (!finished && launched == read) {
+            if (launched >= max_chunks)
+                break;
+            e = launch_chunk();
+        }
     }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return device_fail(e, "cg chunk");
+    if (launched > read)
+        std::memcpy(hs.data(), pin.slot((int)(launched - 1)), sizeof(CgScalars) * nrhs);
+
     // final report
     hisq_status result = HISQ_OK;
     for (int j = 0; j < nrhs; ++j) {
         CgScalars &c = hs[j];
-        if (c.flag != FLAG_DONE) {
+        if (c.flag == FLAG_DONE) {
+            rtrue2[j] = c.rtrue2;
+        } else {
             double r2 = 0.0;
             if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &r2)) != HISQ_OK)
                 return s;
@@ -406,12 +506,12 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         }
         if (info) {
             info[j].iterations = c.iters + (prior_iters ? prior_iters[j] : 0);
-            info[j].reliable_updates = reliable[j];
+            info[j].reliable_updates = c.nrel;
             info[j].true_residual = bnorm2[j] > 0 ? std::sqrt(rtrue2[j] / bnorm2[j]) : std::sqrt(rtrue2[j]);
             info[j].seconds = now_s() - t0;
         }
         if (c.flag == FLAG_BREAKDOWN)
-            result = HISQ_ERR_BREAKDOWN;
+            breakdown = true;
         else if (c.flag != FLAG_DONE && result == HISQ_OK)
             result = HISQ_ERR_NOT_CONVERGED;
     }
@@ -510,7 +610,8 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
         vp.q = S.at<void>(L.q);
         vp.st = dst;
         vp.partials = S.partials();
-            vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+        vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
+        vp.tr_skip = reinterpret_cast<int *>(S.flags() + F_TR0);  // written, not read, here
         vp.nshift = no;
         vp.sh = dsh;
         vp.ms = dms;
@@ -614,6 +715,7 @@ hisq_status setup_solver(Solver &S, hisq_context *ctx, const hisq_lattice *lat, 
     // chunk length: ~1 ms of iterations, 8 .. 64
     const double bytes_per_iter = 2.0 * (double)S.g.vh * 16 * link_matrix_bytes(inner);
     const double est_us = bytes_per_iter / 5.0e6 + 12.0;
+    S.iter_us = est_us;
     S.chunk = std::max(8, std::min(64, (int)(1000.0 / est_us)));
     return HISQ_OK;
 }

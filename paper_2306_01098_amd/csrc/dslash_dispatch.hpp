@@ -22,7 +22,8 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     else
         dslash_site_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && EPI == EPI_AXPY_DOT)
+    // dot_out == nullptr: the caller sums the partials itself
+    if (e == hipSuccess && EPI == EPI_AXPY_DOT && p.dot_out != nullptr)
         e = launch_sum_partials(p.partials, p.nrhs, nsb, p.dot_out, p.dot_stride > 0 ? p.dot_stride : 1, p.skip,
                                 st);
     return e;

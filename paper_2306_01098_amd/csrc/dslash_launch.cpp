@@ -21,6 +21,11 @@ bool dslash_shape_supported(DslashShape s) {
 
 bool dslash_shape_fits(DslashShape s, const Geom &g) { return s.xcd_remap != 2 || g.nz % 8 == 0; }
 
+int dslash_partial_blocks(const Geom &g, DslashShape s) {
+    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
+    return (g.vh + sites_per_block - 1) / sites_per_block;
+}
+
 hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape s, hipStream_t st) {
     if (!dslash_shape_supported(s))
         return hipErrorInvalidValue;

@@ -30,6 +30,9 @@ hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, Dslas
 bool dslash_shape_supported(DslashShape s);
 // Block order 2 (XCDs take z-slabs) needs N_z divisible by 8.
 bool dslash_shape_fits(DslashShape s, const Geom &g);
+// Blocks per right-hand side of a Dslash launch in shape s (the number of
+// EPI_AXPY_DOT partials per right-hand side).
+int dslash_partial_blocks(const Geom &g, DslashShape s);
 
 }  // namespace hisq
 
@@ -38,7 +41,14 @@ namespace hisq {
 struct CgVecParams;
 int blas_blocks(int vh);
 hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st);
-hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st);
+hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st, bool restart_only = false);
+// The true-residual check after r = b - A x of the waiting columns (partials
+// in trpart, blas_blocks(vh) per column).
+hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStream_t st);
+// r = b - ax (sloppy r) and the block partials of ||b - ax||^2, without the
+// sum; the launch does nothing while skip (nullable) points to a nonzero value.
+hipError_t launch_residual_parts(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
+                                 const int *skip, hipStream_t st);
 hipError_t launch_residual(int vh, int fp, const void *b, const void *ax, void *r, double *partials,
                            double *out2, hipStream_t st);
 hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, hipStream_t st);

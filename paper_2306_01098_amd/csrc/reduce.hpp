@@ -73,8 +73,17 @@ template <int NV> __device__ __forceinline__ void wave_sum_multi(double (&v)[NV]
 // Sum of one slot by one wavefront: lane l adds partials l, l + 64, l + 128,
 // ... in that order (eight loads in flight per step), then the wave adds the
 // lanes in a fixed shuffle tree.  The result is the same whichever wave runs
-// it, so the sum is deterministic.  Returns the total in every lane.
-__device__ __forceinline__ double wave_sum_slot(const double *p, int nblk) {
+// it, so the sum is deterministic.  Returns the total in every lane.  NT:
+// non-temporal loads (one reader); plain loads when every block of a grid
+// reads the same slot, so it stays in the L2.
+template <bool NT = true> __device__ __forceinline__ double ld_partial(const double *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT = true> __device__ __forceinline__ double wave_sum_slot(const double *p, int nblk) {
     const int lane = threadIdx.x & 63;
     double v = 0.0;
     int b = lane;
@@ -82,13 +91,13 @@ __device__ __forceinline__ double wave_sum_slot(const double *p, int nblk) {
         double t[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            t[k] = __builtin_nontemporal_load(p + b + k * 64);
+            t[k] = ld_partial<NT>(p + b + k * 64);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             v += t[k];
     }
     for (; b < nblk; b += 64)
-        v += __builtin_nontemporal_load(p + b);
+        v += ld_partial<NT>(p + b);
     return wave_sum(v);
 }
 
@@ -99,7 +108,7 @@ __device__ __forceinline__ void sum_partials_block(const double *partials, int n
                                                    double *tot, int stride = 1) {
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int s = wave; s < nslots; s += nw) {
-        const double v = wave_sum_slot(partials + (size_t)s * nblk, nblk);
+        const double v = wave_sum_slot<true>(partials + (size_t)s * nblk, nblk);
         if ((threadIdx.x & 63) == 0)
             tot[(size_t)s * stride] = v;
     }

@@ -29,11 +29,15 @@ struct alignas(16) CgScalars {
     double target2;  // (tol ||b||)^2
     double delta2;   // reliable-update threshold delta^2 (0: only at convergence)
     double rho_new;  // <r, r> after the last update (kept when a flag is raised)
-    double spare;
+    double rtrue2;   // ||b - A x||^2 (FP64) at the last true-residual check
+    double spare;    // the batch solver's stop time stamp
     int active;      // 1 while the recurrence runs
     int flag;        // FLAG_*
     int iters;       // iterations performed
     int max_iter;
+    int nrel;        // reliable updates (residual replacements) so far
+    int restart;     // 1 right after a replacement, until p = r + beta p is redone
+    int pad[2];
 };
 
 // Per shift k of the multi-shift solver (Jegerlehner's recurrences, FP64).
@@ -67,7 +71,16 @@ struct CgVecParams {
     const void *q;      // sloppy A p [nrhs]
     CgScalars *st;      // [nrhs]
     double *partials;   // [nrhs][gridDim.x]
+    // Re <p, A p> block partials of the D_eo kernel, [nrhs][pq_nblk]: summed
+    // by every cg_xr_kernel block and again by cg_finalize_kernel, in one
+    // fixed order, so no separate reduction launch sits between them
+    const double *pq_part;
+    int pq_nblk;
     int *skip;          // 1 when no right-hand side is active
+    // [nrhs]: 0 while column j waits for its FP64 true residual (set by the
+    // finalize kernel with FLAG_CONV / FLAG_RELIABLE, cleared by the
+    // true-residual check), else 1; the check's kernels of column j skip on it
+    int *tr_skip;
     // multi-shift (nshift > 0): per-shift solutions and directions
     int nshift;
     ShiftScalars *sh;
