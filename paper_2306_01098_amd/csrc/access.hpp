@@ -10,22 +10,35 @@ namespace hisq {
 // ---------------------------------------------------------------------------
 template <int LP> struct LinkIO;
 
-// Every link is read exactly once per Dslash application, so FP64 and FP32
-// link loads carry the non-temporal hint: they stream through the caches
-// without displacing the neighbour vectors, which are reused up to 16 times.
-// (Measured on MI355X at 32^3x8: ~2 % faster for FP64 and FP32; binary16
-// links are faster with ordinary loads.)
+// With one group of right-hand sides every link is read exactly once per
+// Dslash application, so FP64 and FP32 link loads carry the non-temporal hint
+// (NT = true): they stream through the caches without displacing the
+// neighbour vectors, which are reused up to 16 times (32^3x8 FP64: 53.0 ->
+// 50.5 us).  When N_outer > 1 groups of right-hand sides read the same links
+// one after another, the links must stay in the L2 for the next group, and
+// ordinary loads are faster (16 rhs at 48^3x12: FP64 1113 -> 960 us, FP32
+// 576 -> 533 us); so are they for reconstruct-12 links at any N_outer
+// (32^3x8 FP64R12 35.4 -> 33.7 us) and for binary16 links.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
 
+template <bool NT, typename V> __device__ __forceinline__ V ld_link(const V *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 template <> struct LinkIO<HISQ_FP64> {
     using A = double;
     static constexpr bool rebuild = false;
+    static constexpr bool stream = true;  // the non-temporal hint may pay
+    template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
+            const nt_d2 v = ld_link<NT>(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
             m[2 * k] = v.x;
             m[2 * k + 1] = v.y;
         }
@@ -35,16 +48,18 @@ template <> struct LinkIO<HISQ_FP64> {
 template <> struct LinkIO<HISQ_FP32> {
     using A = float;
     static constexpr bool rebuild = false;
+    static constexpr bool stream = true;  // the non-temporal hint may pay
+    template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
+            const nt_f4 v = ld_link<NT>(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
             m[4 * k] = v.x;
             m[4 * k + 1] = v.y;
             m[4 * k + 2] = v.z;
             m[4 * k + 3] = v.w;
         }
-        const nt_f2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(blk + (size_t)vh * 64) + i);
+        const nt_f2 t = ld_link<NT>(reinterpret_cast<const nt_f2 *>(blk + (size_t)vh * 64) + i);
         m[16] = t.x;
         m[17] = t.y;
     }
@@ -62,6 +77,8 @@ union H2 {
 template <> struct LinkIO<HISQ_FP16N> {
     using A = float;
     static constexpr bool rebuild = false;
+    static constexpr bool stream = false;  // the non-temporal hint may pay
+    template <bool NT = true>  // ordinary loads either way
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -83,10 +100,12 @@ template <> struct LinkIO<HISQ_FP16N> {
 template <> struct LinkIO<HISQ_FP64R12> {
     using A = double;
     static constexpr bool rebuild = true;
+    static constexpr bool stream = false;  // the non-temporal hint may pay
+    template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
+            const nt_d2 v = ld_link<NT>(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
             m[2 * k] = v.x;
             m[2 * k + 1] = v.y;
         }
@@ -96,10 +115,12 @@ template <> struct LinkIO<HISQ_FP64R12> {
 template <> struct LinkIO<HISQ_FP32R12> {
     using A = float;
     static constexpr bool rebuild = true;
+    static constexpr bool stream = false;  // the non-temporal hint may pay
+    template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
+            const nt_f4 v = ld_link<NT>(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
             m[4 * k] = v.x;
             m[4 * k + 1] = v.y;
             m[4 * k + 2] = v.z;

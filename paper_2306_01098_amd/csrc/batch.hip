@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(TB) batch_dslash_kernel(BatchArgs a) {
         const void *in = ROLE == ROLE_ITER_DOE ? P.p : ROLE == ROLE_ITER_DEO ? P.t : ROLE == ROLE_TRUE_DOE ? P.x : P.t64;
         void *out = ROLE == ROLE_ITER_DOE ? P.t : ROLE == ROLE_ITER_DEO ? P.q : ROLE == ROLE_TRUE_DOE ? P.t64 : P.ax;
         cplx<A> acc[1][3];
-        dslash_site<LP, FP, 1, A>(P.g, parity, links, in, i, 0, 1, acc);
+        dslash_site<LP, FP, 1, A, true>(P.g, parity, links, in, i, 0, 1, acc);
         if (AXPY) {
             const void *y = ROLE == ROLE_ITER_DEO ? P.p : P.x;
             cplx<A> yv[3];

@@ -177,10 +177,10 @@ __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, 
     }
 }
 
-template <int LP, int FP, int NIN, typename A>
+template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int vh, int ilink, const void *in,
                                          int ipsi, int r0, int nr) {
-    LinkIO<LP>::load(blk, vh, ilink, b.m);
+    LinkIO<LP>::template load<NT>(blk, vh, ilink, b.m);
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
         if (r < nr)
@@ -190,7 +190,7 @@ __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int
 // The four hops along direction mu (runtime) of site s (half index i, parity
 // p), times eta_mu(s), accumulated into acc.  The loads of the next hop are
 // issued before the current hop is computed.
-template <int LP, int FP, int NIN, typename A>
+template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
                                                  int i, const Site &s, int mu, int r0, int nr,
                                                  cplx<A> (&acc)[NIN][3]) {
@@ -209,12 +209,12 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
     zero<NIN, A>(tmp);
     const int q = 1 - p;
     HopBuf<NIN, A> b0, b1;
-    hop_load<LP, FP, NIN, A>(b0, links + link_block(0, p, mu, vh, MB), vh, i, in, n1, r0, nr);
-    hop_load<LP, FP, NIN, A>(b1, links + link_block(0, q, mu, vh, MB), vh, n2, in, n2, r0, nr);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block(0, p, mu, vh, MB), vh, i, in, n1, r0, nr);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block(0, q, mu, vh, MB), vh, n2, in, n2, r0, nr);
     hop_apply<LP, NIN, A>(b0, false, s1, nr, tmp);
-    hop_load<LP, FP, NIN, A>(b0, links + link_block(1, p, mu, vh, MB), vh, i, in, n3, r0, nr);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block(1, p, mu, vh, MB), vh, i, in, n3, r0, nr);
     hop_apply<LP, NIN, A>(b1, true, s2, nr, tmp);
-    hop_load<LP, FP, NIN, A>(b1, links + link_block(1, q, mu, vh, MB), vh, n4, in, n4, r0, nr);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block(1, q, mu, vh, MB), vh, n4, in, n4, r0, nr);
     hop_apply<LP, NIN, A>(b0, false, s3, nr, tmp);
     hop_apply<LP, NIN, A>(b1, true, s4, nr, tmp);
     const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
@@ -259,7 +259,7 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
 // The sixteen hops are software-pipelined: the loads of hop k+1 are issued
 // before hop k is computed, so two hops' worth of link and vector loads are in
 // flight per wavefront instead of one.
-template <int LP, int FP, int NIN, typename A>
+template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
                                             int r0, int nr, cplx<A> (&acc)[NIN][3]) {
     constexpr int MB = Prec<LP>::mat_bytes;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
     auto load = [&](int k, int slot) {
         A sg;
         const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
-        LinkIO<LP>::load(h.blk, g.vh, h.ilink, buf[slot].m);
+        LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m);
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
             if (r < nr)
@@ -336,7 +336,9 @@ __device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, doubl
             prm.partials[(size_t)(bp.r0 + r) * bp.nsb + bp.sb] = dot[r];
 }
 
-template <int LP, int FP, int NIN, int EPI>
+// NT: link loads with the non-temporal hint (chosen by the launcher when
+// each link is read once: one group of right-hand sides, FP64 or FP32 links).
+template <int LP, int FP, int NIN, int EPI, bool NT>
 __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm) {
     using A = typename Prec<LP>::acc;
     if (prm.skip && *prm.skip)
@@ -353,7 +355,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
         dot[r] = 0.0;
     if (valid) {
         cplx<A> acc[NIN][3];
-        dslash_site<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
+        dslash_site<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
 #pragma unroll
         for (int r = 0; r < NIN; ++r) {
             if (r < nr) {
@@ -366,7 +368,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
         dslash_dot_reduce<NIN>(prm, dot, bp);
 }
 
-template <int LP, int FP, int NIN, int EPI>
+template <int LP, int FP, int NIN, int EPI, bool NT>
 __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm) {
     using A = typename Prec<LP>::acc;
     if (prm.skip && *prm.skip)
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
     const Site s = site_coords(prm.g, prm.out_parity, i);
     cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
-    dslash_direction<LP, FP, NIN, A>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, r0, nr, acc);
+    dslash_direction<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, r0, nr, acc);
     // sum over the quad: (mu0 + mu1) + (mu2 + mu3), identical in all 4 lanes
 #pragma unroll
     for (int r = 0; r < NIN; ++r)

@@ -17,10 +17,20 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     DslashParams p = prm;
     p.xcd_remap = s.xcd_remap;
     p.band = zslab_band(prm.g, prm.nrhs);
-    if (s.variant == VAR_DIR)
-        dslash_dir_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
-    else
-        dslash_site_kernel<LP, FP, NIN, EPI><<<grid, s.block, 0, st>>>(p);
+    // non-temporal link loads only when each link is read once (one group of
+    // right-hand sides) and the format profits (FP64, FP32)
+    const bool nt = LinkIO<LP>::stream && nouter == 1;
+    if (s.variant == VAR_DIR) {
+        if (nt)
+            dslash_dir_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream><<<grid, s.block, 0, st>>>(p);
+        else
+            dslash_dir_kernel<LP, FP, NIN, EPI, false><<<grid, s.block, 0, st>>>(p);
+    } else {
+        if (nt)
+            dslash_site_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream><<<grid, s.block, 0, st>>>(p);
+        else
+            dslash_site_kernel<LP, FP, NIN, EPI, false><<<grid, s.block, 0, st>>>(p);
+    }
     hipError_t e = hipGetLastError();
     // dot_out == nullptr: the caller sums the partials itself
     if (e == hipSuccess && EPI == EPI_AXPY_DOT && p.dot_out != nullptr)
