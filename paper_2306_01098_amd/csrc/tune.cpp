@@ -25,6 +25,22 @@ DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     s.xcd_remap = 1;
     if (nrhs == 1) {
         s.nin = 1;
+        // Small lattices cannot fill 256 CUs with one thread per site in
+        // blocks of 256: up to 16384 sites per parity (49152 for FP32 and
+        // FP16N links) four lanes per site (8^4 .. 16^3x8: 9.6-16.1 -> 9.2-9.3
+        // us FP64; 16^4 FP32 12.2 -> 9.4 us), below 131072 blocks of 64
+        // (24^3x6 FP64 19.4 -> 16.6 us)
+        const bool wide = lp == HISQ_FP64 || lp == HISQ_FP64R12;
+        if (g.vh <= (wide ? 16384 : 49152)) {
+            s.variant = VAR_DIR;
+            s.block = 128;
+            return s;
+        }
+        if (g.vh < 131072) {
+            s.block = 64;
+            s.xcd_remap = g.nz % 8 == 0 ? 2 : 1;
+            return s;
+        }
         if (g.nz % 8 == 0) {
             s.xcd_remap = 2;
             s.block = lp == HISQ_FP16N ? 64 : 256;
