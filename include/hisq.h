@@ -175,6 +175,18 @@ hisq_status hisq_smear_links(hisq_context *ctx, const hisq_lattice *lat, const v
  * the copy ceiling the Dslash rates are compared with. */
 hisq_status hisq_stream_copy(hisq_context *ctx, const void *src, void *dst, size_t bytes, void *stream);
 
+/* Read-only bandwidth reference: reads `bytes` bytes of src (16-byte
+ * non-temporal loads, four per thread, blocks of 1024 chunks) and stores in
+ * sink[b] the XOR of the 32-bit words of block b's 16 KiB (the last block:
+ * what remains).  sink: device array of hisq_stream_read_sink_words(bytes)
+ * uint32 (0 when bytes is not a multiple of 16), 4-byte aligned, not
+ * overlapping src.  bytes a positive multiple of 16, src 16-byte aligned;
+ * otherwise HISQ_ERR_INVALID_ARG.  Asynchronous.  Not part of the method: the
+ * Dslash reads 98 % of its bytes, so this is the ceiling its rate is compared
+ * with, next to the copy. */
+size_t hisq_stream_read_sink_words(size_t bytes);
+hisq_status hisq_stream_read(hisq_context *ctx, const void *src, size_t bytes, uint32_t *sink, void *stream);
+
 /* out_even = (m^2) in_even - D_eo D_oe in_even, using tmp_odd (a packed
  * field of nrhs on the odd sites) as scratch.  Asynchronous. */
 hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec,

@@ -264,4 +264,23 @@ hisq_status hisq_stream_copy(hisq_context *ctx, const void *src, void *dst, size
     return e == hipSuccess ? HISQ_OK : device_fail(e, "stream_copy");
 }
 
+size_t hisq_stream_read_sink_words(size_t bytes) { return bytes % 16 != 0 ? 0 : stream_read_blocks(bytes / 16); }
+
+hisq_status hisq_stream_read(hisq_context *ctx, const void *src, size_t bytes, uint32_t *sink, void *stream) {
+    TRY(check_ptr(src, "src"));
+    TRY(check_ptr(sink, "sink"));
+    if (bytes == 0 || bytes % 16 != 0)
+        return fail(HISQ_ERR_INVALID_ARG, "bytes = %zu must be a positive multiple of 16", bytes);
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(sink) % 4 != 0)
+        return fail(HISQ_ERR_INVALID_ARG, "src must be 16-byte and sink 4-byte aligned");
+    const char *s0 = static_cast<const char *>(src);
+    const char *k0 = reinterpret_cast<const char *>(sink);
+    const size_t kb = 4 * stream_read_blocks(bytes / 16);
+    if (s0 < k0 + kb && k0 < s0 + bytes)
+        return fail(HISQ_ERR_INVALID_ARG, "src and sink overlap");
+    TRY(set_device(ctx));
+    const hipError_t e = launch_stream_read(src, bytes / 16, sink, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "stream_read");
+}
+
 }  // extern "C"

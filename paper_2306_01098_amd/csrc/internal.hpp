@@ -56,6 +56,9 @@ hipError_t launch_norm2(int vh, const void *v, double *partials, double *out2, h
 hipError_t launch_dot_re(int vh, int n, const void *a, const void *b, double *partials, double *out, hipStream_t st);
 // dst = src for n16 16-byte chunks (non-temporal streaming copy).
 hipError_t launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t st);
+// Blocks of the read reference for n16 chunks of 16 bytes (= sink words).
+size_t stream_read_blocks(size_t n16);
+hipError_t launch_stream_read(const void *src, size_t n16, unsigned *sink, hipStream_t st);
 // out[s * stride] = sum over nblk block partials of slot s (one-block kernel);
 // does nothing when skip is non-NULL and *skip != 0.
 hipError_t launch_sum_partials(const double *partials, int nslots, int nblk, double *out, int stride,

@@ -77,6 +77,8 @@ _SIGS = {
     "hisq_apply_m": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
                                     ctypes.c_int32, _vp]),
     "hisq_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "hisq_stream_read_sink_words": (ctypes.c_size_t, [ctypes.c_size_t]),
+    "hisq_stream_read": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "hisq_smear_workspace_bytes": (ctypes.c_size_t, [_LAT]),
     "hisq_smear_links": (ctypes.c_int, [_vp, _LAT, _vp, ctypes.c_double, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_tune_dslash": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -289,6 +291,20 @@ def hisq_stream_copy(src, dst, nbytes: int | None = None, ctx=None, stream=None)
     n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     _check(load().hisq_stream_copy(_ctx(ctx), _ptr(src, "src", n), _ptr(dst, "dst", n), n, _stream(stream)),
            "hisq_stream_copy")
+
+
+def hisq_stream_read_sink_words(nbytes: int) -> int:
+    return int(load().hisq_stream_read_sink_words(int(nbytes)))
+
+
+def hisq_stream_read(src, sink, nbytes: int | None = None, ctx=None, stream=None):
+    """Reads the first nbytes bytes of src (default all) with the library's
+    read-only streaming kernel; sink (uint32/int32 device tensor of
+    hisq_stream_read_sink_words(nbytes) words) receives one XOR per 16 KiB."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    words = hisq_stream_read_sink_words(n)
+    _check(load().hisq_stream_read(_ctx(ctx), _ptr(src, "src", n), n, _ptr(sink, "sink", 4 * words),
+                                   _stream(stream)), "hisq_stream_read")
 
 
 def hisq_smear_workspace_bytes(lat) -> int:

@@ -169,6 +169,24 @@ def test_stream_copy_argument_checks(lib):
     assert lib.hisq_stream_copy(None, None, p(1 << 20), 64, None) == h.INVALID_ARG
 
 
+def test_stream_read_argument_checks(lib):
+    from paper_2306_01098_amd import hisq as h
+    p = ctypes.c_void_p
+    assert lib.hisq_stream_read_sink_words(16) == 1
+    assert lib.hisq_stream_read_sink_words(16 * 1024) == 1
+    assert lib.hisq_stream_read_sink_words(16 * 1025) == 2
+    assert lib.hisq_stream_read_sink_words(24) == 0
+    # zero bytes, not a multiple of 16, misaligned src or sink, overlap, NULL
+    assert lib.hisq_stream_read(None, p(4096), 0, p(1 << 20), None) == h.INVALID_ARG
+    assert lib.hisq_stream_read(None, p(4096), 24, p(1 << 20), None) == h.INVALID_ARG
+    assert lib.hisq_stream_read(None, p(4104), 32, p(1 << 20), None) == h.INVALID_ARG
+    assert lib.hisq_stream_read(None, p(4096), 32, p((1 << 20) + 2), None) == h.INVALID_ARG
+    assert lib.hisq_stream_read(None, p(4096), 64, p(4096 + 16), None) == h.INVALID_ARG
+    assert b"overlap" in lib.hisq_last_error()
+    assert lib.hisq_stream_read(None, None, 64, p(1 << 20), None) == h.INVALID_ARG
+    assert lib.hisq_stream_read(None, p(4096), 64, None, None) == h.INVALID_ARG
+
+
 def test_condensate_argument_checks(lib):
     from paper_2306_01098_amd import hisq as h
     lat = ctypes.byref(h.lattice((4, 4, 4, 4), -1))

@@ -342,6 +342,24 @@ def test_autotuner_picks_a_supported_shape(gpu_lib, fields):
     assert relerr(got, O.lattice_from(w).D_eo(w["src_o"][0])) <= 1e-13
 
 
+def test_stream_read_xors_every_word(gpu_lib):
+    """The read-only bandwidth reference touches every 32-bit word: block b's
+    sink word is the XOR of its 16 KiB (ragged last block included)."""
+    h = gpu_lib
+    n = 16 * (3 * 1024 + 517)
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+    words = h.hisq_stream_read_sink_words(n)
+    assert words == 4
+    sink = torch.zeros(words + 4, dtype=torch.int32, device="cuda")
+    h.hisq_stream_read(src, sink, n)
+    torch.cuda.synchronize()
+    w32 = src.cpu().numpy().view(np.uint32)
+    want = [np.bitwise_xor.reduce(w32[b * 4096:(b + 1) * 4096]) for b in range(words)]
+    got = sink.cpu().numpy().view(np.uint32)
+    assert list(got[:words]) == want
+    assert int(sink[words:].count_nonzero()) == 0
+
+
 def test_stream_copy_is_exact(gpu_lib):
     """The bandwidth-reference copy moves every byte, including a ragged tail
     shorter than one block's 16 KiB."""
