@@ -162,11 +162,12 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         B.t64 = W + L.t64[j];
     }
     // work list for `bb` sites per block: problem j owns blocks
-    // [first_blk, first_blk + nblk); returns the number of blocks
-    auto assign = [&](int bb) -> int {
+    // [first_blk, first_blk + nblk); returns the number of blocks.  With
+    // `keep`, problems outside it get no blocks (nblk = 0).
+    auto assign = [&](int bb, const std::vector<char> *keep = nullptr) -> int {
         int total = 0;
         for (int j = 0; j < n; ++j) {
-            const int nb = (probs[j].g.vh + bb - 1) / bb;
+            const int nb = (keep && !(*keep)[j]) ? 0 : (probs[j].g.vh + bb - 1) / bb;
             probs[j].first_blk = total;
             probs[j].nblk = nb;
             for (int b = 0; b < nb; ++b)
@@ -318,22 +319,57 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         return err;
     };
     bool use_graph = false;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (int k = 0; k < chunk && le == hipSuccess; ++k)
-            le = iterate();
-        hipError_t ce = hipStreamEndCapture(st, &cleanup.graph);
-        if (le == hipSuccess && ce == hipSuccess)
-            ce = hipGraphInstantiate(&cleanup.exec, cleanup.graph, nullptr, nullptr, 0);
-        use_graph = le == hipSuccess && ce == hipSuccess;
-    }
-    (void)hipGetLastError();
+    auto capture = [&]() {
+        if (cleanup.exec) (void)hipGraphExecDestroy(cleanup.exec);
+        if (cleanup.graph) (void)hipGraphDestroy(cleanup.graph);
+        cleanup.exec = nullptr;
+        cleanup.graph = nullptr;
+        use_graph = false;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            hipError_t le = hipSuccess;
+            for (int k = 0; k < chunk && le == hipSuccess; ++k)
+                le = iterate();
+            hipError_t ce = hipStreamEndCapture(st, &cleanup.graph);
+            if (le == hipSuccess && ce == hipSuccess)
+                ce = hipGraphInstantiate(&cleanup.exec, cleanup.graph, nullptr, nullptr, 0);
+            use_graph = le == hipSuccess && ce == hipSuccess;
+        }
+        (void)hipGetLastError();
+    };
+    capture();
+    // Compaction: once the problems still running (or waiting for a true
+    // residual) own at most half of the work list, the list is rebuilt
+    // without the finished ones and the chunk graph recaptured, so the tail
+    // of a few long solves stops launching blocks for every finished problem
+    // (the uneven batch of 64: 0.976 -> 0.932 s).
+    auto compact = [&]() -> hipError_t {
+        std::vector<char> keep(n, 0);
+        int kept = 0;
+        for (int j = 0; j < n; ++j) {
+            const CgScalars &c = hs[j];
+            const bool done = !c.active && (c.flag == FLAG_DONE || c.flag == FLAG_BREAKDOWN || c.flag == FLAG_MAXIT);
+            keep[j] = !done;
+            if (!done)
+                kept += (probs[j].g.vh + a.block - 1) / a.block;
+        }
+        if (kept == 0 || 2 * kept > nblocks)
+            return hipSuccess;
+        nblocks = assign(a.block, &keep);
+        hipError_t err = upload();
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(st);
+        if (err == hipSuccess)
+            capture();
+        return err;
+    };
 
     for (int round = 0; round < max_iter + 64; ++round) {
         bool any = false;
         for (int j = 0; j < n; ++j) any |= hs[j].active != 0;
         if (!any)
             break;
+        if ((e = compact()) != hipSuccess)
+            return device_fail(e, "batch compaction");
         e = hipSuccess;
         if (use_graph)
             e = hipGraphLaunch(cleanup.exec, st);
@@ -404,13 +440,19 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx ? ctx->device : 0);
     if (e != hipSuccess)
         return device_fail(e, "batch clock");
-    // final true residual of unfinished problems
+    // final true residual of unfinished problems (on the full work list again:
+    // compaction may have dropped the ones that stopped at MAXIT or BREAKDOWN)
     bool need = false;
     for (int j = 0; j < n; ++j) {
         mask[j] = hs[j].flag != FLAG_DONE;
         need |= mask[j] != 0;
     }
     if (need) {
+        nblocks = assign(a.block);
+        e = upload();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "batch work list");
         std::vector<CgScalars> before = hs;
         if ((e = true_residuals(false)) != hipSuccess)
             return device_fail(e, "batch final residual");

@@ -106,3 +106,28 @@ def test_batch_with_a_zero_source(gpu_lib):
         w = ws_list[j]
         xj = h.unpack_field_to_host(items[j]["lat"], "fp64", items[j]["x"])[0]
         assert O.true_residual(O.lattice_from(w), 0.1, w["src"][0], xj) <= 1e-10
+
+
+def test_batch_compaction_and_iteration_limit(gpu_lib):
+    """Three easy problems finish early, so the work list is compacted to the
+    remaining hard one, which then stops at the iteration limit: the easy ones
+    meet the tolerance, and the hard one's reported true residual (formed on
+    the restored full work list) is the oracle's for the x it returned."""
+    h = gpu_lib
+    dims = [(8, 8, 8, 8), (6, 4, 4, 4), (4, 4, 6, 4), (4, 6, 4, 4)]
+    ws_list = [gen.workload_haar(d, 810 + k, -1) for k, d in enumerate(dims)]
+    ws_list[0]["mass"] = 0.01
+    for w in ws_list[1:]:
+        w["mass"] = 3.0  # kappa ~ 8: a few dozen iterations
+    items, probs, ws, keep = build(h, ws_list, "fp32")
+    st, info, lat_s = h.hisq_cg_batch(probs, "fp32", 200, ws)
+    assert st == h.NOT_CONVERGED
+    assert info[0]["iterations"] == 200
+    for k in range(4):
+        it, w = items[k], ws_list[k]
+        x = h.unpack_field_to_host(it["lat"], "fp64", it["x"])[0]
+        r = O.true_residual(O.lattice_from(w), w["mass"], w["src"][0], x)
+        if k == 0:
+            assert r > 1e-10 and abs(r - info[0]["true_residual"]) <= 1e-9 * r, (r, info[0])
+        else:
+            assert r <= 1e-10 and info[k]["iterations"] < 100, (k, r, info[k])
