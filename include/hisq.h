@@ -99,8 +99,10 @@ typedef enum {
 } hisq_status;
 
 /* Per-solve report (host).  true_residual = ||b - A x|| / ||b|| recomputed
- * in FP64 with FP64 links at the end of the solve; seconds = wall time of the
- * call. */
+ * in FP64 with FP64 links at the end of the solve; reliable_updates = how
+ * often the iterated residual was replaced by the FP64 b - A x and the
+ * recurrence restarted from it (reliable updates, and convergence signals the
+ * true residual did not confirm); seconds = wall time of the call. */
 typedef struct {
     int32_t iterations;
     int32_t reliable_updates;
