@@ -165,10 +165,14 @@ __global__ void __launch_bounds__(1024) cg_finalize_kernel(CgVecParams prm, int 
                     s.flag = FLAG_CONV;
                     s.active = 0;
                     prm.tr_skip[j] = 0;
+                    if (prm.nopend)
+                        *prm.nopend = 0;
                 } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
                     s.flag = FLAG_RELIABLE;
                     s.active = 0;
                     prm.tr_skip[j] = 0;
+                    if (prm.nopend)
+                        *prm.nopend = 0;
                 } else if (s.iters >= s.max_iter) {
                     s.flag = FLAG_MAXIT;
                     s.active = 0;
@@ -233,6 +237,8 @@ __global__ void __launch_bounds__(1024) cg_restart_kernel(CgVecParams prm, const
         any |= s.active;
     }
     *prm.skip = any ? 0 : 1;
+    if (prm.nopend)
+        *prm.nopend = 1;
 }
 
 // p = r + beta p for right-hand side rhs0 + blockIdx.y (if active; in restart

@@ -30,7 +30,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     int fs;  // sloppy field precision (FP64 or FP32)
     int nblk_max;
-    size_t state, shifts, ms, flags, scal, partials, dpart, r, p, q, t, ps, ax, t64, total;
+    size_t state, shifts, ms, flags, scal, partials, dpart, r, p, q, t, ps, ax, t64, t64m, axm, total;
 };
 
 Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
@@ -61,12 +61,17 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     const size_t f64 = field_bytes(g, HISQ_FP64, 1);
     L.ax = take(f64);
     L.t64 = take(f64);
+    // several right-hand sides: the true residuals of all columns in one
+    // multi-right-hand-side FP64 operator application
+    const int nm = nrhs > 1 ? nrhs : 0;
+    L.t64m = take(f64 * nm);
+    L.axm = take(f64 * nm);
     L.total = off;
     return L;
 }
 
 // flags[] slots
-enum { F_SKIP = 0, F_TR0 = 16 };  // F_TR0 + j: tr_skip of column j
+enum { F_SKIP = 0, F_NOPEND = 2, F_TR0 = 16 };  // F_NOPEND: no true residual pending; F_TR0 + j: tr_skip of column j
 // scal[] slots
 enum { S_TMP = 0 };
 
@@ -81,6 +86,7 @@ struct Solver {
     Layout L{};
     char *ws = nullptr;
     DslashShape shape64{};
+    DslashShape shape64m{};  // FP64 operator on all nrhs columns at once
     DslashShape shape_in{};
     int chunk = 16;
     double iter_us = 100.0;  // estimated time of one iteration
@@ -364,12 +370,52 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     vp.partials = S.partials();
     vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
     vp.tr_skip = trf;
+    int *nopend = reinterpret_cast<int *>(S.flags() + F_NOPEND);
+    vp.nopend = nopend;
     vp.nshift = 0;
 
     // true-residual block: columns that wait for one get r = b - A x and the
-    // FP64 partials of ||r||^2 (column j's in partials + j * nb)
+    // FP64 partials of ||r||^2 (column j's in partials + j * nb).  When the
+    // columns of x and b are one packed multi-column field each (hisq_cg),
+    // A x is formed for all of them by one multi-right-hand-side FP64
+    // operator application whenever any column waits (the links are read
+    // once, not once per column); otherwise column by column.
     const int nb = blas_blocks(g.vh);
+    const size_t c64 = S.f64_col();
+    bool packed = nrhs > 1;
+    for (int j = 1; j < nrhs && packed; ++j)
+        packed = static_cast<const char *>(C.x[j]) == static_cast<const char *>(C.x[0]) + j * c64 &&
+                 static_cast<const char *>(C.b[j]) == static_cast<const char *>(C.b[0]) + j * c64;
     auto tr_block = [&]() -> hipError_t {
+        if (packed) {
+            DslashParams prm{};
+            prm.g = g;
+            prm.nrhs = nrhs;
+            prm.links = S.links64;
+            prm.skip = nopend;
+            prm.out_parity = 1;
+            prm.in = C.x[0];
+            prm.out = S.at<void>(L.t64m);
+            hipError_t e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_PLAIN, S.shape64m, st);
+            if (e != hipSuccess)
+                return e;
+            prm.out_parity = 0;
+            prm.in = S.at<void>(L.t64m);
+            prm.out = S.at<void>(L.axm);
+            prm.y = C.x[0];
+            prm.ad = -1.0;
+            prm.ay = S.mass * S.mass + C.sigma[0];
+            prm.ay_per_rhs = 1;
+            for (int j = 0; j < nrhs; ++j)
+                prm.ay_rhs[j] = S.mass * S.mass + C.sigma[j];
+            e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, S.shape64m, st);
+            for (int j = 0; j < nrhs && e == hipSuccess; ++j)
+                e = launch_residual_parts(g.vh, L.fs, C.b[j], S.at<char>(L.axm) + j * c64, rs + j * cs,
+                                          S.partials() + (size_t)j * nb, trf + j, st);
+            if (e == hipSuccess)
+                e = launch_cg_restart(vp, S.partials(), st);
+            return e == hipSuccess ? launch_cg_p(vp, L.fs, 0, nrhs, st, true) : e;
+        }
         for (int j = 0; j < nrhs; ++j) {
             hipError_t e = S.m64(C.sigma[j], C.x[j], S.at<void>(L.ax), trf + j);
             if (e == hipSuccess)
@@ -712,6 +758,7 @@ hisq_status setup_solver(Solver &S, hisq_context *ctx, const hisq_lattice *lat, 
         return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, S.L.total);
     S.ws = static_cast<char *>(ws);
     S.shape64 = pick_shape(ctx, S.g, HISQ_FP64, HISQ_FP64, 1);
+    S.shape64m = nrhs > 1 ? pick_shape(ctx, S.g, HISQ_FP64, HISQ_FP64, nrhs) : S.shape64;
     S.shape_in = pick_shape(ctx, S.g, S.lp_in, S.L.fs, nrhs);
     // chunk length: ~1 ms of iterations, 8 .. 64
     const double bytes_per_iter = 2.0 * (double)S.g.vh * 16 * link_matrix_bytes(inner);

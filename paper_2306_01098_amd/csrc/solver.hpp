@@ -81,6 +81,7 @@ struct CgVecParams {
     // finalize kernel with FLAG_CONV / FLAG_RELIABLE, cleared by the
     // true-residual check), else 1; the check's kernels of column j skip on it
     int *tr_skip;
+    int *nopend;  // optional: 0 while any column waits for its true residual, else 1
     // multi-shift (nshift > 0): per-shift solutions and directions
     int nshift;
     ShiftScalars *sh;

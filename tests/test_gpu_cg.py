@@ -78,10 +78,13 @@ def test_multi_rhs_cg(gpu_lib, inner, nrhs):
     src = w["src"] * (10.0 ** np.arange(nrhs) % 7 + 1)[:, None, None]  # uneven norms
     lat, l64, lin, b, x, ws = setup(h, w, inner, nrhs, src=src)
     # one right-hand side per thread and the same block size for the batched
-    # and the single solve: the same summation order in every reduction
+    # and the single solve, in the iterations and in the FP64 true residuals
+    # (formed for all columns at once in the batched solve): the same
+    # summation order in every reduction
     ctx = h.Context(0)
-    h.hisq_set_dslash_shape(lat, inner, nrhs, (0, 1, 128, 1), ctx)
-    h.hisq_set_dslash_shape(lat, inner, 1, (0, 1, 128, 1), ctx)
+    for prec in {inner, "fp64"}:
+        h.hisq_set_dslash_shape(lat, prec, nrhs, (0, 1, 128, 1), ctx)
+        h.hisq_set_dslash_shape(lat, prec, 1, (0, 1, 128, 1), ctx)
     st, info = h.hisq_cg(lat, m, l64, lin, inner, nrhs, b, x, 1e-10, 20000, ws, ctx=ctx)
     assert st == h.OK, info
     res, xs = oracle_residuals(h, w, lat, x, nrhs, m, src)
