@@ -176,3 +176,29 @@ def test_multishift_with_r12_inner_links(gpu_lib):
     for k, sh in enumerate(shifts):
         xk = h.unpack_field_to_host(lat, "fp64", xs[k])[0]
         assert O.true_residual(lat_o, 0.05, w["src"][0], xk, shift=sh) <= 1e-10
+
+
+def test_multi_rhs_zero_column_and_iteration_limit(gpu_lib):
+    """Mixed-precision multi-RHS CG with one zero source: that column is done
+    before the first iteration (x stays 0) while the others reach the
+    tolerance through the batched FP64 true residuals; with a limit of 5
+    iterations every nonzero column stops at exactly 5."""
+    h = gpu_lib
+    nrhs = 4
+    w = gen.workload_smooth((8, 8, 8, 8), 46, -1, 0.3, nrhs)
+    src = w["src"].copy()
+    src[1] = 0.0
+    m = 0.1
+    lat, l64, lin, b, x, ws = setup(h, w, "fp32", nrhs, src=src)
+    st, info = h.hisq_cg(lat, m, l64, lin, "fp32", nrhs, b, x, 1e-10, 20000, ws)
+    assert st == h.OK, info
+    assert info[1]["iterations"] == 0
+    xs = h.unpack_field_to_host(lat, "fp64", x, nrhs)
+    assert not np.any(xs[1])
+    lat_o = O.lattice_from(w)
+    res = [O.true_residual(lat_o, m, src[j], xs[j]) for j in (0, 2, 3)]
+    assert max(res) <= 1e-10, res
+    x.zero_()
+    st, info = h.hisq_cg(lat, m, l64, lin, "fp32", nrhs, b, x, 1e-10, 5, ws)
+    assert st == h.NOT_CONVERGED
+    assert [i["iterations"] for i in info] == [5, 0, 5, 5]
