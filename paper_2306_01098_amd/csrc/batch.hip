@@ -14,7 +14,7 @@ namespace hisq {
 
 namespace {
 
-enum { FIN_PQ = 0, FIN_XR, FIN_RESID, FIN_BNORM };
+enum { FIN_PQ = 0, FIN_XR, FIN_RESID, FIN_BNORM, FIN_RESTART };
 constexpr int FIN_BLOCK = 256;  // four problems per finalize block
 
 template <int FP> struct SloppyT;
@@ -37,6 +37,8 @@ template <int LP, int FP, int ROLE, int TB>
 __global__ void __launch_bounds__(TB) batch_dslash_kernel(BatchArgs a) {
     using A = typename Prec<LP>::acc;
     if (ROLE <= ROLE_ITER_DEO && *a.nactive == 0)  // iterations stop once no problem is active
+        return;
+    if (ROLE > ROLE_ITER_DEO && *a.npend == 0)  // no problem waits for a true residual
         return;
     constexpr bool DOT = ROLE == ROLE_ITER_DEO;
     constexpr bool AXPY = ROLE == ROLE_ITER_DEO || ROLE == ROLE_TRUE_DEO;
@@ -126,12 +128,48 @@ __global__ void __launch_bounds__(TB) batch_xr_kernel(BatchArgs a) {
 //             active count
 //  FIN_RESID: st[j].rho_new = total (masked problems)
 //  FIN_BNORM: bnorm2[j] = total
+//  FIN_RESTART (no partials): the true-residual decision of each masked
+//             problem from st[j].rho_new = ||b - A x||^2: DONE, MAXIT,
+//             BREAKDOWN, or a residual replacement that restarts the
+//             recurrence (beta = ||r||^2 / rho, rho = rmax2 = ||r||^2; the
+//             problem rejoins the active count and is marked for p = r + beta p)
 __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, int mode, double *bnorm2) {
     if ((mode == FIN_PQ || mode == FIN_XR) && *a.nactive == 0)
         return;
     const int j = blockIdx.x * (FIN_BLOCK / 64) + (threadIdx.x >> 6);
     if (j >= a.nprob)  // uniform over the wavefront
         return;
+    if (mode == FIN_RESTART) {
+        if ((threadIdx.x & 63) != 0)
+            return;
+        CgScalars s = a.st[j];
+        s.restart = 0;
+        if (a.mask[j]) {
+            const double r2 = s.rho_new;
+            a.mask[j] = 0;
+            s.rtrue2 = r2;
+            if (!(r2 >= 0.0 && r2 < 1.0e308)) {
+                s.flag = FLAG_BREAKDOWN;
+            } else if (r2 <= s.target2) {
+                s.flag = FLAG_DONE;
+            } else if (s.iters >= s.max_iter) {
+                s.flag = FLAG_MAXIT;
+            } else {
+                s.nrel += 1;
+                s.beta = r2 / s.rho;
+                s.rho = r2;
+                s.rmax2 = r2;
+                s.flag = FLAG_RUN;
+                s.active = 1;
+                s.restart = 1;
+                atomicAdd(a.nactive, 1);
+            }
+        }
+        a.st[j] = s;
+        if (j == 0)
+            *a.npend = 0;  // read by later launches only
+        return;
+    }
     const BatchProb &P = a.probs[j];
     const double tot = wave_sum_slot(a.partials + P.first_blk, P.nblk);
     if ((threadIdx.x & 63) != 0)
@@ -165,9 +203,13 @@ __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, 
         } else if (rho_new <= s.target2) {
             s.flag = FLAG_CONV;
             s.active = 0;
+            a.mask[j] = 1;  // true residual at the next check
+            *a.npend = 1;
         } else if (s.delta2 > 0.0 && rho_new < s.delta2 * s.rmax2) {
             s.flag = FLAG_RELIABLE;
             s.active = 0;
+            a.mask[j] = 1;
+            *a.npend = 1;
         } else if (s.iters >= s.max_iter) {
             s.flag = FLAG_MAXIT;
             s.active = 0;
@@ -184,8 +226,9 @@ __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, 
     a.st[j] = s;
 }
 
-// p = r + beta p for active problems.
-template <int FP, int TB>
+// p = r + beta p for active problems (RESTART: for the problems the last
+// true-residual decision restarted).
+template <int FP, int TB, bool RESTART>
 __global__ void __launch_bounds__(TB) batch_p_kernel(BatchArgs a) {
     using T = typename SloppyT<FP>::T;
     if (*a.nactive == 0)
@@ -195,7 +238,7 @@ __global__ void __launch_bounds__(TB) batch_p_kernel(BatchArgs a) {
     const BatchProb &P = a.probs[j];
     const int i = (blk - P.first_blk) * TB + threadIdx.x;
     const CgScalars st = a.st[j];
-    if (!st.active || i >= P.g.vh)
+    if (!(RESTART ? st.restart : st.active) || i >= P.g.vh)
         return;
     cplx<T> p[3], r[3];
     FieldIO<FP>::template load<T>(P.p, P.g.vh, 0, i, p);
@@ -214,6 +257,8 @@ __global__ void __launch_bounds__(TB) batch_p_kernel(BatchArgs a) {
 template <int FP, int TB>
 __global__ void __launch_bounds__(TB) batch_residual_kernel(BatchArgs a, int copy_p) {
     using T = typename SloppyT<FP>::T;
+    if (*a.npend == 0)
+        return;
     const int blk = blockIdx.x;
     const int j = a.blk_prob[blk];
     const BatchProb &P = a.probs[j];
@@ -293,8 +338,12 @@ hipError_t launch_batch_tb(const BatchArgs &a, int nblocks, int op, int lp, hipS
         else batch_xr_kernel<HISQ_FP32, TB><<<g, TB, 0, st>>>(a);
         break;
     case BOP_P:
-        if (f64) batch_p_kernel<HISQ_FP64, TB><<<g, TB, 0, st>>>(a);
-        else batch_p_kernel<HISQ_FP32, TB><<<g, TB, 0, st>>>(a);
+        if (f64) batch_p_kernel<HISQ_FP64, TB, false><<<g, TB, 0, st>>>(a);
+        else batch_p_kernel<HISQ_FP32, TB, false><<<g, TB, 0, st>>>(a);
+        break;
+    case BOP_RESTART:
+        if (f64) batch_p_kernel<HISQ_FP64, TB, true><<<g, TB, 0, st>>>(a);
+        else batch_p_kernel<HISQ_FP32, TB, true><<<g, TB, 0, st>>>(a);
         break;
     case BOP_RESIDUAL:
     case BOP_RESIDUAL_COPY_P: {
@@ -312,6 +361,12 @@ hipError_t launch_batch_tb(const BatchArgs &a, int nblocks, int op, int lp, hipS
 }  // namespace
 
 hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st) {
+    if (op == BOP_RESTART) {
+        batch_finalize_kernel<<<(a.nprob + 3) / 4, FIN_BLOCK, 0, st>>>(a, FIN_RESTART, nullptr);
+        const hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess)
+            return e0;
+    }
     hipError_t e = a.block == 64    ? launch_batch_tb<64>(a, nblocks, op, lp, st)
                    : a.block == 128 ? launch_batch_tb<128>(a, nblocks, op, lp, st)
                    : a.block == 256 ? launch_batch_tb<256>(a, nblocks, op, lp, st)

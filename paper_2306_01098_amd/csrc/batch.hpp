@@ -29,16 +29,18 @@ struct BatchArgs {
     int nprob;
     const int *blk_prob;  // work list: problem of each block
     CgScalars *st;        // [nprob]
-    const int *mask;      // [nprob] problems taking part in a true-residual pass
+    int *mask;            // [nprob] problems taking part in a true-residual pass
     double *partials;     // [nblocks]
     int *nactive;         // problems still iterating: iteration kernels do nothing at 0
+    int *npend;           // nonzero while some problem waits for its true residual
     int block;            // sites per block (64, 128, 256)
 };
 
 enum { ROLE_ITER_DOE = 0, ROLE_ITER_DEO = 1, ROLE_TRUE_DOE = 2, ROLE_TRUE_DEO = 3 };
 enum {
     BOP_ITER_DOE = 0, BOP_ITER_DEO, BOP_TRUE_DOE, BOP_TRUE_DEO, BOP_XR, BOP_P, BOP_RESIDUAL,
-    BOP_RESIDUAL_COPY_P, BOP_BNORM
+    BOP_RESIDUAL_COPY_P, BOP_BNORM,
+    BOP_RESTART  // true-residual decision of the masked problems, then p = r + beta p for the restarted
 };
 
 hipError_t launch_batch(const BatchArgs &a, int nblocks, int op, int lp, hipStream_t st);

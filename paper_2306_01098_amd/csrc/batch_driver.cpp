@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "api_util.hpp"
@@ -61,7 +62,7 @@ double wall_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-enum { BF_NACTIVE = 0 };
+enum { BF_NACTIVE = 0, BF_NPEND = 1 };
 
 }  // namespace
 
@@ -181,10 +182,11 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     a.nprob = n;
     a.blk_prob = reinterpret_cast<const int *>(W + L.blk);
     a.st = reinterpret_cast<CgScalars *>(W + L.state);
-    a.mask = reinterpret_cast<const int *>(W + L.mask);
+    a.mask = reinterpret_cast<int *>(W + L.mask);
     a.partials = reinterpret_cast<double *>(W + L.partials);
     unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
     a.nactive = reinterpret_cast<int *>(flags + BF_NACTIVE);
+    a.npend = reinterpret_cast<int *>(flags + BF_NPEND);
     a.block = 128;
     double *scal = reinterpret_cast<double *>(W + L.scal);  // [0..n) ||b||^2, [MAX_BATCH] start clock
     int *mask_d = reinterpret_cast<int *>(W + L.mask);
@@ -201,8 +203,12 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
             if (err == hipSuccess)
                 err = hipMemcpyAsync(flags + BF_NACTIVE, &nact, sizeof nact, hipMemcpyHostToDevice, st);
         }
-        if (msk && err == hipSuccess)
+        if (msk && err == hipSuccess) {
+            static const int one = 1;  // a host-driven true-residual pass: let its kernels run
             err = hipMemcpyAsync(mask_d, mask.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(flags + BF_NPEND, &one, sizeof one, hipMemcpyHostToDevice, st);
+        }
         if (err == hipSuccess)
             err = hipStreamSynchronize(st);
         return err;
@@ -290,6 +296,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     for (int j = 0; j < n; ++j) {
         CgScalars c{};
         rtrue2[j] = hs[j].rho_new;
+        c.rtrue2 = rtrue2[j];
         c.rho = rtrue2[j];
         c.rmax2 = rtrue2[j];
         c.target2 = problems[j].tol * problems[j].tol * bnorm2[j];
@@ -307,17 +314,47 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         hs[j] = c;
     }
     e = push(true, false);
+    // no problem waits for a true residual yet (the masks of the start are spent)
+    std::fill(mask.begin(), mask.end(), 0);
+    static const int zero = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(mask_d, mask.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags + BF_NPEND, &zero, sizeof zero, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = launch_batch_clock(scal + MAX_BATCH, st);
     if (e != hipSuccess)
         return device_fail(e, "batch start");
 
-    // graph of one chunk of batched iterations
-    const int chunk = 16;
+    // graph of one chunk of batched iterations.  Every `check` iterations a
+    // true-residual block serves the problems that raised FLAG_CONV or
+    // FLAG_RELIABLE since the last one (their mask is set on the device): FP64
+    // r = b - A x, then the decision (DONE / MAXIT / residual replacement) and
+    // p = r + beta p for the restarted problems, all without the host; the
+    // launches of the block do nothing while no problem waits.  A block every
+    // 16 iterations (uneven batch of 64: 0.88-0.89 s, against 0.89-0.90 s with
+    // the host deciding between chunks); every 4 its idle launches cost more
+    // than they save (0.917 s).
+    const int chunk = 32, check = 16;
     auto iterate = [&]() -> hipError_t {
         hipError_t err = launch_batch(a, nblocks, BOP_ITER_DOE, lp, st);
         if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_ITER_DEO, lp, st);
         if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_XR, lp, st);
         if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_P, lp, st);
+        return err;
+    };
+    auto tr_block = [&]() -> hipError_t {
+        hipError_t err = launch_batch(a, nblocks, BOP_TRUE_DOE, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_TRUE_DEO, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_RESIDUAL, lp, st);
+        if (err == hipSuccess) err = launch_batch(a, nblocks, BOP_RESTART, lp, st);
+        return err;
+    };
+    auto chunk_eager = [&]() -> hipError_t {
+        hipError_t err = hipSuccess;
+        for (int k = 0; k < chunk && err == hipSuccess; ++k) {
+            err = iterate();
+            if (err == hipSuccess && (k + 1) % check == 0)
+                err = tr_block();
+        }
         return err;
     };
     bool use_graph = false;
@@ -328,9 +365,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         cleanup.graph = nullptr;
         use_graph = false;
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            hipError_t le = hipSuccess;
-            for (int k = 0; k < chunk && le == hipSuccess; ++k)
-                le = iterate();
+            const hipError_t le = chunk_eager();
             hipError_t ce = hipStreamEndCapture(st, &cleanup.graph);
             if (le == hipSuccess && ce == hipSuccess)
                 ce = hipGraphInstantiate(&cleanup.exec, cleanup.graph, nullptr, nullptr, 0);
@@ -339,25 +374,29 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         (void)hipGetLastError();
     };
     capture();
-    // Compaction: once the problems still running (or waiting for a true
-    // residual) own at most half of the work list, the list is rebuilt
-    // without the finished ones and the chunk graph recaptured, so the tail
-    // of a few long solves stops launching blocks for every finished problem
-    // (the uneven batch of 64: 0.976 -> 0.932 s).
+    auto terminal = [&](const CgScalars &c) {
+        return !c.active && (c.flag == FLAG_DONE || c.flag == FLAG_BREAKDOWN || c.flag == FLAG_MAXIT);
+    };
+    // Compaction: once the problems still running own at most half of the
+    // work list, the list is rebuilt without the finished ones and the chunk
+    // graph recaptured, so the tail of a few long solves stops launching
+    // blocks for every finished problem (the uneven batch of 64: 0.976 ->
+    // 0.932 s).  The stream must be idle (the work list is in use).
     auto compact = [&]() -> hipError_t {
         std::vector<char> keep(n, 0);
         int kept = 0;
         for (int j = 0; j < n; ++j) {
-            const CgScalars &c = hs[j];
-            const bool done = !c.active && (c.flag == FLAG_DONE || c.flag == FLAG_BREAKDOWN || c.flag == FLAG_MAXIT);
-            keep[j] = !done;
-            if (!done)
+            keep[j] = !terminal(hs[j]);
+            if (keep[j])
                 kept += (probs[j].g.vh + a.block - 1) / a.block;
         }
         if (kept == 0 || 2 * kept > nblocks)
             return hipSuccess;
-        nblocks = assign(a.block, &keep);
-        hipError_t err = upload();
+        hipError_t err = hipStreamSynchronize(st);
+        if (err == hipSuccess) {
+            nblocks = assign(a.block, &keep);
+            err = upload();
+        }
         if (err == hipSuccess)
             err = hipStreamSynchronize(st);
         if (err == hipSuccess)
@@ -365,75 +404,96 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         return err;
     };
 
-    for (int round = 0; round < max_iter + 64; ++round) {
-        bool any = false;
-        for (int j = 0; j < n; ++j) any |= hs[j].active != 0;
-        if (!any)
-            break;
-        if ((e = compact()) != hipSuccess)
-            return device_fail(e, "batch compaction");
-        e = hipSuccess;
-        if (use_graph)
-            e = hipGraphLaunch(cleanup.exec, st);
-        for (int k = 0; !use_graph && k < chunk && e == hipSuccess; ++k)
-            e = iterate();
-        if (e == hipSuccess) e = pull();
+    // state read-back into pinned memory, a second chunk queued meanwhile
+    struct Pinned {
+        CgScalars *p = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        ~Pinned() {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            if (p) (void)hipHostFree(p);
+        }
+    } pin;
+    e = hipHostMalloc(reinterpret_cast<void **>(&pin.p), sizeof(CgScalars) * n * 2, hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&pin.ev[k], hipEventDisableTiming);
+    if (e != hipSuccess)
+        return device_fail(e, "batch read-back setup");
+    long launched = 0, read = 0;
+    auto launch_chunk = [&]() -> hipError_t {
+        hipError_t err = use_graph ? hipGraphLaunch(cleanup.exec, st) : chunk_eager();
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(pin.p + (launched % 2) * n, a.st, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, st);
+        if (err == hipSuccess)
+            err = hipEventRecord(pin.ev[launched % 2], st);
+        if (err == hipSuccess)
+            ++launched;
+        return err;
+    };
+    bool finished = true;
+    for (int j = 0; j < n; ++j)
+        finished = finished && terminal(hs[j]);
+    const long max_chunks = (long)max_iter * check / chunk + 8;
+    if (!finished)
+        e = launch_chunk();
+    while (!finished && e == hipSuccess) {
+        if (launched == read + 1 && launched < max_chunks)
+            e = launch_chunk();
+        if (e == hipSuccess)
+            e = hipEventSynchronize(pin.ev[read % 2]);
         if (e != hipSuccess)
-            return device_fail(e, "batch chunk");
-        // batched true residual for every problem that raised a flag
-        bool need = false;
-        for (int j = 0; j < n; ++j) {
-            mask[j] = !hs[j].active && (hs[j].flag == FLAG_CONV || hs[j].flag == FLAG_RELIABLE);
-            need |= mask[j] != 0;
-        }
-        if (!need)
-            continue;
-        std::vector<CgScalars> before = hs;
-        if ((e = true_residuals(false)) != hipSuccess)
-            return device_fail(e, "batch reliable update");
-        std::vector<int> restart(n, 0);
-        bool any_restart = false;
-        for (int j = 0; j < n; ++j) {
-            CgScalars c = before[j];
-            if (!mask[j]) {
-                hs[j] = c;
-                continue;
-            }
-            rtrue2[j] = hs[j].rho_new;
-            if (!std::isfinite(rtrue2[j])) {
-                c.flag = FLAG_BREAKDOWN;
-                breakdown = true;
-            } else if (rtrue2[j] <= c.target2) {
-                c.flag = FLAG_DONE;
-                t_stop[j] = c.spare;
-            } else if (c.iters >= c.max_iter) {
-                c.flag = FLAG_MAXIT;
-            } else {
-                reliable[j] += 1;
-                c.beta = rtrue2[j] / c.rho;
-                c.rho = rtrue2[j];
-                c.rmax2 = rtrue2[j];
-                c.flag = FLAG_RUN;
-                restart[j] = 1;
-                any_restart = true;
-            }
-            hs[j] = c;
-        }
-        if (any_restart) {
-            // p = r + beta p for the restarted problems only
-            std::vector<CgScalars> only = hs;
-            for (int j = 0; j < n; ++j) only[j].active = restart[j];
-            std::swap(only, hs);
-            e = push(true, false);
-            if (e == hipSuccess) e = launch_batch(a, nblocks, BOP_P, lp, st);
-            std::swap(only, hs);
+            break;
+        std::memcpy(hs.data(), pin.p + (read % 2) * n, sizeof(CgScalars) * n);
+        ++read;
+        finished = true;
+        for (int j = 0; j < n; ++j)
+            finished = finished && terminal(hs[j]);
+        if (finished)
+            break;
+        if (launched > read) {
+            // a chunk is still queued: compact only from an idle stream
+            bool want = false;
+            int kept = 0;
             for (int j = 0; j < n; ++j)
-                if (restart[j]) hs[j].active = 1;
-            if (e != hipSuccess)
-                return device_fail(e, "batch restart");
+                if (!terminal(hs[j]))
+                    kept += (probs[j].g.vh + a.block - 1) / a.block;
+            want = 2 * kept <= nblocks;
+            if (want) {
+                e = hipEventSynchronize(pin.ev[read % 2]);
+                if (e != hipSuccess)
+                    break;
+                std::memcpy(hs.data(), pin.p + (read % 2) * n, sizeof(CgScalars) * n);
+                ++read;
+                finished = true;
+                for (int j = 0; j < n; ++j)
+                    finished = finished && terminal(hs[j]);
+                if (finished)
+                    break;
+                e = compact();
+            }
+        } else {
+            e = compact();
         }
-        if ((e = push(true, false)) != hipSuccess)
-            return device_fail(e, "batch state");
+        if (e == hipSuccess && launched == read) {
+            if (launched >= max_chunks)
+                break;
+            e = launch_chunk();
+        }
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return device_fail(e, "batch chunk");
+    if (launched > read)
+        std::memcpy(hs.data(), pin.p + ((launched - 1) % 2) * n, sizeof(CgScalars) * n);
+    for (int j = 0; j < n; ++j) {
+        if (hs[j].flag == FLAG_DONE) {
+            rtrue2[j] = hs[j].rtrue2;
+            t_stop[j] = hs[j].spare;
+        }
+        if (hs[j].flag == FLAG_BREAKDOWN)
+            breakdown = true;
+        reliable[j] = hs[j].nrel;
     }
     double clock0 = 0.0;
     e = hipMemcpyAsync(&clock0, scal + MAX_BATCH, sizeof(double), hipMemcpyDeviceToHost, st);
