@@ -427,11 +427,13 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         hipError_t e = launch_cg_restart(vp, S.partials(), st);
         return e == hipSuccess ? launch_cg_p(vp, L.fs, 0, nrhs, st, true) : e;
     };
-    // iterations between blocks: a flagged column idles until the next one;
-    // FP64 iterations flag only at convergence.  Chunks of about 0.5 ms
-    // (measured: longer chunks overshoot more at the end of a solve).
-    const int check = delta > 0.0 ? 4 : 8;
-    const int chunk = check * std::max(1, (int)std::lround(500.0 / (check * S.iter_us)));
+    // iterations between blocks: a flagged column idles until the next one.
+    // Chunks of about 0.5 ms (measured: longer chunks overshoot more at the
+    // end of a solve).  FP64 iterations flag only at convergence, so they need
+    // one block per chunk.
+    const int unit = delta > 0.0 ? 4 : 8;
+    const int chunk = unit * std::max(1, (int)std::lround(500.0 / (unit * S.iter_us)));
+    const int check = delta > 0.0 ? 4 : chunk;
     auto chunk_eager = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int k = 0; k < chunk && e == hipSuccess; ++k) {
