@@ -267,6 +267,61 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
     zero<NIN, A>(acc);
     cplx<A> tmp[NIN][3];
     zero<NIN, A>(tmp);
+    if constexpr (NIN > 1) {
+        // several right-hand sides: the neighbour vectors two hops ahead, the
+        // links one (16 rhs at 48^3x12: FP64 948 -> 918 us, FP32 534 -> 522 us;
+        // at one rhs the FP64 kernel was 2 % slower, so it keeps one hop)
+        HopBuf<NIN, A> lb[2];
+        cplx<A> vb[3][NIN][3];
+        A sgv[3];
+        bool bkv[3];
+        auto load_link = [&](int k, int slot) {
+            A sg;
+            const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
+            LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, lb[slot].m);
+        };
+        auto load_vec = [&](int k, int slot) {
+            A sg;
+            const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+                if (r < nr)
+                    FieldIO<FP>::template load<A>(in, g.vh, r0 + r, h.ipsi, vb[slot][r]);
+            sgv[slot] = sg;
+            bkv[slot] = h.back;
+        };
+        load_vec(0, 0);
+        load_link(0, 0);
+        load_vec(1, 1);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int cur = k & 1, vc = k % 3;
+            if (k + 2 < 16)
+                load_vec(k + 2, (k + 2) % 3);
+            if (k + 1 < 16)
+                load_link(k + 1, cur ^ 1);
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    lb[cur].v[r][c] = vb[vc][r][c];
+            hop_apply<LP, NIN, A>(lb[cur], bkv[vc], sgv[vc], nr, tmp);
+            if ((k & 3) == 3) {
+                const int mu = k >> 2;
+                const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+                const A eta = (par & 1) ? (A)-1 : (A)1;
+#pragma unroll
+                for (int r = 0; r < NIN; ++r)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        acc[r][a].re = fma(eta, tmp[r][a].re, acc[r][a].re);
+                        acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
+                        tmp[r][a].re = tmp[r][a].im = (A)0;
+                    }
+            }
+        }
+        return;
+    }
     HopBuf<NIN, A> buf[2];
     A sgn[2];
     bool back[2];
