@@ -102,12 +102,18 @@ typedef enum {
  * in FP64 with FP64 links at the end of the solve; reliable_updates = how
  * often the iterated residual was replaced by the FP64 b - A x and the
  * recurrence restarted from it (reliable updates, and convergence signals the
- * true residual did not confirm); seconds = wall time of the call. */
+ * true residual did not confirm); seconds = wall time of the call.
+ * Multi-shift solves split `iterations` into shared_iterations (iterations of
+ * the shared Krylov space until this shift was frozen) and
+ * refine_iterations (iterations of this shift's refinement CG afterwards);
+ * every other solver reports shared_iterations = refine_iterations = 0. */
 typedef struct {
     int32_t iterations;
     int32_t reliable_updates;
     double true_residual;
     double seconds;
+    int32_t shared_iterations;
+    int32_t refine_iterations;
 } hisq_solve_info;
 
 /* Opaque context: device ordinal and the autotuning cache.  May be NULL in
@@ -195,6 +201,33 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
                          double mass, const void *links, const void *in_even, void *out_even,
                          void *tmp_odd, int32_t nrhs, void *stream);
 
+/* out_even = (m^2) in_even - D_eo D_oe in_even as in hisq_apply_m, with the
+ * link and field precisions given separately so that every operator the
+ * solvers iterate with can be applied on its own, and
+ * dot_out[r] = Re <in_r, out_r> for each right-hand side r: the fused
+ * <p, M_e p> of the CG iteration (Sec. 3.2), summed in FP64 over the
+ * products of the loaded in-values and the computed out-values before the
+ * out field is rounded to its storage format, block partials first and then
+ * one fixed-order pass (deterministic).
+ *   link_prec, field_prec  one of the pairs the solvers use: (FP64, FP64),
+ *               (FP32, FP32), (FP16N, FP16N), (FP16N, FP32) (binary16 links
+ *               with FP32 vectors, the inner operator of hisq_cg with
+ *               inner = HISQ_FP16N), (FP64R12, FP64), (FP32R12, FP32);
+ *               anything else is HISQ_ERR_INVALID_ARG.
+ *   links       packed links of link_prec; in_even, out_even (even sites) and
+ *               tmp_odd (odd sites, scratch) packed fields of nrhs columns in
+ *               field_prec; distinct buffers.
+ *   dot_out     device array of nrhs doubles.
+ *   ws          device workspace of hisq_apply_m_dot_workspace_bytes(lat, nrhs)
+ *               bytes (the block partials).
+ * The launch shape is the one hisq_get_dslash_shape reports for link_prec
+ * (a shape set for HISQ_FP16N covers both FP16N pairs).  Asynchronous. */
+size_t hisq_apply_m_dot_workspace_bytes(const hisq_lattice *lat, int32_t nrhs);
+hisq_status hisq_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, hisq_prec link_prec,
+                             hisq_prec field_prec, double mass, const void *links, const void *in_even,
+                             void *out_even, void *tmp_odd, int32_t nrhs, double *dot_out, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* Workspace bytes for hisq_cg (nshift = 0) or hisq_multishift_cg (nrhs = 1,
  * nshift shifts) with inner precision `inner`.  0 on invalid arguments. */
 size_t hisq_cg_workspace_bytes(const hisq_lattice *lat, hisq_prec inner, int32_t nrhs, int32_t nshift);
@@ -259,12 +292,28 @@ hisq_status hisq_chiral_condensate(hisq_context *ctx, const hisq_lattice *lat, d
  *                HISQ_FP64 fields (overwritten; the initial guess is zero).
  *   ws           workspace of hisq_cg_workspace_bytes(lat, inner, 1, nshift).
  *   info         host array [nshift]; iterations = shared Krylov iterations up
- *                to the freeze + refinement iterations.
+ *                to the freeze (shared_iterations) + refinement iterations
+ *                (refine_iterations).
  * Other arguments and statuses as for hisq_cg.  Synchronous. */
 hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
                                const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
                                const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
                                size_t ws_bytes, hisq_solve_info *info, void *stream);
+
+/* The shared Krylov phase of hisq_multishift_cg alone, without the
+ * refinement: on return x[k] holds the multi-shift iterate of shift k at the
+ * iteration where it was frozen (|zeta_k| ||r|| <= tol[k] ||b||, or where the
+ * smallest shift met its own tolerance), info[k].iterations =
+ * info[k].shared_iterations = that iteration, and info[k].true_residual its
+ * FP64 true residual ||b - (M_e + shifts[k]) x[k]|| / ||b||.  Returns HISQ_OK
+ * when every shift meets its tolerance, HISQ_ERR_NOT_CONVERGED otherwise
+ * (with a reduced-precision inner operator the Krylov iterates stall near
+ * that precision, which is why hisq_multishift_cg refines them).  Same
+ * arguments and workspace as hisq_multishift_cg.  Synchronous. */
+hisq_status hisq_multishift_krylov(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                                   const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                                   const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                                   size_t ws_bytes, hisq_solve_info *info, void *stream);
 
 /* One problem of a batched solve. */
 typedef struct {
@@ -295,8 +344,8 @@ size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *prob
  *   problems    host array [nproblems]; the structs may be freed on return.
  *   info        host array [nproblems] (seconds = wall time of the batch).
  *   latency_s   host array [nproblems] or NULL: device-clock time from the
- *               start of the batched iterations to the iteration at which the
- *               problem's solution met its tolerance.
+ *               start of the batched iterations to the FP64 true-residual
+ *               check that confirmed the problem's solution.
  * Statuses as for hisq_cg (NOT_CONVERGED / BREAKDOWN if any problem ends so).
  * Synchronous. */
 hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_problem *problems, hisq_prec inner,

@@ -23,6 +23,7 @@ definition.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from dataclasses import dataclass
@@ -30,28 +31,46 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# HISQ_ORACLE_LIB lets a mutation check load a deliberately broken build.
-LIB_PATH = os.environ.get("HISQ_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def _open(path: str):
+    if not os.path.exists(path):
+        raise RuntimeError(f"oracle library not built: {path}")
+    lib_ = ctypes.CDLL(path)
+    lib_.oracle_dslash.restype = ctypes.c_int
+    lib_.oracle_dslash.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int]
+    lib_.oracle_dslash_sites.restype = ctypes.c_int
+    lib_.oracle_dslash_sites.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p]
+    lib_.oracle_num_threads.restype = ctypes.c_int
+    return lib_
+
+
 def lib():
-    """The compiled C oracle (built by ``oracle/build.sh``)."""
+    """The compiled C oracle (built by ``oracle/build.sh`` next to this file)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"oracle library not built: {LIB_PATH}")
-        _lib = ctypes.CDLL(LIB_PATH)
-        _lib.oracle_dslash.restype = ctypes.c_int
-        _lib.oracle_dslash.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_int]
-        _lib.oracle_dslash_sites.restype = ctypes.c_int
-        _lib.oracle_dslash_sites.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int,
-                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                             ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p]
-        _lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = _open(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def substituted_library(path: str):
+    """For the mutation check of the pins only: inside the block every oracle
+    call goes to the C library at ``path`` (a build of a deliberately altered
+    ``hisq_oracle.c``); the previous library is restored on exit."""
+    global _lib
+    saved = _lib
+    _lib = _open(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def num_threads() -> int:

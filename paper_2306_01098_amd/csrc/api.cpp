@@ -71,6 +71,73 @@ hisq_status set_device(hisq_context *ctx) {
     return e == hipSuccess ? HISQ_OK : device_fail(e, "hipSetDevice");
 }
 
+size_t apply_m_dot_partials_max(const Geom &g, int nrhs) {
+    // the smallest site block of any launch shape is 16 sites (four lanes per
+    // site in blocks of 64 threads)
+    return (size_t)nrhs * (size_t)((g.vh + 15) / 16);
+}
+
+hisq_status check_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, int link_prec, int field_prec, double mass,
+                              const void *links, const void *in_even, void *out_even, void *tmp_odd, int nrhs,
+                              double *dot_out, ApplyMDot *a) {
+    TRY(check_lattice(lat));
+    TRY(check_prec(link_prec));
+    TRY(check_prec(field_prec));
+    TRY(check_nrhs(nrhs));
+    const int fp = field_prec_of(field_prec);
+    if (fp != field_prec_of(link_prec) && !(link_prec == HISQ_FP16N && fp == HISQ_FP32))
+        return fail(HISQ_ERR_INVALID_ARG, "no operator with links of precision %d and fields of precision %d",
+                    link_prec, field_prec);
+    TRY(check_ptr(links, "links"));
+    TRY(check_ptr(in_even, "in_even"));
+    TRY(check_ptr(out_even, "out_even"));
+    TRY(check_ptr(tmp_odd, "tmp_odd"));
+    TRY(check_ptr(dot_out, "dot_out"));
+    if (in_even == out_even || tmp_odd == in_even || tmp_odd == out_even)
+        return fail(HISQ_ERR_INVALID_ARG, "in_even, out_even and tmp_odd must be distinct");
+    if (!(mass == mass) || mass * mass <= 0.0 || mass * mass > 1e300)
+        return fail(HISQ_ERR_INVALID_ARG, "mass^2 must be positive and finite (mass = %g)", mass);
+    a->g = make_geom(*lat);
+    a->lp = link_prec;
+    a->fp = fp;
+    a->mass = mass;
+    a->links = static_cast<const char *>(links);
+    a->in = in_even;
+    a->out = out_even;
+    a->tmp = tmp_odd;
+    a->nrhs = nrhs;
+    a->dot = dot_out;
+    a->shape = pick_shape(ctx, a->g, link_prec, fp, nrhs);
+    a->partials = (size_t)nrhs * dslash_partial_blocks(a->g, a->shape);
+    return HISQ_OK;
+}
+
+// D_oe in -> tmp, then out = m^2 in - D_eo tmp with the block partials of
+// Re <in, out> in `partials` and their fixed-order sum in dot[0..nrhs).
+hisq_status run_apply_m_dot(const ApplyMDot &a, double *partials, hipStream_t st) {
+    DslashParams prm{};
+    prm.g = a.g;
+    prm.nrhs = a.nrhs;
+    prm.links = a.links;
+    prm.out_parity = 1;
+    prm.in = a.in;
+    prm.out = a.tmp;
+    hipError_t e = launch_dslash(prm, a.lp, a.fp, EPI_PLAIN, a.shape, st);
+    if (e != hipSuccess)
+        return device_fail(e, "apply_m_dot (D_oe)");
+    prm.out_parity = 0;
+    prm.in = a.tmp;
+    prm.out = a.out;
+    prm.y = a.in;
+    prm.ad = -1.0;
+    prm.ay = a.mass * a.mass;
+    prm.partials = partials;
+    prm.dot_out = a.dot;
+    prm.dot_stride = 1;
+    e = launch_dslash(prm, a.lp, a.fp, EPI_AXPY_DOT, a.shape, st);
+    return e == hipSuccess ? HISQ_OK : device_fail(e, "apply_m_dot (D_eo)");
+}
+
 DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs) {
     if (ctx) {
         DslashShape s;
@@ -246,6 +313,26 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
     prm.ay = mass * mass;
     e = launch_dslash(prm, prec, field_prec_of(prec), EPI_AXPY, s, st);
     return e == hipSuccess ? HISQ_OK : device_fail(e, "apply_m (D_eo)");
+}
+
+size_t hisq_apply_m_dot_workspace_bytes(const hisq_lattice *lat, int32_t nrhs) {
+    if (check_lattice(lat) != HISQ_OK || check_nrhs(nrhs) != HISQ_OK)
+        return 0;
+    return apply_m_dot_partials_max(make_geom(*lat), nrhs) * sizeof(double);
+}
+
+hisq_status hisq_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, hisq_prec link_prec, hisq_prec field_prec,
+                             double mass, const void *links, const void *in_even, void *out_even, void *tmp_odd,
+                             int32_t nrhs, double *dot_out, void *ws, size_t ws_bytes, void *stream) {
+    ApplyMDot a;
+    TRY(check_apply_m_dot(ctx, lat, link_prec, field_prec, mass, links, in_even, out_even, tmp_odd, nrhs, dot_out,
+                          &a));
+    TRY(check_ptr(ws, "ws"));
+    const size_t need = a.partials * sizeof(double);
+    if (ws_bytes < need)
+        return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, need);
+    TRY(set_device(ctx));
+    return run_apply_m_dot(a, static_cast<double *>(ws), static_cast<hipStream_t>(stream));
 }
 
 hisq_status hisq_stream_copy(hisq_context *ctx, const void *src, void *dst, size_t bytes, void *stream) {

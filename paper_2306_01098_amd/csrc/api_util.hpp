@@ -51,6 +51,26 @@ hisq_status set_device(hisq_context *ctx);
     } while (0)
 
 DslashShape pick_shape(hisq_context *ctx, const Geom &g, int lp, int fp, int nrhs);
+
+// M_e with the fused Re <in, out> (hisq_apply_m_dot and its variants): the
+// checked arguments, the launch shape and the number of block partials.
+struct ApplyMDot {
+    Geom g;
+    int lp, fp;
+    double mass;
+    const char *links;
+    const void *in;
+    void *out, *tmp;
+    int nrhs;
+    double *dot;
+    DslashShape shape;
+    size_t partials;  // doubles of block partials this call needs
+};
+size_t apply_m_dot_partials_max(const Geom &g, int nrhs);
+hisq_status check_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, int link_prec, int field_prec, double mass,
+                              const void *links, const void *in_even, void *out_even, void *tmp_odd, int nrhs,
+                              double *dot_out, ApplyMDot *a);
+hisq_status run_apply_m_dot(const ApplyMDot &a, double *partials, hipStream_t st);
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs);
 
 }  // namespace hisq

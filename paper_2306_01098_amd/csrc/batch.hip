@@ -124,13 +124,14 @@ __global__ void __launch_bounds__(TB) batch_xr_kernel(BatchArgs a) {
 // problem's block partials (deterministic, see wave_sum_slot), then its lane 0
 //  FIN_PQ:    st[j].pq = total (active problems)
 //  FIN_XR:    advances the problem's scalars and raises its flags; a problem
-//             that stops is stamped with the device clock and leaves the
-//             active count
+//             that stops leaves the active count (and is stamped with the
+//             device clock, restamped below when its true residual confirms it)
 //  FIN_RESID: st[j].rho_new = total (masked problems)
 //  FIN_BNORM: bnorm2[j] = total
 //  FIN_RESTART (no partials): the true-residual decision of each masked
 //             problem from st[j].rho_new = ||b - A x||^2: DONE, MAXIT,
-//             BREAKDOWN, or a residual replacement that restarts the
+//             BREAKDOWN (DONE stamps the device clock: the problem's
+//             latency ends there), or a residual replacement that restarts the
 //             recurrence (beta = ||r||^2 / rho, rho = rmax2 = ||r||^2; the
 //             problem rejoins the active count and is marked for p = r + beta p)
 __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, int mode, double *bnorm2) {
@@ -152,6 +153,8 @@ __global__ void __launch_bounds__(FIN_BLOCK) batch_finalize_kernel(BatchArgs a, 
                 s.flag = FLAG_BREAKDOWN;
             } else if (r2 <= s.target2) {
                 s.flag = FLAG_DONE;
+                // the solve ends here, when its FP64 true residual confirms it
+                s.spare = (double)wall_clock64();
             } else if (s.iters >= s.max_iter) {
                 s.flag = FLAG_MAXIT;
             } else {

@@ -535,6 +535,8 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
             info[j].reliable_updates = reliable[j];
             info[j].true_residual = bnorm2[j] > 0 ? std::sqrt(rtrue2[j] / bnorm2[j]) : std::sqrt(rtrue2[j]);
             info[j].seconds = elapsed;
+            info[j].shared_iterations = 0;
+            info[j].refine_iterations = 0;
         }
         if (latency_s)
             latency_s[j] = (t_stop[j] > 0.0 && rate_khz > 0) ? (t_stop[j] - clock0) / (rate_khz * 1e3) : 0.0;

@@ -558,6 +558,9 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
             info[j].reliable_updates = c.nrel;
             info[j].true_residual = bnorm2[j] > 0 ? std::sqrt(rtrue2[j] / bnorm2[j]) : std::sqrt(rtrue2[j]);
             info[j].seconds = now_s() - t0;
+            // a refinement after a multi-shift Krylov phase reports both parts
+            info[j].shared_iterations = prior_iters ? prior_iters[j] : 0;
+            info[j].refine_iterations = prior_iters ? c.iters : 0;
         }
         if (c.flag == FLAG_BREAKDOWN)
             breakdown = true;
@@ -576,9 +579,11 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
 // Multi-shift CG (Sec. 3.2: one Krylov space built on the smallest shift,
 // the other shifts advanced by Jegerlehner's zeta recurrences in FP64), then
 // per-shift refinement by (reliable-update) CG from x_k where the FP64 true
-// residual is still above tol_k.
+// residual is still above tol_k.  Without `refine` the call ends after the
+// shared Krylov phase and reports each x_k's FP64 true residual.
 static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, const void *b, void *const *x,
-                                  const double *tol, int max_iter, double delta, hisq_solve_info *info) {
+                                  const double *tol, int max_iter, double delta, hisq_solve_info *info,
+                                  bool refine) {
     const double t0 = now_s();
     const Geom &g = S.g;
     const Layout &L = S.L;
@@ -606,7 +611,7 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
     std::vector<int> krylov_iters(nshift, 0);
     if (!std::isfinite(bnorm2)) {
         for (int k = 0; k < nshift; ++k)
-            if (info) info[k] = hisq_solve_info{0, 0, NAN, now_s() - t0};
+            if (info) info[k] = hisq_solve_info{0, 0, NAN, now_s() - t0, 0, 0};
         return fail(HISQ_ERR_BREAKDOWN, "non-finite source");
     }
     if (bnorm2 > 0.0) {
@@ -706,6 +711,24 @@ static hisq_status run_multishift(Solver &S, int nshift, const double *shifts, c
             krylov_iters[others[j]] = sh[j].iters;
         if (c.flag == FLAG_BREAKDOWN)
             return fail(HISQ_ERR_BREAKDOWN, "multi-shift CG breakdown");
+    }
+    if (!refine) {
+        // the Krylov iterates as they are: each shift's FP64 true residual
+        hisq_status result = HISQ_OK;
+        for (int k = 0; k < nshift; ++k) {
+            double r2 = 0.0;
+            if (bnorm2 > 0.0 &&
+                (s = S.true_residual(shifts[k], b, x[k], S.at<void>(L.r), &r2)) != HISQ_OK)
+                return s;
+            const double rel = bnorm2 > 0.0 ? std::sqrt(r2 / bnorm2) : 0.0;
+            if (!(rel <= tol[k]) && result == HISQ_OK)
+                result = HISQ_ERR_NOT_CONVERGED;
+            if (info)
+                info[k] = hisq_solve_info{krylov_iters[k], 0, rel, now_s() - t0, krylov_iters[k], 0};
+        }
+        if (result != HISQ_OK)
+            fail(result, "a shift's Krylov iterate is above its tolerance (no refinement requested)");
+        return result;
     }
     // refinement: every shift to its own FP64 true residual, the shifts as the
     // columns of one multi-RHS CG (groups of up to HISQ_MAX_RHS), each column
@@ -905,10 +928,10 @@ hisq_status hisq_chiral_condensate(hisq_context *ctx, const hisq_lattice *lat, d
     return worst;
 }
 
-hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
-                               const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
-                               const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
-                               size_t ws_bytes, hisq_solve_info *info, void *stream) {
+static hisq_status multishift_entry(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                                    const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                                    const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                                    size_t ws_bytes, hisq_solve_info *info, void *stream, bool refine) {
     hisq_status s = check_solver_args(lat, mass, links_f64, links_inner, inner, ws);
     if (s == HISQ_OK && (nshift < 1 || nshift > MAX_SHIFTS))
         s = fail(HISQ_ERR_INVALID_ARG, "nshift = %d outside [1, %d]", nshift, MAX_SHIFTS);
@@ -941,7 +964,23 @@ hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, doubl
         HISQ_OK)
         return s;
     const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
-    return run_multishift(S, nshift, shifts, b, x, tol, max_iter, delta, info);
+    return run_multishift(S, nshift, shifts, b, x, tol, max_iter, delta, info, refine);
+}
+
+hisq_status hisq_multishift_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                               const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                               const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                               size_t ws_bytes, hisq_solve_info *info, void *stream) {
+    return multishift_entry(ctx, lat, mass, links_f64, links_inner, inner, nshift, shifts, b, x, tol, max_iter, ws,
+                            ws_bytes, info, stream, true);
+}
+
+hisq_status hisq_multishift_krylov(hisq_context *ctx, const hisq_lattice *lat, double mass, const void *links_f64,
+                                   const void *links_inner, hisq_prec inner, int32_t nshift, const double *shifts,
+                                   const void *b, void *const *x, const double *tol, int32_t max_iter, void *ws,
+                                   size_t ws_bytes, hisq_solve_info *info, void *stream) {
+    return multishift_entry(ctx, lat, mass, links_f64, links_inner, inner, nshift, shifts, b, x, tol, max_iter, ws,
+                            ws_bytes, info, stream, false);
 }
 
 }  // extern "C"

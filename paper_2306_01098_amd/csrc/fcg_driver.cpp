@@ -243,6 +243,8 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
         info->reliable_updates = reliable;
         info->true_residual = bnorm2 > 0 ? std::sqrt(rtrue2 / bnorm2) : std::sqrt(rtrue2);
         info->seconds = fnow() - t0;
+        info->shared_iterations = 0;
+        info->refine_iterations = 0;
     }
     if (broke)
         return fail(HISQ_ERR_BREAKDOWN, "flexible CG breakdown");

@@ -10,8 +10,9 @@
 namespace hisq {
 
 // Built-in shapes (measured on MI355X at 32^3x8 and 48^3x12): one thread per
-// site for a single right-hand side; for several, four lanes per site with
-// eight right-hand sides per thread.
+// site (four lanes per site on lattices too small to fill the chip); with
+// several right-hand sides one thread per site holding four of them (FP16N
+// links: two).
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     (void)fp;
     // measured on 32^3x8 at one right-hand side and 48^3x12 at 4 and 16:

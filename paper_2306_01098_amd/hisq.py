@@ -50,7 +50,8 @@ class hisq_problem(ctypes.Structure):
 
 class hisq_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
-                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("shared_iterations", ctypes.c_int32), ("refine_iterations", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +77,9 @@ _SIGS = {
                                    ctypes.c_int32, _vp]),
     "hisq_apply_m": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
                                     ctypes.c_int32, _vp]),
+    "hisq_apply_m_dot_workspace_bytes": (ctypes.c_size_t, [_LAT, ctypes.c_int32]),
+    "hisq_apply_m_dot": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                        ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_stream_read_sink_words": (ctypes.c_size_t, [ctypes.c_size_t]),
     "hisq_stream_read": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
@@ -97,6 +101,10 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double), _vp, ctypes.POINTER(_vp),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_size_t,
                                           ctypes.POINTER(hisq_solve_info), _vp]),
+    "hisq_multishift_krylov": (ctypes.c_int, [_vp, _LAT, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_double), _vp, ctypes.POINTER(_vp),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp,
+                                              ctypes.c_size_t, ctypes.POINTER(hisq_solve_info), _vp]),
     "hisq_cg_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(hisq_problem),
                                                         ctypes.c_int]),
     "hisq_cg_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(hisq_problem), ctypes.c_int,
@@ -285,6 +293,23 @@ def hisq_apply_m(lat, prec, mass: float, links, in_even, out_even, tmp_odd, nrhs
            "hisq_apply_m")
 
 
+def hisq_apply_m_dot_workspace_bytes(lat, nrhs: int = 1) -> int:
+    return int(load().hisq_apply_m_dot_workspace_bytes(ctypes.byref(lat), int(nrhs)))
+
+
+def hisq_apply_m_dot(lat, link_prec, field_prec, mass: float, links, in_even, out_even, tmp_odd, dot_out, ws,
+                     nrhs: int = 1, ctx=None, stream=None):
+    """out_even = M_e in_even and dot_out[r] = Re <in_r, out_r> (dot_out: a
+    float64 GPU tensor of nrhs entries)."""
+    fb = hisq_field_bytes(lat, field_prec, nrhs)
+    _check(load().hisq_apply_m_dot(_ctx(ctx), ctypes.byref(lat), _prec(link_prec), _prec(field_prec), float(mass),
+                                   _ptr(links, "links", hisq_links_bytes(lat, link_prec)),
+                                   _ptr(in_even, "in_even", fb), _ptr(out_even, "out_even", fb),
+                                   _ptr(tmp_odd, "tmp_odd", fb), int(nrhs), _ptr(dot_out, "dot_out", 8 * int(nrhs)),
+                                   _ptr(ws, "ws"), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                   _stream(stream)), "hisq_apply_m_dot")
+
+
 def hisq_stream_copy(src, dst, nbytes: int | None = None, ctx=None, stream=None):
     """dst = src (first nbytes bytes, default all of src) with the library's
     streaming copy kernel: the bandwidth reference of the benchmark."""
@@ -406,6 +431,28 @@ def hisq_multishift_cg(lat, mass: float, links_f64, links_inner, inner, shifts, 
                                    _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), info, _stream(stream))
     if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
         _check(st, "hisq_multishift_cg")
+    return st, [info[k].as_dict() for k in range(n)]
+
+
+def hisq_multishift_krylov(lat, mass: float, links_f64, links_inner, inner, shifts, b, xs, tol, max_iter: int,
+                           ws, ctx=None, stream=None, check: bool = True):
+    """The shared Krylov phase of the multi-shift solver alone (no refinement):
+    returns (status, [info dict per shift])."""
+    n = len(shifts)
+    sh = (ctypes.c_double * n)(*[float(v) for v in shifts])
+    tols = [float(tol)] * n if not hasattr(tol, "__len__") else [float(v) for v in tol]
+    tl = (ctypes.c_double * n)(*tols)
+    fb = hisq_field_bytes(lat, "fp64", 1)
+    xp = (_vp * n)(*[_ptr(xk, f"x[{k}]", fb) for k, xk in enumerate(xs)])
+    info = (hisq_solve_info * n)()
+    st = load().hisq_multishift_krylov(_ctx(ctx), ctypes.byref(lat), float(mass),
+                                       _ptr(links_f64, "links_f64", hisq_links_bytes(lat, "fp64")),
+                                       None if links_inner is None else _ptr(links_inner, "links_inner",
+                                                                             hisq_links_bytes(lat, inner)),
+                                       _prec(inner), n, sh, _ptr(b, "b", fb), xp, tl, int(max_iter),
+                                       _ptr(ws, "ws"), ctypes.c_size_t(ws.numel()), info, _stream(stream))
+    if check and st not in (OK, NOT_CONVERGED, BREAKDOWN):
+        _check(st, "hisq_multishift_krylov")
     return st, [info[k].as_dict() for k in range(n)]
 
 

@@ -124,6 +124,65 @@ def test_train_step_matches_oracle(setup):
         assert np.abs(a - b).max() <= 1e-6 + 1e-4 * 1e-2
 
 
+def test_adam_kernel_three_steps_carry_moments(setup):
+    """hisq_ptc_adam_step over three steps with changing gradients: weights,
+    both moments (re and im parts as separate parameters) and the FP32 copy
+    equal the oracle's FP64 Adam to rounding."""
+    h, w, lat, l32, X32, ws, weights, master, w32 = setup
+    rng = np.random.default_rng(11)
+    wts = [x.astype(np.complex128) for x in weights]
+    dev_w, dev_w32 = h.weights_to_device(wts)
+    dev_m, dev_v = torch.zeros_like(dev_w), torch.zeros_like(dev_w)
+    m_ref = [np.zeros_like(x) for x in wts]
+    v_ref = [np.zeros_like(x) for x in wts]
+    for step in (1, 2, 3):
+        g = [rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape) for x in wts]
+        g_dev, _ = h.weights_to_device(g)
+        h.hisq_ptc_adam_step(dev_w, dev_w32, g_dev, dev_m, dev_v, step, lr=1e-2, beta1=0.8, beta2=0.95)
+        wts, m_ref, v_ref = ptc.adam_step(wts, g, m_ref, v_ref, step, lr=1e-2, beta1=0.8, beta2=0.95)
+        torch.cuda.synchronize()
+        for got, ref in ((dev_w, wts), (dev_m, m_ref), (dev_v, v_ref)):
+            for a, b in zip(h.weights_from_device(got), ref):
+                np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15)
+        np.testing.assert_array_equal(dev_w32.cpu().numpy(), dev_w.to(torch.float32).cpu().numpy())
+
+
+def test_train_step_three_steps_matches_oracle(setup):
+    """Three training steps on one batch.  Before each step the weights and
+    Adam moments are read from the GPU; the oracle computes the loss and the
+    FP64 gradient at those weights (FP32-rounded, as the kernels use them) and
+    one Adam step from those moments.  The GPU's loss, new weights and new
+    moments must agree: the carried moments of steps 2 and 3 are pinned, not
+    only the sign-like first step."""
+    h, w, lat, l32, X32, ws, weights, master, w32 = setup
+    srcs = f32(w["src"][:2])
+    sols = gen.gaussian_half_field(gen.rng_for(80, 40), DIMS, 2)
+    master, w32 = h.weights_to_device(weights)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    s32 = h.pack_field_from_host(lat, "fp32", srcs)
+    s64 = h.pack_field_from_host(lat, "fp64", sols)
+    mass, lr = 0.2, 1e-2
+    lat_q = O.quantized_lattice(O.lattice_from(w), "fp32")
+    A = lambda v_: lat_q.M_e(mass, v_)  # noqa: E731
+    for step in (1, 2, 3):
+        w_prev = h.weights_from_device(master)
+        m_prev = h.weights_from_device(m)
+        v_prev = h.weights_from_device(v)
+        loss = h.hisq_ptc_train_step(lat, mass, l32, master, w32, m, v, step, 2, s32, s64, ws, lr=lr)
+        L_ref, g_ref = ptc.loss_and_grad(DIMS, -1, X32, [f32(x) for x in w_prev], srcs, O.quantize_fp32(sols), A)
+        assert abs(loss - L_ref) <= 1e-5 * L_ref, (step, loss, L_ref)
+        w_ref, m_ref, v_ref = ptc.adam_step(w_prev, g_ref, m_prev, v_prev, step, lr=lr)
+        for a, b in zip(h.weights_from_device(m), m_ref):
+            assert rel(a, b) <= 1e-5, step
+        for a, b in zip(h.weights_from_device(v), v_ref):
+            assert rel(a, b) <= 1e-5, step
+        for a, b, p in zip(h.weights_from_device(master), w_ref, w_prev):
+            # each update is ~lr per part; FP32 gradients move it by <= 1e-4 lr
+            assert np.abs(a - b).max() <= 1e-6 + 1e-4 * lr, step
+            assert np.abs(b - p).max() >= 0.5 * lr, step
+
+
 def test_fcg_identity_preconditioner(gpu_lib):
     """With N = identity, flexible CG is CG: same tolerance, similar iterations."""
     h = gpu_lib

@@ -107,6 +107,43 @@ def test_adam_first_step_is_sign_times_lr():
     np.testing.assert_allclose(nw[0], w[0] - 1e-3 * (1 - 1j), atol=1e-9)
 
 
+def test_adam_three_steps_hand_computed():
+    """Three Adam steps with beta1 = beta2 = 1/2 and eps = 0, where every
+    moment is a short binary fraction worked out by hand.  The real part sees
+    gradients +1, -1, -1 and the imaginary part 2, 2, -2, so a moment that is
+    not carried from step to step, a bias correction with the wrong power, or
+    real and imaginary moments swapped all change the numbers.
+      re: m = 1/2, -1/4, -5/8;  v = 1/2, 3/4, 7/8;  m^ = 1, -1/3, -5/7;  v^ = 1
+          w_re = 1 - lr (1 - 1/3 - 5/7) = 1 + lr/21
+      im: m = 1, 3/2, -1/4;     v = 2, 3, 7/2;      m^ = 2, 2, -2/7;    v^ = 4
+          w_im = 1 - lr (1 + 1 - 1/7) = 1 - 13 lr/7"""
+    lr = 0.1
+    w = [np.array([[[1.0 + 1.0j]]])]
+    m = [np.zeros_like(w[0])]
+    v = [np.zeros_like(w[0])]
+    for step, g in enumerate((1.0 + 2.0j, -1.0 + 2.0j, -1.0 - 2.0j), start=1):
+        w, m, v = ptc.adam_step(w, [np.array([[[g]]])], m, v, step, lr=lr, beta1=0.5, beta2=0.5, eps=0.0)
+    assert m[0].ravel()[0] == -0.625 - 0.25j
+    assert v[0].ravel()[0] == 0.875 + 3.5j
+    np.testing.assert_allclose(w[0].ravel()[0].real, 1.0 + lr / 21, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w[0].ravel()[0].imag, 1.0 - 13 * lr / 7, rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient the bias-corrected moments are g and g^2 at
+    every step, so each step moves each part by lr sign(g) (eps -> 0), with
+    the standard decays."""
+    w = [np.array([[[0.5 - 0.25j, 2.0 + 0.0j]]])]
+    g = [np.array([[[0.3 - 7.0j, -1e-3 + 4.0j]]])]
+    m = [np.zeros_like(w[0])]
+    v = [np.zeros_like(w[0])]
+    lr = 1e-2
+    for step in range(1, 6):
+        w, m, v = ptc.adam_step(w, g, m, v, step, lr=lr, eps=0.0)
+    np.testing.assert_allclose(w[0], np.array([[[0.5 - 0.05 - 0.25j + 0.05j, 2.0 + 0.05 - 0.05j]]]),
+                               rtol=0, atol=1e-12)
+
+
 def test_fcg_identity_preconditioner_is_cg(field):
     lat = O.lattice_from(field)
     b = field["src"][0]
