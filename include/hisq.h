@@ -228,6 +228,30 @@ hisq_status hisq_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, hisq_pr
                              void *out_even, void *tmp_odd, int32_t nrhs, double *dot_out, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* Bytes of the device scratch array behind hisq_apply_m_dot_noalloc (per
+ * device that runs it, held until the process ends). */
+#define HISQ_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* hisq_apply_m_dot without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the block partials live in a file-scope
+ * device array of HISQ_NOALLOC_SCRATCH_BYTES bytes, one per device, whose
+ * address the library looks up once per device (at hisq_context_create, or
+ * at the first call on a device).  The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine.  Same arguments, operators, launch
+ * shape and results as hisq_apply_m_dot (bitwise: the same kernels).
+ * Limit: the call needs nrhs * (block count of the launch shape) doubles of
+ * partials; every call with hisq_apply_m_dot_workspace_bytes(lat, nrhs) <=
+ * HISQ_NOALLOC_SCRATCH_BYTES fits (e.g. 32^4 with 16 rhs, or 64^4 with 1
+ * rhs); a call whose launch shape needs more returns HISQ_ERR_WORKSPACE
+ * before any launch.  Every call
+ * on one device shares that device's array: each call writes every partial
+ * it reads, but calls that overlap in time on one device (concurrent streams
+ * or threads) race and give wrong dot products.  Asynchronous. */
+hisq_status hisq_apply_m_dot_noalloc(hisq_context *ctx, const hisq_lattice *lat, hisq_prec link_prec,
+                                     hisq_prec field_prec, double mass, const void *links, const void *in_even,
+                                     void *out_even, void *tmp_odd, int32_t nrhs, double *dot_out, void *stream);
+
 /* Workspace bytes for hisq_cg (nshift = 0) or hisq_multishift_cg (nrhs = 1,
  * nshift shifts) with inner precision `inner`.  0 on invalid arguments. */
 size_t hisq_cg_workspace_bytes(const hisq_lattice *lat, hisq_prec inner, int32_t nrhs, int32_t nshift);

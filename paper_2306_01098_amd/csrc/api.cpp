@@ -166,6 +166,11 @@ hisq_status hisq_context_create(hisq_context **ctx, int32_t device) {
     if (!c)
         return fail(HISQ_ERR_DEVICE, "out of host memory");
     c->device = device;
+    const hisq_status s = noalloc_scratch_setup(device);
+    if (s != HISQ_OK) {
+        delete c;
+        return s;
+    }
     *ctx = c;
     return HISQ_OK;
 }

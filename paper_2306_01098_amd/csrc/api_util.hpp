@@ -72,5 +72,8 @@ hisq_status check_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, int li
                               double *dot_out, ApplyMDot *a);
 hisq_status run_apply_m_dot(const ApplyMDot &a, double *partials, hipStream_t st);
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs);
+// Looks up the device address of the allocation-free entry point's scratch
+// array on `device` (once per device).
+hisq_status noalloc_scratch_setup(int device);
 
 }  // namespace hisq

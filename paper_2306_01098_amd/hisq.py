@@ -20,6 +20,8 @@ HISQ_FP64, HISQ_FP32, HISQ_FP16N, HISQ_FP64R12, HISQ_FP32R12 = 0, 1, 2, 3, 4
 PRECS = {"fp64": HISQ_FP64, "fp32": HISQ_FP32, "fp16n": HISQ_FP16N, "fp64r12": HISQ_FP64R12,
          "fp32r12": HISQ_FP32R12}
 HISQ_MAX_RHS = 16
+# bytes of the device scratch array behind hisq_apply_m_dot_noalloc
+HISQ_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 OK, INVALID_ARG, NOT_CONVERGED, BREAKDOWN, DEVICE, WORKSPACE, UNSUPPORTED = range(7)
 
@@ -80,6 +82,8 @@ _SIGS = {
     "hisq_apply_m_dot_workspace_bytes": (ctypes.c_size_t, [_LAT, ctypes.c_int32]),
     "hisq_apply_m_dot": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp,
                                         ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
+    "hisq_apply_m_dot_noalloc": (ctypes.c_int, [_vp, _LAT, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp,
+                                                _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "hisq_stream_copy": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "hisq_stream_read_sink_words": (ctypes.c_size_t, [ctypes.c_size_t]),
     "hisq_stream_read": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
@@ -308,6 +312,19 @@ def hisq_apply_m_dot(lat, link_prec, field_prec, mass: float, links, in_even, ou
                                    _ptr(tmp_odd, "tmp_odd", fb), int(nrhs), _ptr(dot_out, "dot_out", 8 * int(nrhs)),
                                    _ptr(ws, "ws"), ctypes.c_size_t(ws.numel() * ws.element_size()),
                                    _stream(stream)), "hisq_apply_m_dot")
+
+
+def hisq_apply_m_dot_noalloc(lat, link_prec, field_prec, mass: float, links, in_even, out_even, tmp_odd, dot_out,
+                             nrhs: int = 1, ctx=None, stream=None):
+    """hisq_apply_m_dot with its block partials in the library's static
+    device scratch (no workspace argument; allocates nothing)."""
+    fb = hisq_field_bytes(lat, field_prec, nrhs)
+    _check(load().hisq_apply_m_dot_noalloc(_ctx(ctx), ctypes.byref(lat), _prec(link_prec), _prec(field_prec),
+                                           float(mass), _ptr(links, "links", hisq_links_bytes(lat, link_prec)),
+                                           _ptr(in_even, "in_even", fb), _ptr(out_even, "out_even", fb),
+                                           _ptr(tmp_odd, "tmp_odd", fb), int(nrhs),
+                                           _ptr(dot_out, "dot_out", 8 * int(nrhs)), _stream(stream)),
+           "hisq_apply_m_dot_noalloc")
 
 
 def hisq_stream_copy(src, dst, nbytes: int | None = None, ctx=None, stream=None):
