@@ -282,6 +282,372 @@ __global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-reduction CG (after Chronopoulos and Gear).  With w = A r formed by
+// the D_eo kernel together with the block partials of Re <r, w>, one scalar
+// step per iteration needs all inner products at once:
+//   gamma = <r, r>,  delta = Re <r, w>,  beta = gamma / gamma_old,
+//   <p_new, A p_new> = <r + beta p, w + beta s>
+//                    = delta + beta (2 Re <r, s> + beta <p, s>),
+//   alpha = gamma / <p_new, A p_new>,
+//   p = r + beta p,  s = w + beta s (= A p),  x += alpha p,  r -= alpha s,
+// where <r, r>, Re <r, s> and <p, s> of the new vectors are summed by the
+// same update kernel.  (Chronopoulos and Gear write <p, A p> as
+// delta - beta gamma / alpha_old, which assumes r _|_ r_old and s = A p
+// exactly; with FP16 links that form lost all accuracy after a few hundred
+// iterations, CPU emulation: <p, A p> = -0.41 where the direct value is 7.9.)
+// In exact arithmetic these are the iterates of the Hestenes-Stiefel CG; the
+// launches per iteration drop from five to four (D_oe, D_eo, scalars, update).
+// ---------------------------------------------------------------------------
+
+// The scalar step of one column from the sums tot = {<r, r>, Re <r, w>,
+// Re <r, s>, <p, s>} of its partials.  decide: the check block has just formed
+// the column's FP64 true residual (it waited for it), so ||b - A x||^2 is in
+// tot[0] (and Re <r, s> of the replaced r in tot[2]) and the column is decided
+// first: done, the iteration limit, or a residual replacement (the reliable
+// update of Clark et al.), after which the same step continues from the
+// replaced r with beta = ||r||^2 / rho, as the two-reduction solver does.
+// Sets s.go (0: no update; 1: update; 2: update with fresh directions).
+// *wait: 1 when the column starts waiting for its true residual, 0 when it
+// stopped waiting, unchanged otherwise.
+__device__ __forceinline__ void cgcg_decide(CgScalars &s, const double (&tot)[4], bool decide, int *wait) {
+    s.go = 0;
+    const double gamma = tot[0], delta = tot[1];
+    if (decide) {
+        *wait = 0;
+        s.rtrue2 = gamma;
+        if (!(gamma >= 0.0 && gamma < 1.0e308)) {
+            s.flag = FLAG_BREAKDOWN;
+        } else if (gamma <= s.target2) {
+            s.flag = FLAG_DONE;
+        } else if (s.iters >= s.max_iter) {
+            s.flag = FLAG_MAXIT;
+        } else {
+            s.nrel += 1;
+            s.rmax2 = gamma;
+            s.flag = FLAG_RUN;
+            s.active = 1;
+        }
+    }
+    if (!s.active)
+        return;
+    if (!(gamma >= 0.0 && gamma < 1.0e308) || !(delta == delta)) {
+        s.flag = FLAG_BREAKDOWN;
+        s.active = 0;
+    } else if (gamma <= s.target2) {
+        s.flag = FLAG_CONV;
+        s.active = 0;
+        *wait = 1;
+    } else if (s.delta2 > 0.0 && gamma < s.delta2 * s.rmax2) {
+        s.flag = FLAG_RELIABLE;
+        s.active = 0;
+        *wait = 1;
+    } else if (s.iters >= s.max_iter) {
+        s.flag = FLAG_MAXIT;
+        s.active = 0;
+    } else {
+        const bool fresh = s.restart != 0;
+        const double beta = fresh ? 0.0 : gamma / s.rho;
+        const double pap = fresh ? delta : delta + beta * (2.0 * tot[2] + beta * tot[3]);
+        if (!finite_pos(pap)) {
+            s.flag = FLAG_BREAKDOWN;
+            s.active = 0;
+        } else {
+            s.alpha = gamma / pap;
+            s.beta = beta;
+            s.pq = pap;
+            s.rho = gamma;
+            s.rho_new = gamma;
+            s.rmax2 = fmax(s.rmax2, gamma);
+            s.iters += 1;
+            s.restart = 0;
+            s.go = fresh ? 2 : 1;
+        }
+    }
+}
+
+// The four partial slots of column j, summed by the four wavefronts of a block
+// (one each, fixed order: deterministic) into tot; `off` selects the set of
+// <r, r>, Re <r, s> and <p, s> partials.  NT: non-temporal loads (one
+// reading block per column).
+template <bool NT>
+__device__ __forceinline__ void cgcg_sums(const CgVecParams &prm, int j, size_t off, double (&tot)[4],
+                                          double *lds) {
+    const int wave = threadIdx.x >> 6;
+    if (wave < 4) {
+        const size_t o = off + (size_t)j * prm.rr_nblk;
+        const double *slot = wave == 0   ? prm.rr_part + o
+                             : wave == 1 ? prm.rw_part + (size_t)j * prm.rw_nblk
+                             : wave == 2 ? prm.rs_part + o
+                                         : prm.ps_part + o;
+        const double v = wave_sum_slot<NT>(slot, wave == 1 ? prm.rw_nblk : prm.rr_nblk);
+        if ((threadIdx.x & 63) == 0)
+            lds[wave] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        tot[k] = lds[k];
+}
+
+// One block of four wavefronts per right-hand side j = blockIdx.x: the sums of
+// the column's partials and its scalar step.  after_check != 0: the check
+// block ran just before this iteration, so a waiting column (tr_skip == 0) is
+// decided here.
+__global__ void __launch_bounds__(256) cgcg_finalize_kernel(CgVecParams prm, int after_check) {
+    if (*prm.skip)
+        return;
+    const int j = blockIdx.x;
+    __shared__ double lds[4];
+    double tot[4];
+    cgcg_sums<true>(prm, j, 0, tot, lds);
+    if (threadIdx.x != 0)
+        return;
+    CgScalars s = prm.st[j];
+    int wait = -1;
+    cgcg_decide(s, tot, after_check && prm.tr_skip[j] == 0, &wait);
+    if (wait >= 0)
+        prm.tr_skip[j] = wait ? 0 : 1;
+    prm.st[j] = s;
+}
+
+// The vector step of the column blockIdx.y that the finalize kernel stepped
+// (go = 1; go = 2: fresh directions p = r, s = w):
+//   p = r + beta p, s = w + beta s, x += alpha p (FP64 x), r -= alpha s,
+// with the block partials of <r, r>, Re <r, s> and Re <p, s> of the new
+// vectors (their stored values).
+// Block (0, 0) also sets the launch flags of the following kernels: skip while
+// no column is active (a column waiting for its true residual idles until the
+// check block, whose residual kernel clears skip again so that the next
+// iteration decides it), nopend while none is waiting.  (No other block of
+// this launch reads them.)
+template <int FP>
+__global__ void __launch_bounds__(BLK) cgcg_update_kernel(CgVecParams prm) {
+    using T = typename Sloppy<FP>::T;
+    const int j = blockIdx.y;
+    if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) {
+        int run = 0, pend = 0;
+        for (int k = 0; k < prm.nrhs; ++k) {
+            run |= prm.st[k].active;
+            pend |= prm.tr_skip[k] == 0 ? 1 : 0;
+        }
+        *prm.skip = run ? 0 : 1;
+        if (prm.nopend)
+            *prm.nopend = pend ? 0 : 1;
+    }
+    const CgScalars st = prm.st[j];
+    if (!st.go)
+        return;
+    __shared__ double lds[12];
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    double part[3] = {0.0, 0.0, 0.0};
+    if (i < prm.vh) {
+        cplx<T> r[3], w[3], p[3], sv[3];
+        cplx<double> x[3];
+        FieldIO<FP>::template load<T>(prm.r, prm.vh, j, i, r);
+        FieldIO<FP>::template load<T>(prm.w, prm.vh, j, i, w);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 0, i, x);
+        const bool fresh = st.go == 2;
+        if (!fresh) {
+            FieldIO<FP>::template load<T>(prm.p, prm.vh, j, i, p);
+            FieldIO<FP>::template load<T>(prm.s, prm.vh, j, i, sv);
+        }
+        const T b = (T)st.beta, a = (T)st.alpha;
+        const double ad = st.alpha;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (fresh) {
+                p[c] = r[c];
+                sv[c] = w[c];
+            } else {
+                p[c].re = fma(b, p[c].re, r[c].re);
+                p[c].im = fma(b, p[c].im, r[c].im);
+                sv[c].re = fma(b, sv[c].re, w[c].re);
+                sv[c].im = fma(b, sv[c].im, w[c].im);
+            }
+            x[c].re = fma(ad, (double)p[c].re, x[c].re);
+            x[c].im = fma(ad, (double)p[c].im, x[c].im);
+            r[c].re = fma(-a, sv[c].re, r[c].re);
+            r[c].im = fma(-a, sv[c].im, r[c].im);
+            const double rre = r[c].re, rim = r[c].im, sre = sv[c].re, sim = sv[c].im;
+            part[0] = fma(rre, rre, part[0]);
+            part[0] = fma(rim, rim, part[0]);
+            part[1] = fma(rre, sre, part[1]);
+            part[1] = fma(rim, sim, part[1]);
+            part[2] = fma((double)p[c].re, sre, part[2]);
+            part[2] = fma((double)p[c].im, sim, part[2]);
+        }
+        FieldIO<FP>::template store<T>(prm.p, prm.vh, j, i, p);
+        FieldIO<FP>::template store<T>(prm.s, prm.vh, j, i, sv);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 0, i, x);
+        FieldIO<FP>::template store<T>(prm.r, prm.vh, j, i, r);
+    }
+    block_sum<3>(part, lds);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t)j * gridDim.x + blockIdx.x;
+        prm.rr_part[o] = part[0];
+        prm.rs_part[o] = part[1];
+        prm.ps_part[o] = part[2];
+    }
+}
+
+// The scalar step and the vector step in one launch, for lattices with few
+// partials per column: every block of column j = blockIdx.y sums the
+// column's partials (the same values in the same order, so every block takes
+// the same decision) and advances its sites.  The state and the <r, r>,
+// Re <r, s>, <p, s> partials are double-buffered: state read from st_in and
+// written (by block (0, j) alone) to st_out, partials read from set in_buf
+// and written to the other, so no block reads what another block of the
+// launch writes.  A column waits for its true
+// residual while it is inactive with FLAG_CONV or FLAG_RELIABLE; after_check:
+// the check block has just formed it.  Block (0, j) also sets the column's
+// launch gates: col_off[j] (the iteration's Dslash launches skip the column)
+// and tr_skip[j] (the check block skips it).
+template <int FP>
+__global__ void __launch_bounds__(BLK) cgcg_fused_kernel(CgVecParams prm, const CgScalars *st_in, CgScalars *st_out,
+                                                         int *col_off, int after_check, int in_buf) {
+    using T = typename Sloppy<FP>::T;
+    const int j = blockIdx.y;
+    CgScalars s = st_in[j];
+    const bool waiting = !s.active && (s.flag == FLAG_CONV || s.flag == FLAG_RELIABLE);
+    const bool decide = after_check && waiting;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!s.active && !decide) {
+        if (lead)
+            st_out[j] = s;
+        return;
+    }
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    const bool site = i < prm.vh;
+    // the vectors are loaded before the partial sums so the two overlap
+    cplx<T> r[3], w[3], p[3], sv[3];
+    cplx<double> x[3];
+    if (site) {
+        FieldIO<FP>::template load<T>(prm.r, prm.vh, j, i, r);
+        FieldIO<FP>::template load<T>(prm.w, prm.vh, j, i, w);
+        FieldIO<FP>::template load<T>(prm.p, prm.vh, j, i, p);
+        FieldIO<FP>::template load<T>(prm.s, prm.vh, j, i, sv);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 0, i, x);
+    }
+    __shared__ double lds_tot[4];  // apart from lds: a wave may reach block_sum while others still read tot
+    __shared__ double lds[12];
+    double tot[4];
+    cgcg_sums<false>(prm, j, in_buf ? prm.part_buf : 0, tot, lds_tot);
+    int wait = -1;
+    cgcg_decide(s, tot, decide, &wait);
+    if (lead) {
+        st_out[j] = s;
+        if (wait >= 0)
+            prm.tr_skip[j] = wait ? 0 : 1;
+        col_off[j] = s.active ? 0 : 1;
+    }
+    if (!s.go)
+        return;
+    double part[3] = {0.0, 0.0, 0.0};
+    if (site) {
+        const bool fresh = s.go == 2;
+        const T b = (T)s.beta, a = (T)s.alpha;
+        const double ad = s.alpha;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (fresh) {
+                p[c] = r[c];
+                sv[c] = w[c];
+            } else {
+                p[c].re = fma(b, p[c].re, r[c].re);
+                p[c].im = fma(b, p[c].im, r[c].im);
+                sv[c].re = fma(b, sv[c].re, w[c].re);
+                sv[c].im = fma(b, sv[c].im, w[c].im);
+            }
+            x[c].re = fma(ad, (double)p[c].re, x[c].re);
+            x[c].im = fma(ad, (double)p[c].im, x[c].im);
+            r[c].re = fma(-a, sv[c].re, r[c].re);
+            r[c].im = fma(-a, sv[c].im, r[c].im);
+            const double rre = r[c].re, rim = r[c].im, sre = sv[c].re, sim = sv[c].im;
+            part[0] = fma(rre, rre, part[0]);
+            part[0] = fma(rim, rim, part[0]);
+            part[1] = fma(rre, sre, part[1]);
+            part[1] = fma(rim, sim, part[1]);
+            part[2] = fma((double)p[c].re, sre, part[2]);
+            part[2] = fma((double)p[c].im, sim, part[2]);
+        }
+        FieldIO<FP>::template store<T>(prm.p, prm.vh, j, i, p);
+        FieldIO<FP>::template store<T>(prm.s, prm.vh, j, i, sv);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 0, i, x);
+        FieldIO<FP>::template store<T>(prm.r, prm.vh, j, i, r);
+    }
+    block_sum<3>(part, lds);
+    if (threadIdx.x == 0) {
+        const size_t o = (in_buf ? 0 : prm.part_buf) + (size_t)j * gridDim.x + blockIdx.x;
+        prm.rr_part[o] = part[0];
+        prm.rs_part[o] = part[1];
+        prm.ps_part[o] = part[2];
+    }
+}
+
+// r_j = b_j - ax_j for the columns j = blockIdx.y whose tr_skip[j] is 0 (all
+// columns when tr_skip is NULL): FP64 inputs, r stored in the sloppy
+// precision, block partials of ||b_j - ax_j||^2 (FP64 values) in
+// partials[j * gridDim.x + block] and, when s and p are not NULL, of
+// Re <r_j, s_j> (the stored r) and Re <p_j, s_j> in spart and ppart (same
+// layout).  b, ax, r, s, p: packed fields of gridDim.y columns.  A launch that
+// forms residuals reopens the iteration launches after it: *skip = 0
+// (nullable) and col_off[j] = 0 (nullable) for each column it forms.
+template <int FP>
+__global__ void __launch_bounds__(BLK) residual_cols_kernel(int vh, const void *b, const void *ax, void *r,
+                                                            double *partials, const int *tr_skip, const void *s,
+                                                            const void *p, double *spart, double *ppart, int *skip,
+                                                            int *col_off) {
+    using T = typename Sloppy<FP>::T;
+    const int j = blockIdx.y;
+    if (tr_skip && tr_skip[j] != 0)
+        return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (skip)
+            *skip = 0;
+        if (col_off)
+            col_off[j] = 0;
+    }
+    __shared__ double lds[12];
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    double part[3] = {0.0, 0.0, 0.0};
+    const bool sp = s && p;
+    if (i < vh) {
+        cplx<double> bv[3], av[3];
+        FieldIO<HISQ_FP64>::template load<double>(b, vh, j, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(ax, vh, j, i, av);
+        cplx<T> rv[3], sv[3], pv[3];
+        if (sp) {
+            FieldIO<FP>::template load<T>(s, vh, j, i, sv);
+            FieldIO<FP>::template load<T>(p, vh, j, i, pv);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double re = bv[c].re - av[c].re, im = bv[c].im - av[c].im;
+            part[0] = fma(re, re, part[0]);
+            part[0] = fma(im, im, part[0]);
+            rv[c].re = (T)re;
+            rv[c].im = (T)im;
+            if (sp) {
+                part[1] = fma((double)rv[c].re, (double)sv[c].re, part[1]);
+                part[1] = fma((double)rv[c].im, (double)sv[c].im, part[1]);
+                part[2] = fma((double)pv[c].re, (double)sv[c].re, part[2]);
+                part[2] = fma((double)pv[c].im, (double)sv[c].im, part[2]);
+            }
+        }
+        FieldIO<FP>::template store<T>(r, vh, j, i, rv);
+    }
+    block_sum<3>(part, lds);
+    if (threadIdx.x == 0) {
+        const size_t o = (size_t)j * gridDim.x + blockIdx.x;
+        partials[o] = part[0];
+        if (sp) {
+            spart[o] = part[1];
+            ppart[o] = part[2];
+        }
+    }
+}
+
 // r = b - ax (FP64 inputs; r stored in the sloppy precision) and
 // *out2 = ||b - ax||^2 in FP64 (from the FP64 values).
 template <int FP>
@@ -402,6 +768,42 @@ hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStre
 
 hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStream_t st) {
     cg_restart_kernel<<<1, 1024, 0, st>>>(p, trpart, blas_blocks(p.vh));
+    return hipGetLastError();
+}
+
+hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipStream_t st) {
+    cgcg_finalize_kernel<<<dim3((unsigned)p.nrhs), 256, 0, st>>>(p, after_check);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const dim3 g = grid_for(p.vh, p.nrhs);
+    if (fp == HISQ_FP64)
+        cgcg_update_kernel<HISQ_FP64><<<g, BLK, 0, st>>>(p);
+    else
+        cgcg_update_kernel<HISQ_FP32><<<g, BLK, 0, st>>>(p);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
+                                const int *tr_skip, const void *s, const void *p, double *spart, double *ppart,
+                                int *skip, int *col_off, hipStream_t st) {
+    const dim3 g = grid_for(vh, ncol);
+    if (fp == HISQ_FP64)
+        residual_cols_kernel<HISQ_FP64>
+            <<<g, BLK, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+    else
+        residual_cols_kernel<HISQ_FP32>
+            <<<g, BLK, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgcg_fused(const CgVecParams &p, int fp, const CgScalars *st_in, CgScalars *st_out, int *col_off,
+                             int after_check, int in_buf, hipStream_t st) {
+    const dim3 g = grid_for(p.vh, p.nrhs);
+    if (fp == HISQ_FP64)
+        cgcg_fused_kernel<HISQ_FP64><<<g, BLK, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
+    else
+        cgcg_fused_kernel<HISQ_FP32><<<g, BLK, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
     return hipGetLastError();
 }
 

@@ -3,13 +3,19 @@
 // mixed-precision CG, and multi-shift CG with per-shift refinement, all for
 // the even-site operator M_e = m^2 - D_eo D_oe (+ shift).
 //
-// One CG iteration is five kernels on the device: D_oe p -> t;
-// q = (m^2 + sigma) p - D_eo t with the block partials of Re<p, q>;
-// x += alpha p, r -= alpha q with the <r, r> partials (each block sums the
-// Re<p, q> partials itself); the one-block scalar update; p = r + beta p.  Chunks of iterations are
-// captured once into a HIP graph and replayed; kernels of converged
-// right-hand sides do nothing, and the host looks at the device state only
-// between chunks (to run a reliable update or to stop).
+// CG and reliable-update CG (hisq_cg, the refinement of the multi-shift
+// solver) run the single-reduction recurrence of Chronopoulos and Gear, four
+// kernels per iteration: D_oe r -> t; w = (m^2 + sigma) r - D_eo t with the
+// block partials of Re<r, w>; per column, the sums of those and of the <r, r>
+// partials and the scalar step; p = r + beta p, s = w + beta s, x += alpha p,
+// r -= alpha s with the <r, r> partials of the new r.  The shared Krylov
+// phase of multi-shift CG keeps the two-reduction (Hestenes-Stiefel)
+// recurrence, which Jegerlehner's shifted recurrences are written for: five
+// kernels, D_oe p; q = A p with the Re<p, q> partials; x, r with the <r, r>
+// partials; the one-block scalar update; p = r + beta p.  Chunks of
+// iterations are captured once into a HIP graph and replayed; kernels of
+// converged right-hand sides do nothing, and the host looks at the device
+// state only between chunks.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -30,7 +36,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     int fs;  // sloppy field precision (FP64 or FP32)
     int nblk_max;
-    size_t state, shifts, ms, flags, scal, partials, dpart, r, p, q, t, ps, ax, t64, t64m, axm, total;
+    size_t state, state2, shifts, ms, flags, scal, partials, dpart, rr, rspart, pspart, r, p, q, w, t, ps, ax, t64,
+        t64m, axm, total;
+    size_t part_set;  // doubles of one set of <r, r> (or Re <r, s>, <p, s>) partials
 };
 
 Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
@@ -44,6 +52,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
         return o;
     };
     L.state = take(sizeof(CgScalars) * HISQ_MAX_RHS);
+    L.state2 = take(sizeof(CgScalars) * HISQ_MAX_RHS);  // second buffer of the fused single-reduction step
     L.shifts = take(sizeof(ShiftScalars) * MAX_SHIFTS);
     L.ms = take(sizeof(MsGlobal));
     L.flags = take(64 * sizeof(unsigned));
@@ -51,11 +60,18 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     // the multi-shift refinement solves up to HISQ_MAX_RHS shifts as columns
     const int ncol = std::max(nrhs, std::min(std::max(nshift, 0), (int)HISQ_MAX_RHS));
     L.partials = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);
-    L.dpart = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);  // <p, A p> partials
+    // <p, A p> partials (two-reduction CG) or Re <r, A r> partials (single-reduction CG)
+    L.dpart = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);
+    // single-reduction CG: two sets each of the <r, r>, Re <r, s> and <p, s> partials
+    L.part_set = (size_t)std::max(ncol, 1) * blas_blocks(g.vh);
+    L.rr = take(sizeof(double) * 2 * L.part_set);
+    L.rspart = take(sizeof(double) * 2 * L.part_set);
+    L.pspart = take(sizeof(double) * 2 * L.part_set);
     const size_t fb = field_bytes(g, L.fs, 1);
     L.r = take(fb * ncol);
     L.p = take(fb * ncol);
-    L.q = take(fb * ncol);
+    L.q = take(fb * ncol);  // A p (s of the single-reduction CG)
+    L.w = take(fb * ncol);  // A r (single-reduction CG)
     L.t = take(fb * ncol);
     L.ps = take(fb * std::max(nshift, 0));
     const size_t f64 = field_bytes(g, HISQ_FP64, 1);
@@ -71,7 +87,9 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
 }
 
 // flags[] slots
-enum { F_SKIP = 0, F_NOPEND = 2, F_TR0 = 16 };  // F_NOPEND: no true residual pending; F_TR0 + j: tr_skip of column j
+// F_NOPEND: no true residual pending; F_TR0 + j: tr_skip of column j;
+// F_OFF0 + j: column j inactive (the fused single-reduction step's launch gate)
+enum { F_SKIP = 0, F_NOPEND = 2, F_TR0 = 16, F_OFF0 = 32 };
 // scal[] slots
 enum { S_TMP = 0 };
 
@@ -149,8 +167,51 @@ struct Solver {
         return s == HISQ_OK ? read_double(scal() + S_TMP, out2) : s;
     }
 
-    // The five kernels of one iteration for nrhs right-hand sides, column j
-    // solving (M_e + sigma[j]) x = b.
+    // One single-reduction CG iteration for nrhs columns (column j solving
+    // (M_e + sigma[j]) x = b): D_oe r; w = A r with the Re <r, w> partials;
+    // the per-column scalar step and the vector update, as two launches, or
+    // as one (fused: every block sums its column's partials; the state
+    // alternates between the two buffers, iteration k reading buffer k % 2,
+    // and the Dslash launches are gated per column).
+    hipError_t iteration_sr(const CgVecParams &vp, const double *sigma, int nrhs, int after_check, bool fused,
+                            int k) {
+        DslashParams prm{};
+        prm.g = g;
+        prm.nrhs = nrhs;
+        prm.links = links_in;
+        int *off = reinterpret_cast<int *>(flags() + F_OFF0);
+        if (fused)
+            prm.col_skip = off;
+        else
+            prm.skip = reinterpret_cast<const int *>(flags() + F_SKIP);
+        prm.out_parity = 1;
+        prm.in = vp.r;
+        prm.out = at<void>(L.t);
+        hipError_t e = launch_dslash(prm, lp_in, L.fs, EPI_PLAIN, shape_in, st);
+        if (e != hipSuccess)
+            return e;
+        prm.out_parity = 0;
+        prm.in = at<void>(L.t);
+        prm.out = const_cast<void *>(vp.w);
+        prm.y = vp.r;
+        prm.ad = -1.0;
+        prm.ay = mass * mass + sigma[0];
+        prm.ay_per_rhs = 1;
+        for (int j = 0; j < nrhs; ++j)
+            prm.ay_rhs[j] = mass * mass + sigma[j];
+        prm.partials = const_cast<double *>(vp.rw_part);
+        prm.dot_out = nullptr;  // summed by the scalar step
+        e = launch_dslash(prm, lp_in, L.fs, EPI_AXPY_DOT, shape_in, st);
+        if (e != hipSuccess)
+            return e;
+        if (!fused)
+            return launch_cgcg_step(vp, L.fs, after_check, st);
+        CgScalars *b0 = at<CgScalars>(L.state), *b1 = at<CgScalars>(L.state2);
+        return launch_cgcg_fused(vp, L.fs, k & 1 ? b1 : b0, k & 1 ? b0 : b1, off, after_check, k & 1, st);
+    }
+
+    // The five kernels of one two-reduction iteration for nrhs right-hand
+    // sides, column j solving (M_e + sigma[j]) x = b.
     hipError_t iteration(const CgVecParams &vp, const double *sigma, int nrhs) {
         DslashParams prm{};
         prm.g = g;
@@ -287,13 +348,16 @@ bool terminal(const CgScalars &c) {
     return !c.active && (c.flag == FLAG_DONE || c.flag == FLAG_BREAKDOWN || c.flag == FLAG_MAXIT);
 }
 
-// CG / reliable-update CG for nrhs columns.  info[nrhs] is filled.
+// Single-reduction CG / reliable-update CG for nrhs columns.  info[nrhs] is
+// filled.
 //
 // The device runs the whole recurrence: every `check` iterations a
-// true-residual block forms r_j = b_j - A x_j in FP64 for each column that
-// raised FLAG_CONV or FLAG_RELIABLE since the last block (the kernels of the
-// other columns do nothing) and cg_restart_kernel decides DONE / MAXIT /
-// residual replacement, so a reliable update needs no host round trip.
+// true-residual block forms r_j = b_j - A x_j in FP64 (with the partials of
+// its norm in the column's <r, r> slots) for each column that raised
+// FLAG_CONV or FLAG_RELIABLE since the last block (the kernels of the other
+// columns do nothing), and the scalar step of the next iteration decides DONE
+// / MAXIT / residual replacement, so a reliable update needs no host round
+// trip.
 // Chunks of iterations (a multiple of `check`, each ending with a block) are
 // replayed from one HIP graph; the host keeps a second chunk queued while it
 // reads the state of the previous one, and stops when every column is done.
@@ -313,11 +377,24 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     char *rs = S.at<char>(L.r);
     const size_t cs = S.fs_col();
     S.shape_in = pick_shape(S.ctx, g, S.lp_in, L.fs, nrhs);
+    const int nb = blas_blocks(g.vh);
+    double *rr = S.at<double>(L.rr);
     bool breakdown = false;
     for (int j = 0; j < nrhs; ++j) {
         if ((s = S.norm2(C.b[j], &bnorm2[j])) != HISQ_OK)
             return s;
-        if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &rtrue2[j])) != HISQ_OK)
+        // r_j = b_j - A x_j, its <r, r> partials where the first scalar step
+        // reads them, and the FP64 norm for the decisions below
+        if ((s = S.apply_m64(C.sigma[j], C.x[j], S.at<void>(L.ax))) != HISQ_OK)
+            return s;
+        hipError_t e = launch_residual_cols(g.vh, 1, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
+                                            rr + (size_t)j * nb, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                            nullptr, nullptr, st);
+        if (e == hipSuccess)
+            e = launch_sum_partials(rr + (size_t)j * nb, 1, nb, S.scal() + S_TMP, 1, nullptr, st);
+        if ((s = S.dev(e, "initial residual")) != HISQ_OK)
+            return s;
+        if ((s = S.read_double(S.scal() + S_TMP, &rtrue2[j])) != HISQ_OK)
             return s;
         CgScalars c{};
         c.rho = rtrue2[j];
@@ -327,6 +404,7 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         c.delta2 = delta * delta;
         c.max_iter = max_iter;
         c.iters = 0;
+        c.restart = 1;  // the first step starts the directions: p = r, s = A r
         const bool bad = !std::isfinite(bnorm2[j]) || !std::isfinite(rtrue2[j]);
         if (bad) {
             c.flag = FLAG_BREAKDOWN;
@@ -339,16 +417,15 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         }
         hs[j] = c;
     }
-    // p = r
-    if ((s = S.dev(launch_copy(g.vh, nrhs, L.fs, L.fs, rs, S.at<void>(L.p), st), "copy")) != HISQ_OK)
-        return s;
     int *trf = reinterpret_cast<int *>(S.flags() + F_TR0);
     {
         int any = 0;
         for (int j = 0; j < nrhs; ++j)
             any |= hs[j].active;
-        std::vector<unsigned> fl(F_TR0 + HISQ_MAX_RHS, 1u);
+        std::vector<unsigned> fl(F_OFF0 + HISQ_MAX_RHS, 1u);
         fl[F_SKIP] = any ? 0u : 1u;
+        for (int j = 0; j < nrhs; ++j)
+            fl[F_OFF0 + j] = hs[j].active ? 0u : 1u;
         hipError_t e = hipMemcpyAsync(dst, hs.data(), sizeof(CgScalars) * nrhs, hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(S.flags(), fl.data(), sizeof(unsigned) * fl.size(), hipMemcpyHostToDevice, st);
@@ -365,9 +442,21 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         vp.x[j] = C.x[j];
     vp.r = rs;
     vp.p = S.at<void>(L.p);
-    vp.q = S.at<void>(L.q);
+    vp.s = S.at<void>(L.q);
+    vp.w = S.at<void>(L.w);
     vp.st = dst;
     vp.partials = S.partials();
+    vp.rr_part = rr;
+    vp.rs_part = S.at<double>(L.rspart);
+    vp.ps_part = S.at<double>(L.pspart);
+    vp.rr_nblk = nb;
+    // one launch for the scalar and vector steps when every block can afford
+    // to sum its column's partials itself (measured: 32^3x8 and smaller)
+    const bool fused = vp.rw_nblk <= 2048 && nb <= 2048;
+    vp.part_buf = fused ? L.part_set : 0;
+    int *col_off = reinterpret_cast<int *>(S.flags() + F_OFF0);
+    vp.rw_part = S.at<double>(L.dpart);
+    vp.rw_nblk = dslash_partial_blocks(g, S.shape_in);
     vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
     vp.tr_skip = trf;
     int *nopend = reinterpret_cast<int *>(S.flags() + F_NOPEND);
@@ -375,12 +464,12 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     vp.nshift = 0;
 
     // true-residual block: columns that wait for one get r = b - A x and the
-    // FP64 partials of ||r||^2 (column j's in partials + j * nb).  When the
-    // columns of x and b are one packed multi-column field each (hisq_cg),
-    // A x is formed for all of them by one multi-right-hand-side FP64
-    // operator application whenever any column waits (the links are read
-    // once, not once per column); otherwise column by column.
-    const int nb = blas_blocks(g.vh);
+    // FP64 partials of ||r||^2 in their <r, r> slots (column j's at
+    // rr + j * nb), which the next scalar step reads.  When the columns of x
+    // and b are one packed multi-column field each (hisq_cg), A x is formed
+    // for all of them by one multi-right-hand-side FP64 operator application
+    // whenever any column waits (the links are read once, not once per
+    // column); otherwise column by column.
     const size_t c64 = S.f64_col();
     bool packed = nrhs > 1;
     for (int j = 1; j < nrhs && packed; ++j)
@@ -392,7 +481,10 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
             prm.g = g;
             prm.nrhs = nrhs;
             prm.links = S.links64;
-            prm.skip = nopend;
+            if (fused)
+                prm.col_skip = trf;
+            else
+                prm.skip = nopend;
             prm.out_parity = 1;
             prm.in = C.x[0];
             prm.out = S.at<void>(L.t64m);
@@ -409,23 +501,24 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
             for (int j = 0; j < nrhs; ++j)
                 prm.ay_rhs[j] = S.mass * S.mass + C.sigma[j];
             e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, S.shape64m, st);
-            for (int j = 0; j < nrhs && e == hipSuccess; ++j)
-                e = launch_residual_parts(g.vh, L.fs, C.b[j], S.at<char>(L.axm) + j * c64, rs + j * cs,
-                                          S.partials() + (size_t)j * nb, trf + j, st);
             if (e == hipSuccess)
-                e = launch_cg_restart(vp, S.partials(), st);
-            return e == hipSuccess ? launch_cg_p(vp, L.fs, 0, nrhs, st, true) : e;
+                e = launch_residual_cols(g.vh, nrhs, L.fs, C.b[0], S.at<void>(L.axm), rs, rr, trf, vp.s, vp.p,
+                                         vp.rs_part, vp.ps_part, fused ? nullptr : vp.skip,
+                                         fused ? col_off : nullptr, st);
+            return e;
         }
         for (int j = 0; j < nrhs; ++j) {
             hipError_t e = S.m64(C.sigma[j], C.x[j], S.at<void>(L.ax), trf + j);
             if (e == hipSuccess)
-                e = launch_residual_parts(g.vh, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
-                                          S.partials() + (size_t)j * nb, trf + j, st);
+                e = launch_residual_cols(g.vh, 1, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
+                                         rr + (size_t)j * nb, trf + j, static_cast<char *>(vp.s) + j * cs,
+                                         static_cast<char *>(vp.p) + j * cs, vp.rs_part + (size_t)j * nb,
+                                         vp.ps_part + (size_t)j * nb, fused ? nullptr : vp.skip,
+                                         fused ? col_off + j : nullptr, st);
             if (e != hipSuccess)
                 return e;
         }
-        hipError_t e = launch_cg_restart(vp, S.partials(), st);
-        return e == hipSuccess ? launch_cg_p(vp, L.fs, 0, nrhs, st, true) : e;
+        return hipSuccess;
     };
     // iterations between blocks: a flagged column idles until the next one.
     // Chunks of about 0.5 ms (measured: longer chunks overshoot more at the
@@ -434,10 +527,12 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     const int unit = delta > 0.0 ? 4 : 8;
     const int chunk = unit * std::max(1, (int)std::lround(500.0 / (unit * S.iter_us)));
     const int check = delta > 0.0 ? 4 : chunk;
+    // a chunk ends with a check block, so the first scalar step of every
+    // chunk, and the one after each block, decides the waiting columns
     auto chunk_eager = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int k = 0; k < chunk && e == hipSuccess; ++k) {
-            e = S.iteration(vp, C.sigma, nrhs);
+            e = S.iteration_sr(vp, C.sigma, nrhs, k % check == 0 ? 1 : 0, fused, k);
             if (e == hipSuccess && (k + 1) % check == 0)
                 e = tr_block();
         }

@@ -40,6 +40,9 @@ struct DslashParams {
     int ay_per_rhs;                 // EPI_AXPY*: use ay_rhs[r] instead of ay
     double ay_rhs[HISQ_MAX_RHS];
     const int *skip;     // optional: if *skip != 0 the whole launch does nothing
+    // optional [nrhs]: a block whose right-hand sides r all have
+    // col_skip[r] != 0 does nothing (its outputs and partials are not written)
+    const int *col_skip;
     double *partials;    // EPI_AXPY_DOT: [nrhs][site blocks] block partials
     double *dot_out;     // EPI_AXPY_DOT: totals, dot_out[r * dot_stride] (finalize kernel)
     int dot_stride;
@@ -120,6 +123,16 @@ template <int NIN> struct BlockPos {
         nr = min(NIN, prm.nrhs - r0);
     }
 };
+
+// False when col_skip gates off every right-hand side of this block.
+template <int NIN> __device__ __forceinline__ bool columns_run(const DslashParams &prm, const BlockPos<NIN> &bp) {
+    if (!prm.col_skip)
+        return true;
+    int run = 0;
+    for (int r = 0; r < bp.nr; ++r)
+        run |= prm.col_skip[bp.r0 + r] == 0 ? 1 : 0;
+    return run != 0;
+}
 
 template <int NIN, typename A> __device__ __forceinline__ void zero(cplx<A> (&v)[NIN][3]) {
 #pragma unroll
@@ -399,6 +412,8 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
     if (prm.skip && *prm.skip)
         return;
     const BlockPos<NIN> bp(prm);
+    if (!columns_run(prm, bp))
+        return;
     const int i = bp.site(prm, bp.sb * blockDim.x + threadIdx.x);
     const bool valid = i < prm.g.vh;
     if (EPI != EPI_AXPY_DOT && !valid)
@@ -430,6 +445,8 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
         return;
     const int mu = threadIdx.x & 3;
     const BlockPos<NIN> bp(prm);
+    if (!columns_run(prm, bp))
+        return;
     const int i = bp.site(prm, bp.sb * (blockDim.x >> 2) + (threadIdx.x >> 2));
     // a site's four lanes are in one wavefront and share validity, so whole
     // quads drop out together and the shuffles below see only valid partners

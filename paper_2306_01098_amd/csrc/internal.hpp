@@ -45,6 +45,27 @@ hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStre
 // The true-residual check after r = b - A x of the waiting columns (partials
 // in trpart, blas_blocks(vh) per column).
 hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStream_t st);
+// Single-reduction CG: the per-column scalar step (after_check: decide the
+// columns whose FP64 true residual the check block just formed) and the
+// fused vector update with the <r, r> partials of the new residual.
+hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipStream_t st);
+// r_j = b_j - ax_j for the ncol columns of packed fields b, ax (FP64) and r
+// (sloppy) whose tr_skip[j] is 0 (every column if tr_skip is NULL), with the
+// block partials of ||r_j||^2 at partials + j * blas_blocks(vh) and, if s and
+// p (sloppy, ncol columns) are not NULL, those of Re <r_j, s_j> and
+// Re <p_j, s_j> at spart / ppart + j * blas_blocks(vh); a launch that forms
+// residuals clears *skip and col_off[j] of each column it forms (both
+// nullable).
+hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
+                                const int *tr_skip, const void *s, const void *p, double *spart, double *ppart,
+                                int *skip, int *col_off, hipStream_t st);
+// The scalar and vector steps of single-reduction CG in one launch (every
+// block sums its column's partials): state read from st_in, written to
+// st_out, partials read from set in_buf and written to the other;
+// col_off[j] = 1 while column j is inactive.
+struct CgScalars;
+hipError_t launch_cgcg_fused(const CgVecParams &p, int fp, const CgScalars *st_in, CgScalars *st_out, int *col_off,
+                             int after_check, int in_buf, hipStream_t st);
 // r = b - ax (sloppy r) and the block partials of ||b - ax||^2, without the
 // sum; the launch does nothing while skip (nullable) points to a nonzero value.
 hipError_t launch_residual_parts(int vh, int fp, const void *b, const void *ax, void *r, double *partials,

@@ -31,13 +31,18 @@ struct alignas(16) CgScalars {
     double rho_new;  // <r, r> after the last update (kept when a flag is raised)
     double rtrue2;   // ||b - A x||^2 (FP64) at the last true-residual check
     double spare;    // the batch solver's stop time stamp
+    double alpha;    // single-reduction CG: the step length of the last update
     int active;      // 1 while the recurrence runs
     int flag;        // FLAG_*
     int iters;       // iterations performed
     int max_iter;
     int nrel;        // reliable updates (residual replacements) so far
-    int restart;     // 1 right after a replacement, until p = r + beta p is redone
-    int pad[2];
+    // two-reduction CG: 1 right after a replacement, until p = r + beta p is
+    // redone; single-reduction CG: 1 while the next step starts the
+    // directions afresh (p = r, s = w)
+    int restart;
+    int go;          // single-reduction CG: the update kernel steps this column now
+    int pad;
 };
 
 // Per shift k of the multi-shift solver (Jegerlehner's recurrences, FP64).
@@ -88,6 +93,19 @@ struct CgVecParams {
     MsGlobal *ms;
     void *xs[MAX_SHIFTS];  // FP64 x_k
     void *ps;              // sloppy p_k, [nshift] fields
+    // single-reduction CG (r, p as above; q unused):
+    void *s;               // sloppy s = A p [nrhs]
+    const void *w;         // sloppy w = A r [nrhs] (the D_eo kernel's output)
+    // [nrhs][rr_nblk] block partials of <r, r>, Re <r, s> and Re <p, s> of
+    // the vectors the update kernel wrote; with the fused step two sets
+    // alternate, part_buf doubles apart (0: one set)
+    double *rr_part;
+    double *rs_part;
+    double *ps_part;
+    int rr_nblk;
+    size_t part_buf;
+    const double *rw_part; // [nrhs][rw_nblk] block partials of Re <r, w> (D_eo kernel)
+    int rw_nblk;
 };
 
 }  // namespace hisq
