@@ -46,6 +46,8 @@ def dslash_bytes(vh: int, prec: str) -> int:
         return vh * (288 * 2 + 16 + 16)      # binary16 links, 16-byte site records in and out
     if prec.endswith("r12"):
         return vh * (16 * 12 + 12) * REAL_BYTES[prec[:4]]   # 12 stored reals per link
+    if prec.endswith("w14"):
+        return vh * (8 * 18 + 8 * 14 + 12) * REAL_BYTES[prec[:4]]   # fat links 18 reals, Naik links 14
     return vh * 300 * REAL_BYTES[prec]
 
 
@@ -66,6 +68,9 @@ def parse():
     ap.add_argument("--no-cg", action="store_true", help="skip the CG time-to-solution legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the default workload legs w1, w3, w4 (8^4 CG, 48^3x12 multi-rhs and "
+                         "multi-shift CG, uneven batch of 64)")
     ap.add_argument("--suite", default="",
                     help="comma list of extra workload legs to add to the JSON line: "
                          "w1 (8^4 FP64 CG), w3 (48^3x12 16-rhs Dslash/CG and 14-shift CG), "
@@ -127,11 +132,11 @@ def leg_dslash16(h, gen, O, torch):
             "shape": list(h.hisq_get_dslash_shape(lat, "fp32", 16, None))}
 
 
-def leg_w3(h, gen, O, torch):
+def leg_w3(h, gen, O, torch, w=None):
     """48^3x12 smooth links, m = 0.005: 16-rhs FP32 Dslash, 16-rhs CG vs 16
     single solves, 14-shift CG."""
     import numpy as np
-    w = gen.workload_3()
+    w = gen.workload_3() if w is None else w
     dims, m = w["dims"], w["mass"]
     lat = h.lattice(dims, w["t_bc"])
     vh = int(np.prod(dims)) // 2
@@ -197,14 +202,15 @@ def leg_w3(h, gen, O, torch):
         tms = time.perf_counter() - t0
     out["multishift14"] = {"seconds": round(tms, 4), "status": st,
                            "iterations": [i["iterations"] for i in info],
+                           "shared_iterations": [i["shared_iterations"] for i in info],
                            "true_residuals": [i["true_residual"] for i in info]}
     return out
 
 
-def leg_w4(h, gen, O, torch):
+def leg_w4(h, gen, O, torch, probs_in=None):
     """Uneven batch: 64 Haar-link solves, FP32 + FP64 reliable updates."""
     import numpy as np
-    probs_in = gen.workload_4()
+    probs_in = gen.workload_4() if probs_in is None else probs_in
     items = []
     for w in probs_in:
         lat = h.lattice(w["dims"], w["t_bc"])
@@ -227,16 +233,18 @@ def leg_w4(h, gen, O, torch):
            "iterations_min_max": [min(i["iterations"] for i in info), max(i["iterations"] for i in info)],
            "max_true_residual": max(i["true_residual"] for i in info)}
     t0 = time.perf_counter()
-    seq_lat = []
+    seq_lat, seq_its = [], []
     for it in items:
         it["x"].zero_()
         wsi = h.empty_workspace(h.hisq_cg_workspace_bytes(it["lat"], "fp32", 1, 0))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        h.hisq_cg(it["lat"], it["mass"], it["links_f64"], it["links_inner"], "fp32", 1, it["b"], it["x"],
-                  1e-10, 40000, wsi)
+        _, info1 = h.hisq_cg(it["lat"], it["mass"], it["links_f64"], it["links_inner"], "fp32", 1, it["b"],
+                             it["x"], 1e-10, 40000, wsi)
         seq_lat.append(time.perf_counter() - t1)
+        seq_its.append(info1[0]["iterations"])
     tseq = time.perf_counter() - t0
+    out["_sequential_iterations"] = seq_its   # for the CPU estimate; not printed
     out["sequential_seconds"] = round(tseq, 4)
     out["sequential_latency_ms_p50"] = round(float(np.percentile(np.array(seq_lat) * 1e3, 50)), 2)
     out["speedup_batch_vs_sequential"] = round(tseq / tb, 3)
@@ -420,6 +428,109 @@ def leg_ptc(h, gen, O, torch):
             "peak": "157.3 TFLOP/s FP32 vector (packed dual-issue); without packed FP32 the ceiling is 78.6"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_cg_seconds_per_iteration(O, w, mass, n=4):
+    """Wall time of one iteration of the oracle's textbook CG on workload w:
+    a capped solve of n iterations minus the setup (one M_e application and the
+    final true residual, i.e. two more M_e), divided by n."""
+    lat = O.lattice_from(w)
+    src = w["src"][0]
+    t0 = time.perf_counter()
+    lat.M_e(mass, src)
+    t_me = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.cg(lat, mass, src, 1e-30, n)
+    t = time.perf_counter() - t0
+    return max(t - 2.0 * t_me, t_me) / n
+
+
+def cpu_baseline(gen, w, dims, t_bc, mass, bytes64, legs, inputs):
+    """The oracle on the host cores: FP64 D_oe throughput at 32^3x8 (all
+    threads, and one thread in a child process), CG to 1e-10 for the 32^3x8
+    and 8^4 workloads, and estimates for the 48^3x12 per-shift solves and the
+    64 sequential batch solves (measured oracle CG time per iteration x the
+    GPU solves' iteration counts)."""
+    import numpy as np
+    from oracle import hisq as O
+    s0 = w["src"][0]
+    O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
+    n = 0
+    c0 = time.perf_counter()
+    while time.perf_counter() - c0 < 10.0:
+        O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
+        n += 1
+    dt = (time.perf_counter() - c0) / n
+    out = {
+        "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
+        "sample": f"{n} FP64 D_oe applications of the C oracle at 32^3x8 in ~10 s (same inputs), "
+                  "algorithmic bytes per application / mean time",
+        "cpu_model": cpu_model(), "cpus_available": len(os.sched_getaffinity(0))}
+    # one thread (the oracle's own thread setting; the results do not depend on it)
+    nall = O.num_threads()
+    O.set_num_threads(1)
+    try:
+        O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
+        n1 = 0
+        c0 = time.perf_counter()
+        while time.perf_counter() - c0 < 5.0:
+            O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
+            n1 += 1
+        dt1 = (time.perf_counter() - c0) / n1
+        out["one_thread"] = {"GB/s": round(bytes64 / dt1 / 1e9, 3), "threads": O.num_threads(),
+                             "sample": f"{n1} FP64 D_oe applications in ~5 s"}
+    finally:
+        O.set_num_threads(nall)
+    # the oracle's textbook FP64 CG to the same 1e-10 true residual
+    cgcpu = {}
+    c0 = time.perf_counter()
+    r = O.cg(O.lattice_from(w), mass, s0, 1e-10, 40000)
+    cgcpu["32^3x8_m0.01"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
+    w1 = gen.workload_1()
+    c0 = time.perf_counter()
+    r = O.cg(O.lattice_from(w1), w1["mass"], w1["src"][0], 1e-10, 40000)
+    cgcpu["8^4_m0.1"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
+    out["cg_time_to_solution_1e-10"] = cgcpu
+    est = {}
+    if "w3" in inputs and "w3" in legs:
+        w3 = inputs["w3"]
+        its = legs["w3"]["multishift14"]["shared_iterations"]
+        per = oracle_cg_seconds_per_iteration(O, w3, w3["mass"])
+        est["48^3x12_14_per_shift_cgs"] = {
+            "seconds_estimate": round(per * sum(its), 1), "oracle_cg_seconds_per_iteration": round(per, 4),
+            "iterations_total": int(sum(its)),
+            "how": "oracle CG seconds per iteration (a 4-iteration solve, timed) x the sum over the 14 shifts "
+                   "of the iterations the GPU multi-shift solve froze each shift at (about what an "
+                   "independent CG per shift takes)"}
+    if "w4" in inputs and "w4" in legs and "_sequential_iterations" in legs["w4"]:
+        probs = inputs["w4"]
+        its = legs["w4"]["_sequential_iterations"]
+        per_dims = {}
+        for p in probs:
+            key = tuple(p["dims"])
+            if key not in per_dims:
+                per_dims[key] = oracle_cg_seconds_per_iteration(O, p, p["mass"], n=8)
+        secs = np.array([per_dims[tuple(p["dims"])] * it for p, it in zip(probs, its)])
+        est["uneven_batch_64_sequential"] = {
+            "seconds_estimate": round(float(secs.sum()), 1),
+            "per_solve_ms_p50_p99": [round(float(np.percentile(secs, q)) * 1e3, 1) for q in (50, 99)],
+            "oracle_cg_ms_per_iteration": {"x".join(map(str, k)): round(v * 1e3, 3) for k, v in per_dims.items()},
+            "how": "oracle CG seconds per iteration on each lattice size (an 8-iteration solve, timed) x the "
+                   "iterations of the GPU's one-by-one solve of each problem"}
+    if est:
+        out["estimates"] = est
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -446,7 +557,7 @@ def main():
     ctx = h.Context(0)
     stream = torch.cuda.current_stream()
 
-    PRECS = ("fp64", "fp32", "fp16n", "fp64r12", "fp32r12")
+    PRECS = ("fp64", "fp32", "fp16n", "fp64r12", "fp32r12", "fp64w14", "fp32w14")
     links = {p: h.pack_links_from_host(lat, p, w["fat"], w["naik"], ctx=ctx) for p in PRECS}
     src = {p: h.pack_field_from_host(lat, p, w["src"][0], ctx=ctx) for p in PRECS}
     tmp = {p: h.empty_field(lat, p) for p in PRECS}
@@ -581,7 +692,7 @@ def main():
             "what": "D_eo after a 1 GiB device write, median of 20"},
     }
     other = {}
-    for p in ("fp32", "fp16n", "fp64r12", "fp32r12"):
+    for p in PRECS[1:]:
         n_p = min(100, steps)
         ms_p, _ = timed(p, n_p, min(10, warm))
         t = ms_p * 1e-3 / (2 * n_p)
@@ -594,7 +705,7 @@ def main():
     if not args.no_cg:
         b = src["fp64"]
         cg = {}
-        for inner in ("fp64", "fp32", "fp16n", "fp64r12", "fp32r12"):
+        for inner in PRECS:
             lin = None if inner == "fp64" else links[inner]
             ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, inner, 1, 0))
             x = h.empty_field(lat, "fp64")
@@ -611,47 +722,38 @@ def main():
                          "true_residual": info["true_residual"]}
         result["cg_time_to_solution_1e-10"] = cg
         result["cg_speedup_mixed_vs_fp64"] = {
-            p: round(cg["fp64"]["seconds"] / cg[p]["seconds"], 3) for p in ("fp32", "fp16n", "fp64r12", "fp32r12")}
+            p: round(cg["fp64"]["seconds"] / cg[p]["seconds"], 3) for p in PRECS[1:]}
 
-    if not args.no_cpu:
-        from oracle import hisq as O
-        s0 = w["src"][0]
-        O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
-        n = 0
-        c0 = time.perf_counter()
-        while time.perf_counter() - c0 < 10.0:
-            O.dslash(dims, t_bc, w["fat"], w["naik"], s0, 1)
-            n += 1
-        dt = (time.perf_counter() - c0) / n
-        result["cpu_baseline"] = {
-            "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{n} FP64 D_oe applications of the C oracle at 32^3x8 in ~10 s (same inputs), "
-                      "algorithmic bytes per application / mean time"}
-        # the oracle's textbook FP64 CG to the same 1e-10 true residual, for the
-        # time-to-solution comparison (32^3x8 and the 8^4 Haar workload)
-        cgcpu = {}
-        c0 = time.perf_counter()
-        r = O.cg(O.lattice_from(w), mass, s0, 1e-10, 40000)
-        cgcpu["32^3x8_m0.01"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
-        w1 = gen.workload_1()
-        c0 = time.perf_counter()
-        r = O.cg(O.lattice_from(w1), w1["mass"], w1["src"][0], 1e-10, 40000)
-        cgcpu["8^4_m0.1"] = {"seconds": round(time.perf_counter() - c0, 3), "iterations": r.iterations}
-        result["cpu_baseline"]["cg_time_to_solution_1e-10"] = cgcpu
-
-    legs = [x for x in args.suite.split(",") if x]
+    # workload legs: 8^4 CG, 48^3x12 multi-rhs / multi-shift CG and the uneven
+    # batch by default, the others on request; the library only
+    legs = [] if args.no_legs else ["w1", "w3", "w4"]
+    legs += [x for x in args.suite.split(",") if x and x not in legs]
+    inputs = {}
+    if "w3" in legs:
+        inputs["w3"] = gen.workload_3()
+    if "w4" in legs:
+        inputs["w4"] = gen.workload_4()
     if legs:
-        O = None   # the workload legs run the library only
         result["workloads"] = {}
         for leg in legs:
             log(f"leg {leg} ...")
             fn = {"w1": leg_w1, "w3": leg_w3, "w4": leg_w4, "w5": leg_w5, "ptc": leg_ptc, "pbp": leg_pbp,
                   "dslash16": leg_dslash16, "smear": leg_smear}[leg]
             t0 = time.perf_counter()
-            result["workloads"][leg] = fn(h, gen, O, torch)
+            if leg in inputs:
+                result["workloads"][leg] = fn(h, gen, None, torch, inputs[leg])
+            else:
+                result["workloads"][leg] = fn(h, gen, None, torch)
             result["workloads"][leg]["leg_wall_s"] = round(time.perf_counter() - t0, 1)
             log(f"leg {leg}: {json.dumps(result['workloads'][leg])}")
             torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(gen, w, dims, t_bc, mass, bytes64, result.get("workloads", {}),
+                                              inputs)
+    for leg in result.get("workloads", {}).values():
+        for k in [k for k in leg if k.startswith("_")]:
+            del leg[k]
 
     print(json.dumps(result), flush=True)
 

@@ -73,19 +73,41 @@ typedef struct {
  *                rows 0 and 1 of each matrix are stored (12 reals, rounded as
  *                for HISQ_FP64 / HISQ_FP32); row 2 is rebuilt in-kernel as the
  *                complex conjugate of the cross product of rows 0 and 1, which
- *                is exact for SU(3) and wrong for anything else (the library
- *                does not check; HISQ fat links are in general not unitary).
- *                Colour vectors and arithmetic as for HISQ_FP64 / HISQ_FP32,
- *                so fields of these precisions are HISQ_FP64 / HISQ_FP32
- *                fields.  Accepted by the pack/unpack calls, hisq_dslash,
- *                hisq_apply_m, the autotuner, and as the `inner` precision of
- *                hisq_cg and hisq_multishift_cg (links_inner in this format). */
+ *                is exact for SU(3) and wrong for anything else.
+ *                hisq_pack_links checks every link (X and W) and refuses
+ *                (HISQ_ERR_INVALID_ARG) links whose rebuilt row 2 differs from
+ *                the given one by more than 1e-10 (FP64R12) or 1e-5 (FP32R12)
+ *                times the matrix's Frobenius norm: HISQ fat links, and the
+ *                U(3) Naik links of hisq_smear_links, are refused.
+ *   HISQ_FP64W14, HISQ_FP32W14 : fat links X stored in full (as HISQ_FP64 /
+ *                HISQ_FP32); Naik links W stored as rows 0 and 1 plus one
+ *                complex factor z (14 reals), row 2 rebuilt in-kernel as
+ *                z conj(row 0 x row 1).  z = <c, row 2> / <c, c> with
+ *                c = conj(row 0 x row 1) is formed from the FP64 input; the
+ *                form is exact for SU(3) (z = 1), U(3) (z = det) and real
+ *                multiples a V of U(3) matrices (z = det V / a), such as the
+ *                HISQ Naik link c_Naik Y(x) Y(x+mu) Y(x+2mu) with Y in U(3)
+ *                that hisq_smear_links returns.  hisq_pack_links refuses
+ *                (HISQ_ERR_INVALID_ARG) Naik links that the form does not
+ *                reproduce to 1e-10 (FP64W14) or 1e-5 (FP32W14) of their
+ *                Frobenius norm.  Bytes per Dslash output site: 2144 (FP64W14)
+ *                and 1072 (FP32W14), against 2400 and 1200 uncompressed.
+ *                Reconstruct-12 and W14 packing synchronize `stream` (they
+ *                read the check's result back) and are serialized within the
+ *                process.  Colour vectors and arithmetic of the R12 and W14
+ *                formats are those of HISQ_FP64 / HISQ_FP32, so their fields
+ *                are HISQ_FP64 / HISQ_FP32 fields.  Accepted by the
+ *                pack/unpack calls, hisq_dslash, hisq_apply_m (and _dot), the
+ *                autotuner, and as the `inner` precision of hisq_cg and
+ *                hisq_multishift_cg (links_inner in this format). */
 typedef enum {
     HISQ_FP64 = 0,
     HISQ_FP32 = 1,
     HISQ_FP16N = 2,
     HISQ_FP64R12 = 3,
-    HISQ_FP32R12 = 4
+    HISQ_FP32R12 = 4,
+    HISQ_FP64W14 = 5,
+    HISQ_FP32W14 = 6
 } hisq_prec;
 
 typedef enum {
@@ -212,7 +234,8 @@ hisq_status hisq_apply_m(hisq_context *ctx, const hisq_lattice *lat, hisq_prec p
  *   link_prec, field_prec  one of the pairs the solvers use: (FP64, FP64),
  *               (FP32, FP32), (FP16N, FP16N), (FP16N, FP32) (binary16 links
  *               with FP32 vectors, the inner operator of hisq_cg with
- *               inner = HISQ_FP16N), (FP64R12, FP64), (FP32R12, FP32);
+ *               inner = HISQ_FP16N), (FP64R12, FP64), (FP32R12, FP32),
+ *               (FP64W14, FP64), (FP32W14, FP32);
  *               anything else is HISQ_ERR_INVALID_ARG.
  *   links       packed links of link_prec; in_even, out_even (even sites) and
  *               tmp_odd (odd sites, scratch) packed fields of nrhs columns in
@@ -363,7 +386,7 @@ size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *prob
  * iterated residual meets its target stops updating while the others go on.
  * With inner = FP32/FP16N the iterations use that link precision with FP32
  * vectors and FP64 reliable updates (batched over the problems that need
- * one), as in hisq_cg.  The reconstruct-12 precisions are not accepted here
+ * one), as in hisq_cg.  The compressed (R12, W14) precisions are not accepted here
  * (HISQ_ERR_UNSUPPORTED; the workspace query returns 0).
  *   problems    host array [nproblems]; the structs may be freed on return.
  *   info        host array [nproblems] (seconds = wall time of the batch).

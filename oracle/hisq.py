@@ -48,6 +48,8 @@ def _open(path: str):
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_long, ctypes.c_void_p]
     lib_.oracle_num_threads.restype = ctypes.c_int
+    lib_.oracle_set_num_threads.restype = None
+    lib_.oracle_set_num_threads.argtypes = [ctypes.c_int]
     return lib_
 
 
@@ -75,6 +77,11 @@ def substituted_library(path: str):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (timing only; results are the same)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------
@@ -269,6 +276,9 @@ def multishift_reference(lat: Lattice, mass: float, shifts, b, tol, max_iter: in
 #   FP32:   each real and imaginary part rounded to binary32 (nearest-even).
 #   R12:    links: rows 0 and 1 rounded as FP64 / FP32, row 2 rebuilt as
 #           conj(row0 x row1); colour vectors as FP64 / FP32.
+#   W14:    fat links as FP64 / FP32; Naik links: rows 0 and 1 and the factor
+#           z (from the FP64 input) rounded as FP64 / FP32, row 2 rebuilt as
+#           z conj(row0 x row1); colour vectors as FP64 / FP32.
 #   FP16N:  links: each real part rounded once, from binary64, to binary16
 #           (nearest-even).
 #           colour vectors: per site n = max |component| over the 6 reals,
@@ -322,6 +332,43 @@ def quantize_links_r12(U, prec: str):
     return reconstruct12(U)
 
 
+def scaled_row2_factor(U):
+    """The complex factor z with row 2 closest to z conj(row0 x row1) in the
+    least-squares sense, z = <c, r2> / <c, c> with c = conj(row0 x row1) (0
+    where c = 0).  For U in SU(3) z = 1; for U in U(3) z = det U (write
+    U = e^{i phi} S with S in SU(3): row 2 = e^{i phi} conj(s0 x s1) and
+    conj(u0 x u1) = e^{-2 i phi} conj(s0 x s1)); for a real multiple a V of a
+    U(3) matrix z = det V / a."""
+    U = np.asarray(U, dtype=np.complex128)
+    c = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    cc = np.sum(c.real ** 2 + c.imag ** 2, axis=-1)
+    num = np.sum(np.conj(c) * U[..., 2, :], axis=-1)
+    d = np.where(cc > 0, cc, 1.0)        # complex / positive real: part by part
+    return np.where(cc > 0, num.real / d + 1j * (num.imag / d), 0.0)
+
+
+def reconstruct_scaled(U, z):
+    """Rows 0 and 1 of U kept, row 2 replaced by z conj(row0 x row1)."""
+    U = np.array(U, dtype=np.complex128)
+    U[..., 2, :] = np.asarray(z)[..., None] * np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    return U
+
+
+def quantize_links_w14(U, prec: str):
+    """The 14-real storage of the Naik links: the factor z of
+    scaled_row2_factor formed from the FP64 input, then rows 0 and 1 and z
+    rounded to `prec` ("fp64" or "fp32"), row 2 rebuilt from the rounded
+    values (in FP64).  Exact (up to that rounding) for SU(3), U(3) and real
+    multiples of U(3) matrices, such as the HISQ Naik link c_Naik Y Y Y."""
+    U = np.asarray(U, dtype=np.complex128)
+    z = scaled_row2_factor(U)
+    if prec == "fp32":
+        U, z = quantize_fp32(U), quantize_fp32(z)
+    elif prec != "fp64":
+        raise ValueError(prec)
+    return reconstruct_scaled(U, z)
+
+
 def quantized_lattice(lat: Lattice, prec: str) -> Lattice:
     if prec == "fp64":
         return lat
@@ -332,11 +379,15 @@ def quantized_lattice(lat: Lattice, prec: str) -> Lattice:
     if prec in ("fp64r12", "fp32r12"):
         base = prec[:4]
         return Lattice(lat.dims, lat.t_bc, quantize_links_r12(lat.X, base), quantize_links_r12(lat.W, base))
+    if prec in ("fp64w14", "fp32w14"):   # fat links in full, Naik links in 14 reals
+        base = prec[:4]
+        X = lat.X if base == "fp64" else quantize_fp32(lat.X)
+        return Lattice(lat.dims, lat.t_bc, X, quantize_links_w14(lat.W, base))
     raise ValueError(prec)
 
 
 def quantize_field(psi, prec: str):
-    if prec in ("fp64r12", "fp32r12"):   # colour vectors as in the base precision
+    if prec in ("fp64r12", "fp32r12", "fp64w14", "fp32w14"):   # colour vectors as in the base precision
         prec = prec[:4]
     if prec == "fp64":
         return np.asarray(psi, dtype=np.complex128)

@@ -33,9 +33,10 @@ template <bool NT, typename V> __device__ __forceinline__ V ld_link(const V *p) 
 template <> struct LinkIO<HISQ_FP64> {
     using A = double;
     static constexpr bool rebuild = false;
+    __device__ __forceinline__ static void finish(A *, int) {}
     static constexpr bool stream = true;  // the non-temporal hint may pay
     template <bool NT = true>
-    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const nt_d2 v = ld_link<NT>(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
@@ -48,9 +49,10 @@ template <> struct LinkIO<HISQ_FP64> {
 template <> struct LinkIO<HISQ_FP32> {
     using A = float;
     static constexpr bool rebuild = false;
+    __device__ __forceinline__ static void finish(A *, int) {}
     static constexpr bool stream = true;  // the non-temporal hint may pay
     template <bool NT = true>
-    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const nt_f4 v = ld_link<NT>(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
@@ -77,9 +79,10 @@ union H2 {
 template <> struct LinkIO<HISQ_FP16N> {
     using A = float;
     static constexpr bool rebuild = false;
+    __device__ __forceinline__ static void finish(A *, int) {}
     static constexpr bool stream = false;  // the non-temporal hint may pay
     template <bool NT = true>  // ordinary loads either way
-    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             H8 v;
@@ -95,14 +98,19 @@ template <> struct LinkIO<HISQ_FP16N> {
     }
 };
 
-// Reconstruct-12: load fills m[0..11] (rows 0 and 1); rebuild_row2 computes
-// row 2 at the point of use, so the loads of the next hop stay in flight.
+template <typename A> __device__ __forceinline__ void rebuild_row2(A m[18]);
+template <typename A> __device__ __forceinline__ void rebuild_row2_scaled(A m[18]);
+
+// Reconstruct-12: load fills m[0..11] (rows 0 and 1); finish (rebuild_row2)
+// computes row 2 at the point of use, so the loads of the next hop stay in
+// flight.
 template <> struct LinkIO<HISQ_FP64R12> {
     using A = double;
     static constexpr bool rebuild = true;
+    __device__ __forceinline__ static void finish(A *m, int) { rebuild_row2<A>(m); }
     static constexpr bool stream = false;  // the non-temporal hint may pay
     template <bool NT = true>
-    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const nt_d2 v = ld_link<NT>(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
@@ -115,9 +123,10 @@ template <> struct LinkIO<HISQ_FP64R12> {
 template <> struct LinkIO<HISQ_FP32R12> {
     using A = float;
     static constexpr bool rebuild = true;
+    __device__ __forceinline__ static void finish(A *m, int) { rebuild_row2<A>(m); }
     static constexpr bool stream = false;  // the non-temporal hint may pay
     template <bool NT = true>
-    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18]) {
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const nt_f4 v = ld_link<NT>(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
@@ -126,6 +135,59 @@ template <> struct LinkIO<HISQ_FP32R12> {
             m[4 * k + 2] = v.z;
             m[4 * k + 3] = v.w;
         }
+    }
+};
+
+// W14: fat links (f = 0) in full as HISQ_FP64 / HISQ_FP32; Naik links
+// (f = 1) as rows 0 and 1 and the factor z = (m[12], m[13]), row 2 rebuilt
+// by finish as z conj(row 0 x row 1).
+template <> struct LinkIO<HISQ_FP64W14> {
+    using A = double;
+    static constexpr bool rebuild = true;
+    static constexpr bool stream = true;  // the non-temporal hint may pay
+    __device__ __forceinline__ static void finish(A *m, int f) {
+        if (f == 1)
+            rebuild_row2_scaled<A>(m);
+    }
+    template <bool NT = true>
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
+        const int nc = f == 0 ? 9 : 7;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            if (k < nc) {
+                const nt_d2 v = ld_link<NT>(reinterpret_cast<const nt_d2 *>(blk + (size_t)vh * 16 * k) + i);
+                m[2 * k] = v.x;
+                m[2 * k + 1] = v.y;
+            }
+        }
+    }
+};
+
+template <> struct LinkIO<HISQ_FP32W14> {
+    using A = float;
+    static constexpr bool rebuild = true;
+    static constexpr bool stream = true;  // the non-temporal hint may pay
+    __device__ __forceinline__ static void finish(A *m, int f) {
+        if (f == 1)
+            rebuild_row2_scaled<A>(m);
+    }
+    template <bool NT = true>
+    __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
+        const int nc = f == 0 ? 4 : 3;  // 16-byte chunks before the 8-byte tail
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < nc) {
+                const nt_f4 v = ld_link<NT>(reinterpret_cast<const nt_f4 *>(blk + (size_t)vh * 16 * k) + i);
+                m[4 * k] = v.x;
+                m[4 * k + 1] = v.y;
+                m[4 * k + 2] = v.z;
+                m[4 * k + 3] = v.w;
+            }
+        }
+        // tail: entries 16, 17 of a full matrix, or the factor z of a Naik link
+        const nt_f2 t = ld_link<NT>(reinterpret_cast<const nt_f2 *>(blk + (size_t)vh * 16 * nc) + i);
+        m[f == 0 ? 16 : 12] = t.x;
+        m[f == 0 ? 17 : 13] = t.y;
     }
 };
 
@@ -143,6 +205,19 @@ template <typename A> __device__ __forceinline__ void rebuild_row2(A m[18]) {
         const A im = fma(ajr, bli, fma(aji, blr, fma(-alr, bji, -ali * bjr)));
         m[12 + 2 * k] = re;
         m[12 + 2 * k + 1] = -im;
+    }
+}
+
+// Row 2 = z conj(a x b) with z = (m[12], m[13]) (read before row 2 is
+// written over it): exact for real multiples of U(3) matrices.
+template <typename A> __device__ __forceinline__ void rebuild_row2_scaled(A m[18]) {
+    const A zr = m[12], zi = m[13];
+    rebuild_row2<A>(m);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const A cr = m[12 + 2 * k], ci = m[12 + 2 * k + 1];
+        m[12 + 2 * k] = fma(zr, cr, -zi * ci);
+        m[12 + 2 * k + 1] = fma(zr, ci, zi * cr);
     }
 }
 

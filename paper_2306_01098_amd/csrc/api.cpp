@@ -47,7 +47,7 @@ hisq_status check_lattice(const hisq_lattice *lat) {
 
 hisq_status check_prec(int prec) {
     if (prec != HISQ_FP64 && prec != HISQ_FP32 && prec != HISQ_FP16N && prec != HISQ_FP64R12 &&
-        prec != HISQ_FP32R12)
+        prec != HISQ_FP32R12 && prec != HISQ_FP64W14 && prec != HISQ_FP32W14)
         return fail(HISQ_ERR_INVALID_ARG, "unknown precision %d", prec);
     return HISQ_OK;
 }
@@ -196,7 +196,7 @@ size_t hisq_links_bytes(const hisq_lattice *lat, hisq_prec prec) {
     if (check_lattice(lat) != HISQ_OK || check_prec(prec) != HISQ_OK)
         return 0;
     const Geom g = make_geom(*lat);
-    return links_bytes(g, link_matrix_bytes(prec));
+    return links_bytes(g, prec);
 }
 
 size_t hisq_field_bytes(const hisq_lattice *lat, hisq_prec prec, int32_t nrhs) {
@@ -213,9 +213,19 @@ hisq_status hisq_pack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_pre
     TRY(check_ptr(naik_c128, "naik_c128"));
     TRY(check_ptr(packed, "packed"));
     TRY(set_device(ctx));
+    int bad = 0;
     const hipError_t e = launch_pack_links(make_geom(*lat), prec, fat_c128, naik_c128, packed,
-                                           static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HISQ_OK : device_fail(e, "pack_links");
+                                           static_cast<hipStream_t>(stream), &bad);
+    if (e != hipSuccess)
+        return device_fail(e, "pack_links");
+    if (bad)
+        return fail(HISQ_ERR_INVALID_ARG,
+                    prec == HISQ_FP64W14 || prec == HISQ_FP32W14
+                        ? "a Naik link is not of the form z conj(row 0 x row 1) in its row 2 (not a multiple "
+                          "of a U(3) matrix): use an uncompressed format"
+                        : "a link is not special unitary (its row 2 is not conj(row 0 x row 1)): use an "
+                          "uncompressed format, or HISQ_FP64W14 / HISQ_FP32W14 for U(3) Naik links");
+    return HISQ_OK;
 }
 
 hisq_status hisq_unpack_links(hisq_context *ctx, const hisq_lattice *lat, hisq_prec prec, const void *packed,

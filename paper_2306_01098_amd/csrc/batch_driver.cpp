@@ -74,7 +74,7 @@ extern "C" {
 
 size_t hisq_cg_batch_workspace_bytes(int32_t nproblems, const hisq_problem *problems, hisq_prec inner) {
     if (nproblems < 1 || nproblems > MAX_BATCH || !problems || check_prec(inner) != HISQ_OK ||
-        inner == HISQ_FP64R12 || inner == HISQ_FP32R12)
+        inner == HISQ_FP64R12 || inner == HISQ_FP32R12 || inner == HISQ_FP64W14 || inner == HISQ_FP32W14)
         return 0;
     for (int j = 0; j < nproblems; ++j)
         if (check_lattice(&problems[j].lat) != HISQ_OK)
@@ -90,8 +90,9 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         return fail(HISQ_ERR_INVALID_ARG, "nproblems = %d outside [1, %d]", nproblems, MAX_BATCH);
     hisq_status s = check_ptr(problems, "problems");
     if (s == HISQ_OK) s = check_prec(inner);
-    if (s == HISQ_OK && (inner == HISQ_FP64R12 || inner == HISQ_FP32R12))
-        s = fail(HISQ_ERR_UNSUPPORTED, "the batched solver takes FP64, FP32 or FP16N links, not reconstruct-12");
+    if (s == HISQ_OK &&
+        (inner == HISQ_FP64R12 || inner == HISQ_FP32R12 || inner == HISQ_FP64W14 || inner == HISQ_FP32W14))
+        s = fail(HISQ_ERR_UNSUPPORTED, "the batched solver takes FP64, FP32 or FP16N links, not compressed ones");
     if (s == HISQ_OK) s = check_ptr(ws, "ws");
     if (s == HISQ_OK && max_iter < 1)
         s = fail(HISQ_ERR_INVALID_ARG, "max_iter = %d must be >= 1", max_iter);

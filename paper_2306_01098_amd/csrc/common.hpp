@@ -43,7 +43,10 @@ inline Geom make_geom(const hisq_lattice &l) {
 // contiguous, so a wavefront reading chunk k for 64 consecutive sites issues
 // one fully coalesced 1 KiB request.  The last chunk may be shorter
 // (FP32: 8 bytes, FP16: 4 bytes).  Reconstruct-12 formats store only the 12
-// reals of rows 0 and 1 (FP64: 6 chunks, FP32: 3 chunks).
+// reals of rows 0 and 1 (FP64: 6 chunks, FP32: 3 chunks).  The W14 formats
+// store the fat links X in full and the Naik links W as rows 0 and 1 plus a
+// complex factor z (14 reals: FP64 7 chunks, FP32 3 chunks + 8 bytes); all X
+// blocks come first, then the W blocks.
 // ---------------------------------------------------------------------------
 template <int P> struct Prec;
 template <> struct Prec<HISQ_FP64> {
@@ -77,24 +80,49 @@ template <> struct Prec<HISQ_FP32R12> {
     static constexpr int real_bytes = 4;
     static constexpr int mat_bytes = 12 * 4;
 };
+// W14: mat_bytes is the fat-link matrix, mat_bytes_w the Naik-link matrix.
+template <> struct Prec<HISQ_FP64W14> {
+    using store = double;
+    using acc = double;
+    static constexpr int real_bytes = 8;
+    static constexpr int mat_bytes = 18 * 8;
+    static constexpr int mat_bytes_w = 14 * 8;
+};
+template <> struct Prec<HISQ_FP32W14> {
+    using store = float;
+    using acc = float;
+    static constexpr int real_bytes = 4;
+    static constexpr int mat_bytes = 18 * 4;
+    static constexpr int mat_bytes_w = 14 * 4;
+};
 
-// Bytes of one stored link matrix, and the precision of the colour-vector
-// fields that go with a link precision.
+// Bytes of one stored fat-link (X) and Naik-link (W) matrix, and the
+// precision of the colour-vector fields that go with a link precision.
 __host__ __device__ constexpr int link_matrix_bytes(int prec) {
     return prec == HISQ_FP64 ? 144 : prec == HISQ_FP32 ? 72 : prec == HISQ_FP16N ? 36
-         : prec == HISQ_FP64R12 ? 96 : 48;
+         : prec == HISQ_FP64R12 ? 96 : prec == HISQ_FP32R12 ? 48 : prec == HISQ_FP64W14 ? 144 : 72;
+}
+__host__ __device__ constexpr int link_matrix_bytes_w(int prec) {
+    return prec == HISQ_FP64W14 ? 112 : prec == HISQ_FP32W14 ? 56 : link_matrix_bytes(prec);
 }
 __host__ __device__ constexpr int field_prec_of(int prec) {
-    return prec == HISQ_FP64R12 ? HISQ_FP64 : prec == HISQ_FP32R12 ? HISQ_FP32 : prec;
+    return prec == HISQ_FP64R12 || prec == HISQ_FP64W14   ? HISQ_FP64
+           : prec == HISQ_FP32R12 || prec == HISQ_FP32W14 ? HISQ_FP32
+                                                          : prec;
 }
 
-inline size_t links_bytes(const Geom &g, int mat_bytes) {
-    return (size_t)2 * 2 * 4 * (size_t)g.vh * mat_bytes;
+inline size_t links_bytes(const Geom &g, int prec) {
+    return (size_t)2 * 4 * (size_t)g.vh * (link_matrix_bytes(prec) + link_matrix_bytes_w(prec));
 }
 
-// Byte offset of the block (f, p, mu) for matrices of mat_bytes bytes.
-__host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int mat_bytes) {
-    return (size_t)((f * 2 + p) * 4 + mu) * (size_t)vh * mat_bytes;
+// Byte offset of the block (f, p, mu) for fat-link matrices of mx bytes and
+// Naik-link matrices of mw bytes (all X blocks first).
+__host__ __device__ inline size_t link_block(int f, int p, int mu, int vh, int mx, int mw) {
+    return f == 0 ? (size_t)(p * 4 + mu) * (size_t)vh * mx
+                  : (size_t)8 * vh * mx + (size_t)(p * 4 + mu) * (size_t)vh * mw;
+}
+template <int LP> __host__ __device__ inline size_t link_block(int f, int p, int mu, int vh) {
+    return link_block(f, p, mu, vh, link_matrix_bytes(LP), link_matrix_bytes_w(LP));
 }
 
 // ---------------------------------------------------------------------------

@@ -161,13 +161,13 @@ template <int NIN, typename A> struct HopBuf {
 };
 
 // tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b); row 2 of a
-// reconstruct-12 link is rebuilt here, after its loads have landed.
+// compressed link (field f) is rebuilt here, after its loads have landed.
 template <int LP, int NIN, typename A>
 __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, A sg, int nr,
-                                          cplx<A> (&tmp)[NIN][3]) {
+                                          cplx<A> (&tmp)[NIN][3], int f) {
     HopBuf<NIN, A> b = bin;
     if constexpr (LinkIO<LP>::rebuild)
-        rebuild_row2<A>(b.m);
+        LinkIO<LP>::finish(b.m, f);
 #pragma unroll
     for (int r = 0; r < NIN; ++r) {
         if (r < nr) {
@@ -192,8 +192,8 @@ __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, 
 
 template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int vh, int ilink, const void *in,
-                                         int ipsi, int r0, int nr) {
-    LinkIO<LP>::template load<NT>(blk, vh, ilink, b.m);
+                                         int ipsi, int r0, int nr, int f) {
+    LinkIO<LP>::template load<NT>(blk, vh, ilink, b.m, f);
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
         if (r < nr)
@@ -207,7 +207,6 @@ template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
                                                  int i, const Site &s, int mu, int r0, int nr,
                                                  cplx<A> (&acc)[NIN][3]) {
-    constexpr int MB = Prec<LP>::mat_bytes;
     const int vh = g.vh;
     const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
     const int n = mu == 0 ? g.nx : mu == 1 ? g.ny : mu == 2 ? g.nz : g.nt;
@@ -222,14 +221,14 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
     zero<NIN, A>(tmp);
     const int q = 1 - p;
     HopBuf<NIN, A> b0, b1;
-    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block(0, p, mu, vh, MB), vh, i, in, n1, r0, nr);
-    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block(0, q, mu, vh, MB), vh, n2, in, n2, r0, nr);
-    hop_apply<LP, NIN, A>(b0, false, s1, nr, tmp);
-    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block(1, p, mu, vh, MB), vh, i, in, n3, r0, nr);
-    hop_apply<LP, NIN, A>(b1, true, s2, nr, tmp);
-    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block(1, q, mu, vh, MB), vh, n4, in, n4, r0, nr);
-    hop_apply<LP, NIN, A>(b0, false, s3, nr, tmp);
-    hop_apply<LP, NIN, A>(b1, true, s4, nr, tmp);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(0, p, mu, vh), vh, i, in, n1, r0, nr, 0);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(0, q, mu, vh), vh, n2, in, n2, r0, nr, 0);
+    hop_apply<LP, NIN, A>(b0, false, s1, nr, tmp, 0);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(1, p, mu, vh), vh, i, in, n3, r0, nr, 1);
+    hop_apply<LP, NIN, A>(b1, true, s2, nr, tmp, 0);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(1, q, mu, vh), vh, n4, in, n4, r0, nr, 1);
+    hop_apply<LP, NIN, A>(b0, false, s3, nr, tmp, 1);
+    hop_apply<LP, NIN, A>(b1, true, s4, nr, tmp, 1);
     const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
     const A eta = (par & 1) ? (A)-1 : (A)1;
 #pragma unroll
@@ -241,14 +240,16 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
         }
 }
 
-// Address of hop k (k = 4 mu + {0: +1, 1: -1, 2: +3, 3: -3}) of site s.
+// Address of hop k (k = 4 mu + {0: +1, 1: -1, 2: +3, 3: -3}) of site s; f:
+// the link field (0 fat, 1 Naik).
 struct HopAddr {
     const char *blk;
     int ilink, ipsi;
     bool back;
+    int f;
 };
 
-template <int MB, typename A>
+template <int LP, typename A>
 __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *links, int i, const Site &s, int k,
                                             A &sg) {
     const int mu = k >> 2, type = k & 3;
@@ -262,7 +263,8 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
     h.back = (type & 1) != 0;
     const int f = type >> 1;            // 0: fat X (one hop), 1: long W (three hops)
     const int lpar = h.back ? 1 - p : p;
-    h.blk = links + link_block(f, lpar, mu, g.vh, MB);
+    h.f = f;
+    h.blk = links + link_block<LP>(f, lpar, mu, g.vh);
     h.ilink = h.back ? nb : i;
     h.ipsi = nb;
     return h;
@@ -275,7 +277,6 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
 template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
                                             int r0, int nr, cplx<A> (&acc)[NIN][3]) {
-    constexpr int MB = Prec<LP>::mat_bytes;
     const Site s = site_coords(g, p, i);
     zero<NIN, A>(acc);
     cplx<A> tmp[NIN][3];
@@ -290,12 +291,12 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         bool bkv[3];
         auto load_link = [&](int k, int slot) {
             A sg;
-            const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
-            LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, lb[slot].m);
+            const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
+            LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, lb[slot].m, h.f);
         };
         auto load_vec = [&](int k, int slot) {
             A sg;
-            const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
+            const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
 #pragma unroll
             for (int r = 0; r < NIN; ++r)
                 if (r < nr)
@@ -318,7 +319,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     lb[cur].v[r][c] = vb[vc][r][c];
-            hop_apply<LP, NIN, A>(lb[cur], bkv[vc], sgv[vc], nr, tmp);
+            hop_apply<LP, NIN, A>(lb[cur], bkv[vc], sgv[vc], nr, tmp, (k & 3) >> 1);
             if ((k & 3) == 3) {
                 const int mu = k >> 2;
                 const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
@@ -340,8 +341,8 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
     bool back[2];
     auto load = [&](int k, int slot) {
         A sg;
-        const HopAddr h = hop_addr<MB, A>(g, p, links, i, s, k, sg);
-        LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m);
+        const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
+        LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m, h.f);
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
             if (r < nr)
@@ -355,7 +356,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         const int cur = k & 1;
         if (k + 1 < 16)
             load(k + 1, cur ^ 1);
-        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp);
+        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp, (k & 3) >> 1);
         if ((k & 3) == 3) {
             const int mu = k >> 2;
             const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);

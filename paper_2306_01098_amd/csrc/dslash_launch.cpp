@@ -10,6 +10,8 @@ hipError_t dslash_launch_f16(const DslashParams &, int, DslashShape, hipStream_t
 hipError_t dslash_launch_f16f32(const DslashParams &, int, DslashShape, hipStream_t);
 hipError_t dslash_launch_f64r12(const DslashParams &, int, DslashShape, hipStream_t);
 hipError_t dslash_launch_f32r12(const DslashParams &, int, DslashShape, hipStream_t);
+hipError_t dslash_launch_f64w14(const DslashParams &, int, DslashShape, hipStream_t);
+hipError_t dslash_launch_f32w14(const DslashParams &, int, DslashShape, hipStream_t);
 
 bool dslash_shape_supported(DslashShape s) {
     const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR;
@@ -43,6 +45,10 @@ hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, Dslas
         return dslash_launch_f64r12(prm, epi, s, st);
     if (lp == HISQ_FP32R12 && fp == HISQ_FP32)
         return dslash_launch_f32r12(prm, epi, s, st);
+    if (lp == HISQ_FP64W14 && fp == HISQ_FP64)
+        return dslash_launch_f64w14(prm, epi, s, st);
+    if (lp == HISQ_FP32W14 && fp == HISQ_FP32)
+        return dslash_launch_f32w14(prm, epi, s, st);
     return hipErrorInvalidValue;
 }
 

@@ -6,8 +6,10 @@
 
 namespace hisq {
 
+// Compressed formats (reconstruct-12, W14) check every link and synchronize
+// st to report in *bad (nullable) whether any link does not fit the format.
 hipError_t launch_pack_links(const Geom &g, int prec, const void *fat, const void *naik, void *packed,
-                             hipStream_t st);
+                             hipStream_t st, int *bad);
 hipError_t launch_unpack_links(const Geom &g, int prec, const void *packed, void *fat, void *naik,
                                hipStream_t st);
 hipError_t launch_pack_field(const Geom &g, int prec, int nrhs, const void *src, void *dst, hipStream_t st);

@@ -1,13 +1,95 @@
 // Conversion between the canonical complex128 layouts and the packed
 // parity-split structure-of-arrays layouts (one-off per gauge field / source).
+#include <mutex>
+
 #include "internal.hpp"
+
+// Raised by the pack kernel when a link does not fit a compressed format (one
+// copy per device; host code uses the address hipGetSymbolAddress returns).
+static __device__ int g_pack_bad;
 
 namespace hisq {
 
 namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_pack_mu;
+int *g_pack_bad_ptr[kMaxDevices] = {};
+}  // namespace
 
+namespace {
+
+// d[12..17] (row 2) against z conj(row 0 x row 1), all in FP64: returns the
+// squared deviation; z = (1, 0) for reconstruct-12, and for W14 the
+// least-squares factor z = <c, row 2> / <c, c>, c = conj(row 0 x row 1),
+// returned in zr, zi (0 where c = 0).
+__device__ __forceinline__ double row2_deviation(const double d[18], bool fit, double &zr, double &zi) {
+    double c[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int j = (k + 1) % 3, l = (k + 2) % 3;
+        const double ajr = d[2 * j], aji = d[2 * j + 1], alr = d[2 * l], ali = d[2 * l + 1];
+        const double bjr = d[6 + 2 * j], bji = d[6 + 2 * j + 1], blr = d[6 + 2 * l], bli = d[6 + 2 * l + 1];
+        c[2 * k] = ajr * blr - aji * bli - (alr * bjr - ali * bji);
+        c[2 * k + 1] = -(ajr * bli + aji * blr - (alr * bji + ali * bjr));
+    }
+    zr = 1.0;
+    zi = 0.0;
+    if (fit) {
+        double cc = 0.0, nr = 0.0, ni = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double cr = c[2 * k], ci = c[2 * k + 1], rr = d[12 + 2 * k], ri = d[12 + 2 * k + 1];
+            cc += cr * cr + ci * ci;
+            nr += cr * rr + ci * ri;  // conj(c) r
+            ni += cr * ri - ci * rr;
+        }
+        zr = cc > 0.0 ? nr / cc : 0.0;
+        zi = cc > 0.0 ? ni / cc : 0.0;
+    }
+    double dev = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double er = d[12 + 2 * k] - (zr * c[2 * k] - zi * c[2 * k + 1]);
+        const double ei = d[12 + 2 * k + 1] - (zr * c[2 * k + 1] + zi * c[2 * k]);
+        dev += er * er + ei * ei;
+    }
+    return dev;
+}
+
+// Stores matrix d (field f) in the format of LP.  The compressed formats
+// (reconstruct-12; W14 Naik links) also check that the stored part rebuilds
+// row 2 to tol times the Frobenius norm of the matrix, and set *bad otherwise
+// (every offending thread stores 1: no ordering needed).
 template <int LP>
-__device__ __forceinline__ void store_matrix(char *blk, int vh, int i, const double d[18]) {
+__device__ __forceinline__ void store_matrix(char *blk, int vh, int i, const double d[18], int f, double tol,
+                                             int *bad) {
+    constexpr bool r12 = LP == HISQ_FP64R12 || LP == HISQ_FP32R12;
+    constexpr bool w14 = LP == HISQ_FP64W14 || LP == HISQ_FP32W14;
+    double zr = 1.0, zi = 0.0;
+    if (r12 || (w14 && f == 1)) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 18; ++k)
+            n2 += d[k] * d[k];
+        const double dev = row2_deviation(d, w14, zr, zi);
+        if (!(dev <= tol * tol * n2) && bad)
+            *bad = 1;
+    }
+    if (w14 && f == 1) {  // rows 0 and 1, then z
+        if (LP == HISQ_FP64W14) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                reinterpret_cast<double2 *>(blk + (size_t)vh * 16 * k)[i] = make_double2(d[2 * k], d[2 * k + 1]);
+            reinterpret_cast<double2 *>(blk + (size_t)vh * 96)[i] = make_double2(zr, zi);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                reinterpret_cast<float4 *>(blk + (size_t)vh * 16 * k)[i] =
+                    make_float4((float)d[4 * k], (float)d[4 * k + 1], (float)d[4 * k + 2], (float)d[4 * k + 3]);
+            reinterpret_cast<float2 *>(blk + (size_t)vh * 48)[i] = make_float2((float)zr, (float)zi);
+        }
+        return;
+    }
     if (LP == HISQ_FP64R12) {  // rows 0 and 1 only
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -17,11 +99,11 @@ __device__ __forceinline__ void store_matrix(char *blk, int vh, int i, const dou
         for (int k = 0; k < 3; ++k)
             reinterpret_cast<float4 *>(blk + (size_t)vh * 16 * k)[i] =
                 make_float4((float)d[4 * k], (float)d[4 * k + 1], (float)d[4 * k + 2], (float)d[4 * k + 3]);
-    } else if (LP == HISQ_FP64) {
+    } else if (LP == HISQ_FP64 || LP == HISQ_FP64W14) {
 #pragma unroll
         for (int k = 0; k < 9; ++k)
             reinterpret_cast<double2 *>(blk + (size_t)vh * 16 * k)[i] = make_double2(d[2 * k], d[2 * k + 1]);
-    } else if (LP == HISQ_FP32) {
+    } else if (LP == HISQ_FP32 || LP == HISQ_FP32W14) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             reinterpret_cast<float4 *>(blk + (size_t)vh * 16 * k)[i] =
@@ -47,7 +129,7 @@ __device__ __forceinline__ void store_matrix(char *blk, int vh, int i, const dou
 // One thread per (mu, lexicographic site): both X and W of that link.
 template <int LP>
 __global__ void __launch_bounds__(256) pack_links_kernel(Geom g, const double *fat, const double *naik,
-                                                         char *packed) {
+                                                         char *packed, double tol, int *bad) {
     const int64_t V = 2 * (int64_t)g.vh;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= 4 * V)
@@ -63,25 +145,24 @@ __global__ void __launch_bounds__(256) pack_links_kernel(Geom g, const double *f
     const int t = (int)(rest / g.nz);
     const int p = (x + y + z + t) & 1;
     const int i = (int)(lex >> 1);
-    constexpr int MB = Prec<LP>::mat_bytes;
     for (int f = 0; f < 2; ++f) {
         const double *src = (f == 0 ? fat : naik) + gid * 18;
         double d[18];
 #pragma unroll
         for (int k = 0; k < 18; ++k)
             d[k] = src[k];
-        store_matrix<LP>(packed + link_block(f, p, mu, g.vh, MB), g.vh, i, d);
+        store_matrix<LP>(packed + link_block<LP>(f, p, mu, g.vh), g.vh, i, d, f, tol, bad);
     }
 }
 
 // Unpacking a reconstruct-12 link returns the rebuilt matrix (row 2 formed in
 // the storage precision, as the Dslash forms it).
 template <int LP>
-__device__ __forceinline__ void load_matrix_f64(const char *blk, int vh, int i, double d[18]) {
+__device__ __forceinline__ void load_matrix_f64(const char *blk, int vh, int i, double d[18], int f) {
     typename LinkIO<LP>::A m[18];
-    LinkIO<LP>::load(blk, vh, i, m);
+    LinkIO<LP>::load(blk, vh, i, m, f);
     if constexpr (LinkIO<LP>::rebuild)
-        rebuild_row2(m);
+        LinkIO<LP>::finish(m, f);
 #pragma unroll
     for (int k = 0; k < 18; ++k)
         d[k] = (double)m[k];
@@ -105,10 +186,9 @@ __global__ void __launch_bounds__(256) unpack_links_kernel(Geom g, const char *p
     const int t = (int)(rest / g.nz);
     const int p = (x + y + z + t) & 1;
     const int i = (int)(lex >> 1);
-    constexpr int MB = Prec<LP>::mat_bytes;
     for (int f = 0; f < 2; ++f) {
         double d[18];
-        load_matrix_f64<LP>(packed + link_block(f, p, mu, g.vh, MB), g.vh, i, d);
+        load_matrix_f64<LP>(packed + link_block<LP>(f, p, mu, g.vh), g.vh, i, d, f);
         double *dst = (f == 0 ? fat : naik) + gid * 18;
 #pragma unroll
         for (int k = 0; k < 18; ++k)
@@ -193,23 +273,61 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 }  // namespace
 
 hipError_t launch_pack_links(const Geom &g, int prec, const void *fat, const void *naik, void *packed,
-                             hipStream_t st) {
+                             hipStream_t st, int *bad) {
     const int64_t n = 8 * (int64_t)g.vh;
     const dim3 grid(blocks_for(n, 256));
     const double *f = static_cast<const double *>(fat);
     const double *w = static_cast<const double *>(naik);
     char *p = static_cast<char *>(packed);
-    if (prec == HISQ_FP64)
-        pack_links_kernel<HISQ_FP64><<<grid, 256, 0, st>>>(g, f, w, p);
-    else if (prec == HISQ_FP32)
-        pack_links_kernel<HISQ_FP32><<<grid, 256, 0, st>>>(g, f, w, p);
-    else if (prec == HISQ_FP64R12)
-        pack_links_kernel<HISQ_FP64R12><<<grid, 256, 0, st>>>(g, f, w, p);
+    const bool check = prec == HISQ_FP64R12 || prec == HISQ_FP32R12 || prec == HISQ_FP64W14 || prec == HISQ_FP32W14;
+    if (bad)
+        *bad = 0;
+    if (!check) {
+        if (prec == HISQ_FP64)
+            pack_links_kernel<HISQ_FP64><<<grid, 256, 0, st>>>(g, f, w, p, 0.0, nullptr);
+        else if (prec == HISQ_FP32)
+            pack_links_kernel<HISQ_FP32><<<grid, 256, 0, st>>>(g, f, w, p, 0.0, nullptr);
+        else
+            pack_links_kernel<HISQ_FP16N><<<grid, 256, 0, st>>>(g, f, w, p, 0.0, nullptr);
+        return hipGetLastError();
+    }
+    // the compressed formats: the kernel raises the check's flag, read back
+    // here; packs are serialized so that they do not share the flag
+    std::lock_guard<std::mutex> lk(g_pack_mu);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    if (!g_pack_bad_ptr[dev]) {
+        void *ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_pack_bad))) != hipSuccess)
+            return e;
+        g_pack_bad_ptr[dev] = static_cast<int *>(ptr);
+    }
+    int *flag = g_pack_bad_ptr[dev];
+    if ((e = launch_fill_u32(reinterpret_cast<unsigned *>(flag), 1, 0u, st)) != hipSuccess)
+        return e;
+    const double tol = prec == HISQ_FP64R12 || prec == HISQ_FP64W14 ? 1e-10 : 1e-5;
+    if (prec == HISQ_FP64R12)
+        pack_links_kernel<HISQ_FP64R12><<<grid, 256, 0, st>>>(g, f, w, p, tol, flag);
     else if (prec == HISQ_FP32R12)
-        pack_links_kernel<HISQ_FP32R12><<<grid, 256, 0, st>>>(g, f, w, p);
+        pack_links_kernel<HISQ_FP32R12><<<grid, 256, 0, st>>>(g, f, w, p, tol, flag);
+    else if (prec == HISQ_FP64W14)
+        pack_links_kernel<HISQ_FP64W14><<<grid, 256, 0, st>>>(g, f, w, p, tol, flag);
     else
-        pack_links_kernel<HISQ_FP16N><<<grid, 256, 0, st>>>(g, f, w, p);
-    return hipGetLastError();
+        pack_links_kernel<HISQ_FP32W14><<<grid, 256, 0, st>>>(g, f, w, p, tol, flag);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    int h = 0;
+    if ((e = hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return e;
+    if (bad)
+        *bad = h;
+    return hipSuccess;
 }
 
 hipError_t launch_unpack_links(const Geom &g, int prec, const void *packed, void *fat, void *naik,
@@ -227,6 +345,10 @@ hipError_t launch_unpack_links(const Geom &g, int prec, const void *packed, void
         unpack_links_kernel<HISQ_FP64R12><<<grid, 256, 0, st>>>(g, p, f, w);
     else if (prec == HISQ_FP32R12)
         unpack_links_kernel<HISQ_FP32R12><<<grid, 256, 0, st>>>(g, p, f, w);
+    else if (prec == HISQ_FP64W14)
+        unpack_links_kernel<HISQ_FP64W14><<<grid, 256, 0, st>>>(g, p, f, w);
+    else if (prec == HISQ_FP32W14)
+        unpack_links_kernel<HISQ_FP32W14><<<grid, 256, 0, st>>>(g, p, f, w);
     else
         unpack_links_kernel<HISQ_FP16N><<<grid, 256, 0, st>>>(g, p, f, w);
     return hipGetLastError();

@@ -64,7 +64,7 @@ __device__ __forceinline__ void transport(const float m[18], bool back, float sg
 }
 
 __device__ __forceinline__ const char *xblock(const char *links, int par, int mu, int vh) {
-    return links + link_block(0, par, mu, vh, Prec<HISQ_FP32>::mat_bytes);
+    return links + link_block<HISQ_FP32>(0, par, mu, vh);
 }
 
 // out_co(x) = sum_ci sum_p w[co][ci][p] (T_p in_ci)(x), one thread per site.

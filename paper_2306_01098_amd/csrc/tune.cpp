@@ -31,7 +31,7 @@ DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
         // FP16N links) four lanes per site (8^4 .. 16^3x8: 9.6-16.1 -> 9.2-9.3
         // us FP64; 16^4 FP32 12.2 -> 9.4 us), below 131072 blocks of 64
         // (24^3x6 FP64 19.4 -> 16.6 us)
-        const bool wide = lp == HISQ_FP64 || lp == HISQ_FP64R12;
+        const bool wide = lp == HISQ_FP64 || lp == HISQ_FP64R12 || lp == HISQ_FP64W14;
         if (g.vh <= (wide ? 16384 : 49152)) {
             s.variant = VAR_DIR;
             s.block = 128;
@@ -66,7 +66,7 @@ std::vector<DslashShape> candidate_shapes(const Geom &g, int nrhs, int lp) {
         for (int nin : {1, 2, 4, 8}) {
             if (nin > 1 && nin > nrhs)
                 continue;
-            if (var == VAR_SITE && (lp == HISQ_FP64 || lp == HISQ_FP64R12) && nin > 4)
+            if (var == VAR_SITE && (lp == HISQ_FP64 || lp == HISQ_FP64R12 || lp == HISQ_FP64W14) && nin > 4)
                 continue;  // exceeds the register file (spills)
             for (int block : {64, 128, 256})
                 for (int remap : {0, 1, 2})

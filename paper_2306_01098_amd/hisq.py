@@ -16,9 +16,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhisq.so")
 
-HISQ_FP64, HISQ_FP32, HISQ_FP16N, HISQ_FP64R12, HISQ_FP32R12 = 0, 1, 2, 3, 4
+HISQ_FP64, HISQ_FP32, HISQ_FP16N, HISQ_FP64R12, HISQ_FP32R12, HISQ_FP64W14, HISQ_FP32W14 = 0, 1, 2, 3, 4, 5, 6
 PRECS = {"fp64": HISQ_FP64, "fp32": HISQ_FP32, "fp16n": HISQ_FP16N, "fp64r12": HISQ_FP64R12,
-         "fp32r12": HISQ_FP32R12}
+         "fp32r12": HISQ_FP32R12, "fp64w14": HISQ_FP64W14, "fp32w14": HISQ_FP32W14}
 HISQ_MAX_RHS = 16
 # bytes of the device scratch array behind hisq_apply_m_dot_noalloc
 HISQ_NOALLOC_SCRATCH_BYTES = 4 << 20

@@ -69,7 +69,12 @@ def test_sizes(lib):
     assert h.hisq_links_bytes(lat, "fp32r12") == 2 * 4 * V * 12 * 4
     assert h.hisq_field_bytes(lat, "fp64r12", 2) == h.hisq_field_bytes(lat, "fp64", 2)
     assert h.hisq_field_bytes(lat, "fp32r12", 2) == h.hisq_field_bytes(lat, "fp32", 2)
-    assert h.hisq_links_bytes(lat, 5) == 0
+    # W14: fat links in full (18 reals), Naik links in 14
+    assert h.hisq_links_bytes(lat, "fp64w14") == 4 * V * (18 + 14) * 8
+    assert h.hisq_links_bytes(lat, "fp32w14") == 4 * V * (18 + 14) * 4
+    assert h.hisq_field_bytes(lat, "fp64w14", 2) == h.hisq_field_bytes(lat, "fp64", 2)
+    assert h.hisq_field_bytes(lat, "fp32w14", 2) == h.hisq_field_bytes(lat, "fp32", 2)
+    assert h.hisq_links_bytes(lat, 7) == 0
 
 
 def test_dslash_argument_checks(lib):
