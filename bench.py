@@ -302,7 +302,8 @@ def leg_w5(h, gen, O, torch, ntrain=256, ntest=4, epochs=12):
     wsf = h.empty_workspace(h.hisq_fcg_workspace_bytes(lat))
     ws1 = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 1, 0))
     test = gen.gaussian_half_field(gen.rng_for(5, gen.FIELD_SOURCE + 1), dims, ntest)
-    fcg, cg = [], []
+    ws64 = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp64", 1, 0))
+    fcg, cg, cg64 = [], [], []
     for j in range(ntest):
         b = h.pack_field_from_host(lat, "fp64", test[j])
         x = h.empty_field(lat, "fp64")
@@ -316,13 +317,22 @@ def leg_w5(h, gen, O, torch, ntrain=256, ntest=4, epochs=12):
         t0 = time.perf_counter()
         st, info = h.hisq_cg(lat, m, l64, l32, "fp32", 1, b, x, 1e-10, 40000, ws1)
         cg.append((time.perf_counter() - t0, info[0]["iterations"], info[0]["true_residual"], st))
-        log(f"w5: held-out {j}: FCG+PTC {fcg[-1][:2]} mixed CG {cg[-1][:2]}")
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = h.hisq_cg(lat, m, l64, None, "fp64", 1, b, x, 1e-10, 40000, ws64)
+        cg64.append((time.perf_counter() - t0, info[0]["iterations"], info[0]["true_residual"], st))
+        log(f"w5: held-out {j}: FCG+PTC {fcg[-1][:2]} mixed CG {cg[-1][:2]} FP64 CG {cg64[-1][:2]}")
     out["fcg_ptc"] = {"seconds": [round(f[0], 4) for f in fcg], "iterations": [f[1] for f in fcg],
                       "true_residual": [f[2] for f in fcg], "status": [f[3] for f in fcg]}
     out["mixed_cg"] = {"seconds": [round(c[0], 4) for c in cg], "iterations": [c[1] for c in cg],
                        "true_residual": [c[2] for c in cg], "status": [c[3] for c in cg]}
+    out["fp64_cg"] = {"seconds": [round(c[0], 4) for c in cg64], "iterations": [c[1] for c in cg64],
+                      "true_residual": [c[2] for c in cg64], "status": [c[3] for c in cg64]}
     out["iteration_ratio_cg_over_fcg"] = round(float(np.mean([c[1] for c in cg]) / np.mean([f[1] for f in fcg])), 3)
     out["time_ratio_cg_over_fcg"] = round(float(np.mean([c[0] for c in cg]) / np.mean([f[0] for f in fcg])), 3)
+    out["time_ratio_fp64_cg_over_fcg"] = round(float(np.mean([c[0] for c in cg64]) / np.mean([f[0] for f in fcg])),
+                                               3)
     return out
 
 

@@ -12,7 +12,10 @@ constexpr int FB = 256;
 
 // Block partials of <a, b> = sum conj(a) b of two FP32 even fields (FP64
 // sums): real parts in partials[0 .. nblk), imaginary in [nblk .. 2 nblk).
-__global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const void *b, double *partials) {
+__global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const void *b, double *partials,
+                                                 const int *skip) {
+    if (skip && *skip)
+        return;
     __shared__ double lds[8];
     const int i = blockIdx.x * FB + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -66,8 +69,10 @@ __global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, 
 }
 
 // One block: sums the ||r||^2 partials of xr_kernel, advances the scalars
-// and raises the flags.
-__global__ void __launch_bounds__(FB) xr_finalize_kernel(FcgScalars *s, const double *partials, int nblk) {
+// and raises the flags; sets the launch flags skip (not active) and nopend (no
+// true residual pending).
+__global__ void __launch_bounds__(FB) xr_finalize_kernel(FcgScalars *s, const double *partials, int nblk,
+                                                         int *flags) {
     __shared__ double tot;
     sum_partials_block(partials, 1, nblk, &tot);
     if (threadIdx.x != 0)
@@ -99,10 +104,56 @@ __global__ void __launch_bounds__(FB) xr_finalize_kernel(FcgScalars *s, const do
         }
     }
     *s = n;
+    flags[FCG_SKIP] = n.active ? 0 : 1;
+    flags[FCG_NOPEND] = (n.flag == FLAG_CONV || n.flag == FLAG_RELIABLE) && !n.active ? 0 : 1;
+}
+
+// The decision after the FP64 true residual of a waiting solve (its block
+// partials in trpart): done, iteration limit, breakdown, or residual
+// replacement (the recurrence goes on from the replaced r: the direction is
+// rebuilt from z = N(r) by the launches that follow, gated by norestart).
+// Every check block runs it: with nothing pending it only clears norestart.
+__global__ void __launch_bounds__(FB) fcg_restart_kernel(FcgScalars *s, const double *trpart, int nblk,
+                                                         int *flags) {
+    __shared__ double tot;
+    const bool pend = flags[FCG_NOPEND] == 0;
+    if (pend)
+        sum_partials_block(trpart, 1, nblk, &tot);
+    if (threadIdx.x != 0)
+        return;
+    if (!pend) {
+        flags[FCG_NORESTART] = 1;
+        return;
+    }
+    FcgScalars n = *s;
+    const double r2 = tot;
+    n.rtrue2 = r2;
+    int replaced = 0;
+    if (!(r2 >= 0.0 && r2 < 1.0e308)) {
+        n.flag = FLAG_BREAKDOWN;
+    } else if (r2 <= n.target2) {
+        n.flag = FLAG_DONE;
+    } else if (n.iters >= n.max_iter) {
+        n.flag = FLAG_MAXIT;
+    } else {
+        n.nrel += 1;
+        n.rho = r2;
+        n.rmax2 = r2;
+        n.flag = FLAG_RUN;
+        n.active = 1;
+        replaced = 1;
+    }
+    *s = n;
+    flags[FCG_SKIP] = n.active ? 0 : 1;
+    flags[FCG_NOPEND] = 1;
+    flags[FCG_NORESTART] = replaced ? 0 : 1;
 }
 
 // beta = <A p, z> / <p, A p>;  p = z - beta p.
-__global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, const FcgScalars *s) {
+__global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, const FcgScalars *s,
+                                               const int *skip) {
+    if (skip && *skip)
+        return;
     const FcgScalars st = *s;
     const int i = blockIdx.x * FB + threadIdx.x;
     if (!st.active || i >= vh)
@@ -122,27 +173,33 @@ __global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, c
 
 }  // namespace
 
-hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, double2 *out, hipStream_t st) {
+hipError_t launch_fcg_dot(int vh, const void *a, const void *b, double *partials, double2 *out, hipStream_t st,
+                          const int *skip) {
     const int nblk = (vh + FB - 1) / FB;
-    dot_kernel<<<nblk, FB, 0, st>>>(vh, a, b, partials);
+    dot_kernel<<<nblk, FB, 0, st>>>(vh, a, b, partials, skip);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? launch_sum_partials(partials, 2, nblk, reinterpret_cast<double *>(out), 1, nullptr, st)
+    return e == hipSuccess ? launch_sum_partials(partials, 2, nblk, reinterpret_cast<double *>(out), 1, skip, st)
                            : e;
 }
 
 hipError_t launch_fcg_xr(int vh, void *x, const void *p, const void *q, void *r, FcgScalars *s, double *partials,
-                         hipStream_t st) {
+                         int *flags, hipStream_t st) {
     const int nblk = (vh + FB - 1) / FB;
     xr_kernel<<<nblk, FB, 0, st>>>(vh, x, p, q, r, s, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    xr_finalize_kernel<<<1, FB, 0, st>>>(s, partials, nblk);
+    xr_finalize_kernel<<<1, FB, 0, st>>>(s, partials, nblk, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_fcg_p(int vh, const void *z, void *p, const FcgScalars *s, hipStream_t st) {
-    p_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, z, p, s);
+hipError_t launch_fcg_restart(int vh, FcgScalars *s, const double *trpart, int *flags, hipStream_t st) {
+    fcg_restart_kernel<<<1, FB, 0, st>>>(s, trpart, (vh + FB - 1) / FB, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_p(int vh, const void *z, void *p, const FcgScalars *s, hipStream_t st, const int *skip) {
+    p_kernel<<<(vh + FB - 1) / FB, FB, 0, st>>>(vh, z, p, s, skip);
     return hipGetLastError();
 }
 

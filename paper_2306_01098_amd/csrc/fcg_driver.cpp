@@ -2,6 +2,10 @@
 // the PTC network as preconditioner: FP32 iteration vectors and links, FP64
 // solution, FP64 inner products and FP64 reliable updates (residual
 // replacement by the FP64 true residual, the recurrence continuing from it).
+// The device takes every decision: each iteration is followed by a check
+// block whose launches are gated by flags in device memory, and chunks of
+// iterations are replayed from a HIP graph; the host reads the state once per
+// chunk.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -14,7 +18,7 @@ namespace hisq {
 
 size_t ptc_workspace(const Geom &g);
 hisq_status ptc_apply_internal(const hisq_lattice *lat, const void *links_f32, const void *weights, const void *in,
-                               void *out, void *ws, size_t ws_bytes, hipStream_t st);
+                               void *out, void *ws, size_t ws_bytes, hipStream_t st, const int *skip);
 
 namespace {
 
@@ -50,6 +54,29 @@ FcgLayout fcg_layout(const Geom &g) {
 }
 
 double fnow() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
+
+// A private non-blocking stream ordered after the caller's stream; waited
+// for and destroyed on exit.
+struct FcgStream {
+    hipStream_t own = nullptr;
+    hipEvent_t ev = nullptr;
+    hipError_t init(hipStream_t caller) {
+        hipError_t e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(ev, caller);
+        return e == hipSuccess ? hipStreamWaitEvent(own, ev, 0) : e;
+    }
+    ~FcgStream() {
+        if (own) {
+            (void)hipStreamSynchronize(own);
+            (void)hipStreamDestroy(own);
+        }
+        if (ev)
+            (void)hipEventDestroy(ev);
+    }
+};
 
 }  // namespace
 
@@ -92,23 +119,31 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
     if (ws_bytes < L.total)
         return fail(HISQ_ERR_WORKSPACE, "workspace holds %zu bytes, needs %zu", ws_bytes, L.total);
     char *W = static_cast<char *>(ws);
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    // a private stream ordered after the caller's (graphs cannot be captured
+    // on the legacy default stream)
+    FcgStream fs;
+    if (hipError_t e = fs.init(static_cast<hipStream_t>(stream)); e != hipSuccess)
+        return device_fail(e, "fcg stream");
+    hipStream_t st = fs.own;
     FcgScalars *ds = reinterpret_cast<FcgScalars *>(W + L.state);
-    unsigned *flags = reinterpret_cast<unsigned *>(W + L.flags);
+    int *flags = reinterpret_cast<int *>(W + L.flags);
     double *scal = reinterpret_cast<double *>(W + L.scal);
     double *partials = reinterpret_cast<double *>(W + L.partials);
     void *r = W + L.r, *p = W + L.p, *q = W + L.q, *t = W + L.t, *z = W + L.z, *ax = W + L.ax, *t64 = W + L.t64;
     const DslashShape sh64 = pick_shape(ctx, g, HISQ_FP64, HISQ_FP64, 1);
     const DslashShape sh32 = pick_shape(ctx, g, HISQ_FP32, HISQ_FP32, 1);
     const double m2 = mass * mass;
+    const int *f_skip = flags + FCG_SKIP, *f_nopend = flags + FCG_NOPEND, *f_norestart = flags + FCG_NORESTART;
     auto dev = [](hipError_t e, const char *w) { return e == hipSuccess ? HISQ_OK : device_fail(e, w); };
 
-    // rtrue2 = ||b - M x||^2, r = b - M x (FP32 copy)
-    auto true_residual = [&](double *rtrue2) -> hisq_status {
+    // r = b - M x in FP64 (FP32 copy in r) and the block partials of its
+    // norm; the launches do nothing while *gate != 0 (gate nullable)
+    auto residual_launches = [&](const int *gate) -> hipError_t {
         DslashParams prm{};
         prm.g = g;
         prm.nrhs = 1;
         prm.links = static_cast<const char *>(links_f64);
+        prm.skip = gate;
         prm.out_parity = 1;
         prm.in = x;
         prm.out = t64;
@@ -122,60 +157,71 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
             prm.ay = m2;
             e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, sh64, st);
         }
-        if (e == hipSuccess)
-            e = launch_residual(g.vh, HISQ_FP32, b, ax, r, partials, scal + 0, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(rtrue2, scal + 0, sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        return dev(e, "fcg true residual");
+        return e == hipSuccess ? launch_residual_parts(g.vh, HISQ_FP32, b, ax, r, partials, gate, st) : e;
     };
-    auto precondition = [&]() -> hisq_status {  // z = N(r)
-        return ptc_apply_internal(lat, links_f32, weights, r, z, W + L.ptc, L.total - L.ptc, st);
+    auto precondition = [&](const int *gate) -> hisq_status {  // z = N(r)
+        return ptc_apply_internal(lat, links_f32, weights, r, z, W + L.ptc, L.total - L.ptc, st, gate);
     };
 
-    hipError_t e = launch_fill_u32(flags, 64, 0u, st);
+    // set-up on the host: ||b||, the FP64 true residual, z = N(r), p = z
     double bnorm2 = 0.0, rtrue2 = 0.0;
-    if (e == hipSuccess)
-        e = launch_norm2(g.vh, b, partials, scal + 1, st);
+    hipError_t e = launch_norm2(g.vh, b, partials, scal + 1, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&bnorm2, scal + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = residual_launches(nullptr);
+    if (e == hipSuccess)
+        e = launch_sum_partials(partials, 1, (g.vh + 255) / 256, scal + 0, 1, nullptr, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&rtrue2, scal + 0, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
     if (e != hipSuccess)
         return device_fail(e, "fcg setup");
-    if ((s = true_residual(&rtrue2)) != HISQ_OK)
-        return s;
     FcgScalars hs{};
     hs.rho = rtrue2;
     hs.rmax2 = rtrue2;
+    hs.rtrue2 = rtrue2;
     hs.target2 = tol * tol * bnorm2;
     hs.delta2 = 0.01;  // replace r by the true residual when it fell by 10x
     hs.max_iter = max_iter;
-    int reliable = 0;
-    bool done = !(rtrue2 > hs.target2);
+    hs.flag = FLAG_DONE;
     bool broke = !std::isfinite(rtrue2) || !std::isfinite(bnorm2);
-    if (!done && !broke) {
+    if (broke)
+        hs.flag = FLAG_BREAKDOWN;
+    const bool start = !broke && rtrue2 > hs.target2;
+    if (start) {
         hs.active = 1;
         hs.flag = FLAG_RUN;
-        if ((s = precondition()) != HISQ_OK)
+        if ((s = precondition(nullptr)) != HISQ_OK)
             return s;
         e = launch_copy(g.vh, 1, HISQ_FP32, HISQ_FP32, z, p, st);
+        const int fl[3] = {0, 1, 1};  // skip, nopend, norestart
         if (e == hipSuccess)
             e = hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(flags, fl, sizeof fl, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
         if (e != hipSuccess)
             return device_fail(e, "fcg start");
     }
-    DslashParams prm{};
-    prm.g = g;
-    prm.nrhs = 1;
-    prm.links = static_cast<const char *>(links_f32);
-    while (!done && !broke) {
-        // q = M p with Re <p, q>
+
+    // One iteration, then a check block, all gated on the device:
+    //   q = M p with Re <p, q>; <p, r>; x += alpha p, r -= alpha q, flags;
+    //   z = N(r); <q, z>; p = z - beta p                   (while running)
+    //   r = b - M x in FP64 and the decision               (when flagged)
+    //   z = N(r); <q, z>; p = z - beta p                   (after a replacement)
+    auto step = [&]() -> hisq_status {
+        DslashParams prm{};
+        prm.g = g;
+        prm.nrhs = 1;
+        prm.links = static_cast<const char *>(links_f32);
+        prm.skip = f_skip;
         prm.out_parity = 1;
         prm.in = p;
         prm.out = t;
-        prm.y = nullptr;
-        prm.partials = nullptr;
-        e = launch_dslash(prm, HISQ_FP32, HISQ_FP32, EPI_PLAIN, sh32, st);
+        hipError_t e2 = launch_dslash(prm, HISQ_FP32, HISQ_FP32, EPI_PLAIN, sh32, st);
         DslashParams pd = prm;
         pd.out_parity = 0;
         pd.in = t;
@@ -186,61 +232,92 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
         pd.partials = partials;
         pd.dot_out = &ds->pq;
         pd.dot_stride = 1;
-        if (e == hipSuccess) e = launch_dslash(pd, HISQ_FP32, HISQ_FP32, EPI_AXPY_DOT, sh32, st);
-        if (e == hipSuccess) e = launch_fcg_dot(g.vh, p, r, partials, &ds->pr, st);
-        if (e == hipSuccess) e = launch_fcg_xr(g.vh, x, p, q, r, ds, partials, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess)
-            return device_fail(e, "fcg iteration");
-        if (!hs.active) {
-            if (hs.flag == FLAG_BREAKDOWN) {
-                broke = true;
-                break;
-            }
-            if (hs.flag == FLAG_MAXIT)
-                break;
-            // CONV or RELIABLE: FP64 true residual, then finish or go on
-            if ((s = true_residual(&rtrue2)) != HISQ_OK)
-                return s;
-            if (!std::isfinite(rtrue2)) {
-                broke = true;
-                break;
-            }
-            if (rtrue2 <= hs.target2) {
-                done = true;
-                break;
-            }
-            if (hs.iters >= max_iter)
-                break;
-            // residual replacement: r now holds the FP64 b - A x; the
-            // recurrence goes on from it (q and <p, A p> of this iteration
-            // are kept), as in reliable-update CG
-            ++reliable;
-            hs.rho = rtrue2;
-            hs.rmax2 = rtrue2;
-            hs.active = 1;
-            hs.flag = FLAG_RUN;
-            e = hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, st);
-            if (e != hipSuccess)
-                return device_fail(e, "fcg replacement");
+        if (e2 == hipSuccess) e2 = launch_dslash(pd, HISQ_FP32, HISQ_FP32, EPI_AXPY_DOT, sh32, st);
+        if (e2 == hipSuccess) e2 = launch_fcg_dot(g.vh, p, r, partials, &ds->pr, st, f_skip);
+        if (e2 == hipSuccess) e2 = launch_fcg_xr(g.vh, x, p, q, r, ds, partials, flags, st);
+        if (e2 != hipSuccess)
+            return dev(e2, "fcg iteration");
+        hisq_status s2 = precondition(f_skip);
+        if (s2 != HISQ_OK)
+            return s2;
+        e2 = launch_fcg_dot(g.vh, q, z, partials, &ds->qz, st, f_skip);
+        if (e2 == hipSuccess) e2 = launch_fcg_p(g.vh, z, p, ds, st, f_skip);
+        if (e2 == hipSuccess) e2 = residual_launches(f_nopend);
+        if (e2 == hipSuccess) e2 = launch_fcg_restart(g.vh, ds, partials, flags, st);
+        if (e2 != hipSuccess)
+            return dev(e2, "fcg check");
+        if ((s2 = precondition(f_norestart)) != HISQ_OK)
+            return s2;
+        e2 = launch_fcg_dot(g.vh, q, z, partials, &ds->qz, st, f_norestart);
+        if (e2 == hipSuccess) e2 = launch_fcg_p(g.vh, z, p, ds, st, f_norestart);
+        return dev(e2, "fcg direction");
+    };
+
+    // chunks of iterations captured once in a graph and replayed; the host
+    // reads the state after each chunk
+    const int chunk = 8;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipGraph_t *g;
+        hipGraphExec_t *x;
+        ~GraphGuard() {
+            if (*x) (void)hipGraphExecDestroy(*x);
+            if (*g) (void)hipGraphDestroy(*g);
         }
-        // z = N(r); p = z - (<q, z> / <p, q>) p
-        if ((s = precondition()) != HISQ_OK)
-            return s;
-        e = launch_fcg_dot(g.vh, q, z, partials, &ds->qz, st);
-        if (e == hipSuccess) e = launch_fcg_p(g.vh, z, p, ds, st);
-        if (e != hipSuccess)
-            return device_fail(e, "fcg direction");
+    } gg{&graph, &exec};
+    if (start) {
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hisq_status ls = HISQ_OK;
+            for (int k = 0; k < chunk && ls == HISQ_OK; ++k)
+                ls = step();
+            e = hipStreamEndCapture(st, &graph);
+            if (ls == HISQ_OK && e == hipSuccess)
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ls != HISQ_OK || e != hipSuccess)
+                exec = nullptr;
+        }
+        (void)hipGetLastError();
     }
-    if (!done && !broke) {
-        if ((s = true_residual(&rtrue2)) != HISQ_OK)
-            return s;
+    const long max_chunks = (long)max_iter / chunk + 4;
+    for (long c = 0; start && c < max_chunks; ++c) {
+        if (exec) {
+            e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess)
+                return device_fail(e, "fcg chunk");
+        } else {
+            for (int k = 0; k < chunk; ++k)
+                if ((s = step()) != HISQ_OK)
+                    return s;
+        }
+        e = hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "fcg state");
+        if (!hs.active && (hs.flag == FLAG_DONE || hs.flag == FLAG_MAXIT || hs.flag == FLAG_BREAKDOWN))
+            break;
+    }
+    broke = broke || hs.flag == FLAG_BREAKDOWN;
+    bool done = hs.flag == FLAG_DONE;
+    if (hs.flag == FLAG_DONE || hs.flag == FLAG_BREAKDOWN) {
+        rtrue2 = hs.rtrue2;
+    } else {  // stopped on the iteration limit: the true residual of the last iterate
+        e = residual_launches(nullptr);
+        if (e == hipSuccess)
+            e = launch_sum_partials(partials, 1, (g.vh + 255) / 256, scal + 0, 1, nullptr, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&rtrue2, scal + 0, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return device_fail(e, "fcg final residual");
         done = std::isfinite(rtrue2) && rtrue2 <= hs.target2;
     }
     if (info) {
         info->iterations = hs.iters;
-        info->reliable_updates = reliable;
+        info->reliable_updates = hs.nrel;
         info->true_residual = bnorm2 > 0 ? std::sqrt(rtrue2 / bnorm2) : std::sqrt(rtrue2);
         info->seconds = fnow() - t0;
         info->shared_iterations = 0;

@@ -68,11 +68,18 @@ __device__ __forceinline__ const char *xblock(const char *links, int par, int mu
 }
 
 // out_co(x) = sum_ci sum_p w[co][ci][p] (T_p in_ci)(x), one thread per site.
-template <int CIN, int COUT>
+// IN_EVEN: the input is zero on the odd sites (the first layer), so the paths
+// that read odd sites are left out (an even site keeps the identity path, an
+// odd site the eight hops).  OUT_EVEN: only the even output sites are formed
+// (the last layer, whose odd sites nothing reads).  The launch does nothing
+// while skip (nullable) points to a nonzero value.
+template <int CIN, int COUT, bool IN_EVEN, bool OUT_EVEN>
 __global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links, const float2 *w, const void *in,
-                                                       void *out) {
+                                                       void *out, const int *skip) {
+    if (skip && *skip)
+        return;
     const int gid = blockIdx.x * PB + threadIdx.x;
-    if (gid >= 2 * g.vh)
+    if (gid >= (OUT_EVEN ? 1 : 2) * g.vh)
         return;
     const int par = gid >= g.vh;
     const int i = gid - par * g.vh;
@@ -86,6 +93,8 @@ __global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links
 #pragma unroll
     for (int p = 0; p < PTC_PATHS; ++p) {
         const Hop h = path_hop(g, s, par, i, p);
+        if (IN_EVEN && h.par == 1)
+            continue;
         float m[18];
         if (p > 0)
             LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
@@ -114,11 +123,14 @@ __global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links
 }
 
 // g_in_ci(x) = sum_p T_p^+ (sum_co conj(w[co][ci][p]) g_co)(x); T_{+mu}^+ = T_{-mu}.
-template <int CIN, int COUT>
+// GOUT_EVEN: g_out is zero on the odd sites (the last layer), so the paths
+// that read odd sites are left out; OUT_EVEN: only the even sites of g_in are
+// formed (the first layer, whose input gradient is read on the even sites).
+template <int CIN, int COUT, bool GOUT_EVEN, bool OUT_EVEN>
 __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *links, const float2 *w,
                                                           const void *gout, void *gin) {
     const int gid = blockIdx.x * PB + threadIdx.x;
-    if (gid >= 2 * g.vh)
+    if (gid >= (OUT_EVEN ? 1 : 2) * g.vh)
         return;
     const int par = gid >= g.vh;
     const int i = gid - par * g.vh;
@@ -134,6 +146,8 @@ __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *li
         // adjoint of path p is the opposite hop
         const int padj = p == 0 ? 0 : (((p - 1) & 1) == 0 ? p + 1 : p - 1);
         const Hop h = path_hop(g, s, par, i, padj);
+        if (GOUT_EVEN && h.par == 1)
+            continue;
         float m[18];
         if (p > 0)
             LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
@@ -164,17 +178,20 @@ __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *li
 // Block partials of dL/dw[co][ci][p] = sum_x <(T_p in_ci)(x), g_co(x)>, one
 // thread per site for all (ci, p) pairs: g_out of the site and each path's
 // link are loaded once and reused by every input channel.  Each wave sums
-// its 2 COUT values of a pair (halving exchanges) into LDS without a block
-// barrier; at the end the block adds the waves in order (deterministic) into
+// its 2 COUT values of a pair (halving exchanges, in FP32: 64 products of
+// FP32 values) into LDS as FP64 without a block barrier; at the end the block
+// adds the waves in order (deterministic, FP64) into
 // partials[(pair * 2 COUT + k) * gridDim.x + blockIdx.x], pair = ci * 9 + p.
-template <int CIN, int COUT>
+// IN_EVEN: the input is zero on odd sites (paths reading them contribute 0);
+// GOUT_EVEN: g_out is zero on odd sites, so only the even sites are summed.
+template <int CIN, int COUT, bool IN_EVEN, bool GOUT_EVEN>
 __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *links, const void *in,
                                                          const void *gout, double *partials) {
     constexpr int NV = 2 * COUT;
     constexpr int NPAIR = CIN * PTC_PATHS;
     __shared__ double lds[(PB / 64) * NPAIR * NV];  // per wave, per pair, NV totals
     const int gid = blockIdx.x * PB + threadIdx.x;
-    const bool valid = gid < 2 * g.vh;
+    const bool valid = gid < (GOUT_EVEN ? 1 : 2) * g.vh;
     const int par = valid && gid >= g.vh;
     const int i = valid ? gid - par * g.vh : 0;
     const Site s = site_coords(g, par, i);
@@ -192,15 +209,16 @@ __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *lin
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int p = 0; p < PTC_PATHS; ++p) {
         const Hop h = path_hop(g, s, par, i, p);
+        const bool use = valid && !(IN_EVEN && h.par == 1);
         float m[18];
-        if (p > 0 && valid)
+        if (p > 0 && use)
             LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
         for (int ci = 0; ci < CIN; ++ci) {
-            double acc[NV];
+            float acc[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                acc[k] = 0.0;
-            if (valid) {
+                acc[k] = 0.f;
+            if (use) {
                 cplx<float> v[3], t[3];
                 FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
                 if (p > 0) {
@@ -219,13 +237,13 @@ __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *lin
                         re = fmaf(t[a].re, gv[co][a].re, fmaf(t[a].im, gv[co][a].im, re));
                         im = fmaf(t[a].re, gv[co][a].im, fmaf(-t[a].im, gv[co][a].re, im));
                     }
-                    acc[2 * co] = (double)re;
-                    acc[2 * co + 1] = (double)im;
+                    acc[2 * co] = re;
+                    acc[2 * co + 1] = im;
                 }
             }
             wave_sum_multi<NV>(acc);
             if ((lane & (64 / NV - 1)) == 0)
-                lds[(wave * NPAIR + ci * PTC_PATHS + p) * NV + wave_multi_index<NV>(lane)] = acc[0];
+                lds[(wave * NPAIR + ci * PTC_PATHS + p) * NV + wave_multi_index<NV>(lane)] = (double)acc[0];
         }
     }
     // one barrier per block: the waves' totals of every pair, added in wave order
@@ -263,7 +281,9 @@ __global__ void __launch_bounds__(256) wgrad_reduce_kernel(int cin, int cout, in
 }
 
 // a0 = (in_even, 0 on odd sites), channel 0.
-__global__ void embed_kernel(int vh, const void *in_even, void *a0) {
+__global__ void embed_kernel(int vh, const void *in_even, void *a0, const int *skip) {
+    if (skip && *skip)
+        return;
     const int gid = blockIdx.x * PB + threadIdx.x;
     if (gid >= 2 * vh)
         return;
@@ -280,7 +300,9 @@ __global__ void embed_kernel(int vh, const void *in_even, void *a0) {
     FieldIO<HISQ_FP32>::template store<float>(a0, vh, par, i, v);
 }
 
-__global__ void extract_kernel(int vh, const void *a3, void *out_even) {
+__global__ void extract_kernel(int vh, const void *a3, void *out_even, const int *skip) {
+    if (skip && *skip)
+        return;
     const int i = blockIdx.x * PB + threadIdx.x;
     if (i >= vh)
         return;
@@ -390,39 +412,43 @@ inline unsigned nb(int64_t n) { return (unsigned)((n + PB - 1) / PB); }
 
 int ptc_blocks(const Geom &g) { return (int)nb(2 * (int64_t)g.vh); }
 
-hipError_t ptc_embed(const Geom &g, const void *in_even, void *a0, hipStream_t st) {
-    embed_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, in_even, a0);
+hipError_t ptc_embed(const Geom &g, const void *in_even, void *a0, hipStream_t st, const int *skip) {
+    embed_kernel<<<nb(2 * (int64_t)g.vh), PB, 0, st>>>(g.vh, in_even, a0, skip);
     return hipGetLastError();
 }
 
-hipError_t ptc_extract(const Geom &g, const void *a3, void *out_even, hipStream_t st) {
-    extract_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, a3, out_even);
+hipError_t ptc_extract(const Geom &g, const void *a3, void *out_even, hipStream_t st, const int *skip) {
+    extract_kernel<<<nb(g.vh), PB, 0, st>>>(g.vh, a3, out_even, skip);
     return hipGetLastError();
 }
 
+// The three layers of the 1 -> 8 -> 8 -> 1 network: layer 1 reads an input
+// that is zero on odd sites, layer 3's output is read on even sites only.
 hipError_t ptc_layer_fwd(const Geom &g, int cin, int cout, const char *links, const float2 *w, const void *in,
-                         void *out, hipStream_t st) {
-    const dim3 grid(nb(2 * (int64_t)g.vh));
+                         void *out, hipStream_t st, const int *skip) {
+    const dim3 full(nb(2 * (int64_t)g.vh)), even(nb(g.vh));
     if (cin == 1 && cout == PTC_CH)
-        layer_fwd_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, in, out);
+        layer_fwd_kernel<1, PTC_CH, true, false><<<full, PB, 0, st>>>(g, links, w, in, out, skip);
     else if (cin == PTC_CH && cout == PTC_CH)
-        layer_fwd_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, in, out);
+        layer_fwd_kernel<PTC_CH, PTC_CH, false, false><<<full, PB, 0, st>>>(g, links, w, in, out, skip);
     else if (cin == PTC_CH && cout == 1)
-        layer_fwd_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, w, in, out);
+        layer_fwd_kernel<PTC_CH, 1, false, true><<<even, PB, 0, st>>>(g, links, w, in, out, skip);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+// Backward through the same layers: layer 3's output gradient is zero on odd
+// sites, layer 1's input gradient is needed on even sites only.
 hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links, const float2 *w,
                             const void *g_out, void *g_in, hipStream_t st) {
-    const dim3 grid(nb(2 * (int64_t)g.vh));
+    const dim3 full(nb(2 * (int64_t)g.vh)), even(nb(g.vh));
     if (cin == PTC_CH && cout == PTC_CH)
-        layer_bwd_in_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+        layer_bwd_in_kernel<PTC_CH, PTC_CH, false, false><<<full, PB, 0, st>>>(g, links, w, g_out, g_in);
     else if (cin == PTC_CH && cout == 1)
-        layer_bwd_in_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+        layer_bwd_in_kernel<PTC_CH, 1, true, false><<<full, PB, 0, st>>>(g, links, w, g_out, g_in);
     else if (cin == 1 && cout == PTC_CH)
-        layer_bwd_in_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, w, g_out, g_in);
+        layer_bwd_in_kernel<1, PTC_CH, false, true><<<even, PB, 0, st>>>(g, links, w, g_out, g_in);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -430,15 +456,16 @@ hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links,
 
 hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, const void *in, const void *g_out,
                            double *partials, double2 *grad, hipStream_t st) {
-    const int nblk = ptc_blocks(g);
-    const dim3 grid((unsigned)nblk);
+    int nblk = ptc_blocks(g);
     if (cin == 1 && cout == PTC_CH)
-        layer_bwd_w_kernel<1, PTC_CH><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
+        layer_bwd_w_kernel<1, PTC_CH, true, false><<<dim3((unsigned)nblk), PB, 0, st>>>(g, links, in, g_out, partials);
     else if (cin == PTC_CH && cout == PTC_CH)
-        layer_bwd_w_kernel<PTC_CH, PTC_CH><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
-    else if (cin == PTC_CH && cout == 1)
-        layer_bwd_w_kernel<PTC_CH, 1><<<grid, PB, 0, st>>>(g, links, in, g_out, partials);
-    else
+        layer_bwd_w_kernel<PTC_CH, PTC_CH, false, false>
+            <<<dim3((unsigned)nblk), PB, 0, st>>>(g, links, in, g_out, partials);
+    else if (cin == PTC_CH && cout == 1) {
+        nblk = nb(g.vh);  // the even sites only
+        layer_bwd_w_kernel<PTC_CH, 1, false, true><<<dim3((unsigned)nblk), PB, 0, st>>>(g, links, in, g_out, partials);
+    } else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

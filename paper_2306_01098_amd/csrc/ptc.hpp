@@ -23,10 +23,12 @@ constexpr int PTC_BLOCK = 256;
 // i.e. the packed FP32 half-field layout with right-hand-side index 2c + parity.
 inline size_t ptc_field_bytes(const Geom &g, int channels) { return (size_t)channels * 2 * 3 * g.vh * 8; }
 
-hipError_t ptc_embed(const Geom &g, const void *in_even, void *a0, hipStream_t st);
-hipError_t ptc_extract(const Geom &g, const void *a3, void *out_even, hipStream_t st);
+// skip (nullable): the launch does nothing while *skip != 0.
+hipError_t ptc_embed(const Geom &g, const void *in_even, void *a0, hipStream_t st, const int *skip = nullptr);
+hipError_t ptc_extract(const Geom &g, const void *a3, void *out_even, hipStream_t st, const int *skip = nullptr);
+// Layer 3's output (cout = 1) is formed on the even sites only.
 hipError_t ptc_layer_fwd(const Geom &g, int cin, int cout, const char *links, const float2 *w, const void *in,
-                         void *out, hipStream_t st);
+                         void *out, hipStream_t st, const int *skip = nullptr);
 hipError_t ptc_layer_bwd_in(const Geom &g, int cin, int cout, const char *links, const float2 *w,
                             const void *g_out, void *g_in, hipStream_t st);
 hipError_t ptc_layer_bwd_w(const Geom &g, int cin, int cout, const char *links, const void *in, const void *g_out,

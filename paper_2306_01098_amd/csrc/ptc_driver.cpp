@@ -55,16 +55,21 @@ struct Ptc {
     template <typename T> T *at(size_t o) const { return reinterpret_cast<T *>(ws + o); }
 };
 
-hipError_t forward(const Ptc &P, const float2 *w, const void *in_even, void *out_even) {
-    hipError_t e = ptc_embed(P.g, in_even, P.at<void>(P.L.a0), P.st);
+// skip (nullable): every launch does nothing while *skip != 0.
+hipError_t forward(const Ptc &P, const float2 *w, const void *in_even, void *out_even,
+                   const int *skip = nullptr) {
+    hipError_t e = ptc_embed(P.g, in_even, P.at<void>(P.L.a0), P.st, skip);
     if (e == hipSuccess)
-        e = ptc_layer_fwd(P.g, 1, PTC_CH, P.links, w + PTC_W1, P.at<void>(P.L.a0), P.at<void>(P.L.a1), P.st);
+        e = ptc_layer_fwd(P.g, 1, PTC_CH, P.links, w + PTC_W1, P.at<void>(P.L.a0), P.at<void>(P.L.a1), P.st,
+                          skip);
     if (e == hipSuccess)
-        e = ptc_layer_fwd(P.g, PTC_CH, PTC_CH, P.links, w + PTC_W2, P.at<void>(P.L.a1), P.at<void>(P.L.a2), P.st);
+        e = ptc_layer_fwd(P.g, PTC_CH, PTC_CH, P.links, w + PTC_W2, P.at<void>(P.L.a1), P.at<void>(P.L.a2), P.st,
+                          skip);
     if (e == hipSuccess)
-        e = ptc_layer_fwd(P.g, PTC_CH, 1, P.links, w + PTC_W3, P.at<void>(P.L.a2), P.at<void>(P.L.a3), P.st);
+        e = ptc_layer_fwd(P.g, PTC_CH, 1, P.links, w + PTC_W3, P.at<void>(P.L.a2), P.at<void>(P.L.a3), P.st,
+                          skip);
     if (e == hipSuccess && out_even)
-        e = ptc_extract(P.g, P.at<void>(P.L.a3), out_even, P.st);
+        e = ptc_extract(P.g, P.at<void>(P.L.a3), out_even, P.st, skip);
     return e;
 }
 
@@ -114,14 +119,15 @@ hisq_status common_checks(const hisq_lattice *lat, const void *links, const void
 
 }  // namespace
 
-// Internal entry used by the flexible CG: z = N(r) on even sites.
+// Internal entry used by the flexible CG: z = N(r) on even sites; the launches
+// do nothing while skip (nullable) points to a nonzero value.
 hisq_status ptc_apply_internal(const hisq_lattice *lat, const void *links_f32, const void *weights, const void *in,
-                               void *out, void *ws, size_t ws_bytes, hipStream_t st) {
+                               void *out, void *ws, size_t ws_bytes, hipStream_t st, const int *skip) {
     Ptc P;
     hisq_status s = common_checks(lat, links_f32, weights, ws, ws_bytes, &P, nullptr, st);
     if (s != HISQ_OK)
         return s;
-    const hipError_t e = forward(P, static_cast<const float2 *>(weights), in, out);
+    const hipError_t e = forward(P, static_cast<const float2 *>(weights), in, out, skip);
     return e == hipSuccess ? HISQ_OK : device_fail(e, "ptc forward");
 }
 

@@ -51,7 +51,7 @@ template <int NV> __device__ __forceinline__ int wave_multi_index(int lane) {
     return idx;
 }
 
-template <int NV> __device__ __forceinline__ void wave_sum_multi(double (&v)[NV]) {
+template <int NV, typename T> __device__ __forceinline__ void wave_sum_multi(T (&v)[NV]) {
     static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
     const int lane = threadIdx.x & 63;
     int o = 32;
@@ -60,8 +60,8 @@ template <int NV> __device__ __forceinline__ void wave_sum_multi(double (&v)[NV]
         const bool upper = (lane & o) != 0;
 #pragma unroll
         for (int k = 0; k < n / 2; ++k) {
-            const double give = upper ? v[k] : v[k + n / 2];
-            const double keep = upper ? v[k + n / 2] : v[k];
+            const T give = upper ? v[k] : v[k + n / 2];
+            const T keep = upper ? v[k + n / 2] : v[k];
             v[k] = keep + __shfl_xor(give, o, 64);
         }
     }
