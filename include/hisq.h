@@ -464,7 +464,15 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
 
 /* Launch shape of hisq_dslash (and of the Dslash inside the solvers).
  *   variant   0: one thread per output site; 1: four lanes per site, one per
- *             direction, combined by wavefront shuffles.
+ *             direction, combined by wavefront shuffles; 2: one thread per
+ *             site, a block per piece of 8 y-rows x N_x/2 sites at fixed
+ *             (t, z) in the z-slab order, whose x- and y-hop neighbour
+ *             vectors are first staged in LDS (block and xcd_remap are then
+ *             set by the library: 4 N_x threads, order 2; needs N_z and N_y
+ *             divisible by 8, N_x in {16, 32, 48, 64} and FP64 or FP32
+ *             fields within 64 KiB of LDS per block, else
+ *             hisq_set_dslash_shape returns HISQ_ERR_INVALID_ARG; with FP16N
+ *             fields the launch falls back to variant 0).
  *   nin       right-hand sides per thread sharing each link load (1, 2, 4, 8;
  *             the remaining right-hand sides run as further blocks: the
  *             N_inner x N_outer split of the paper's Sec. 5.1).

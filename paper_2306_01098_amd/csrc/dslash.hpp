@@ -20,7 +20,7 @@
 
 namespace hisq {
 
-enum { VAR_SITE = 0, VAR_DIR = 1 };
+enum { VAR_SITE = 0, VAR_DIR = 1, VAR_LDS = 2 };
 // EPI_PLAIN: out = D in.  EPI_AXPY: out = ad * D in + ay * y.
 // EPI_AXPY_DOT: as EPI_AXPY, and dot_out[r] = Re <y_r, out_r> (FP64 sums,
 // deterministic: block partials summed in block order by the last block).
@@ -491,6 +491,171 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
             }
         }
     }
+    }
+    if (EPI == EPI_AXPY_DOT)
+        dslash_dot_reduce<NIN>(prm, dot, bp);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged neighbours (VAR_LDS), for several right-hand sides in the banded
+// z-slab block order: a block is one piece of LDS_BAND y-rows x N_x/2 sites at
+// fixed (t, z), one thread per site.  The block first copies, for its group of
+// right-hand sides, the input rows y0 - 3 .. y0 + LDS_BAND + 2 of that (t, z)
+// (the rows every x- and y-hop of the piece reads) into LDS with coalesced
+// loads; the eight x- and y-hops then read their neighbour vectors from LDS,
+// the z- and t-hops through the caches.  Each staged vector serves up to eight
+// hops of the piece, so the vector loads issued per site fall from 16 NIN x 3
+// to 8 NIN x 3 plus (1 + 6 / LDS_BAND) NIN x 3 for the staging.
+// ---------------------------------------------------------------------------
+constexpr int LDS_BAND = 8;
+constexpr int LDS_HALO = 3;
+
+template <int FP> struct StageElem;
+template <> struct StageElem<HISQ_FP64> { using T = double2; };
+template <> struct StageElem<HISQ_FP32> { using T = float2; };
+
+// Bytes of LDS a VAR_LDS block needs for nin right-hand sides.
+__host__ __device__ inline size_t lds_stage_bytes(const Geom &g, int fp, int nin) {
+    return (size_t)nin * 3 * (LDS_BAND + 2 * LDS_HALO) * g.hx * (fp == HISQ_FP64 ? 16 : 8);
+}
+
+template <int LP, int FP, int NIN, int EPI, bool NT>
+__global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm) {
+    using A = typename Prec<LP>::acc;
+    using E = typename StageElem<FP>::T;
+    extern __shared__ char lds_raw[];
+    E *stage = reinterpret_cast<E *>(lds_raw);
+    if (prm.skip && *prm.skip)
+        return;
+    const BlockPos<NIN> bp(prm);
+    if (!columns_run(prm, bp))
+        return;
+    const Geom &g = prm.g;
+    const int p = prm.out_parity;
+    // the piece: (t, z, y-band) of the banded z-slab traversal, q = bp.sb
+    const int zw = g.nz >> 3;
+    const int q = bp.sb;
+    const int zl = q % zw;
+    int st = q / zw;
+    const int t = st % g.nt;
+    st /= g.nt;
+    const int nbands = g.ny / LDS_BAND;
+    const int bd = st % nbands, slab = st / nbands;
+    const int z = slab * zw + zl;
+    const int y0 = bd * LDS_BAND;
+    const int plane = (t * g.nz + z) * (g.ny * g.hx);  // half index of (t, z, y = 0, xh = 0)
+    const int nrow = LDS_BAND + 2 * LDS_HALO;
+    const int r0 = bp.r0, nr = bp.nr;
+    // stage rows y0 - 3 .. y0 + band + 2 (periodic in y) of the input parity:
+    // blockDim = LDS_BAND * hx threads and NIN * 3 * nrow * hx elements, so
+    // each thread copies at most PER of them; all its loads are issued
+    // before the first LDS store
+    {
+        constexpr int PER = (NIN * 3 * (LDS_BAND + 2 * LDS_HALO) + LDS_BAND - 1) / LDS_BAND;
+        const int per_rc = nrow * g.hx;
+        const int total = nr * 3 * per_rc;
+        const E *src = reinterpret_cast<const E *>(prm.in);
+        E v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + j * blockDim.x;
+            if (e < total) {
+                const int rc = e / per_rc, rem = e - rc * per_rc;
+                const int row = rem / g.hx, xh = rem - row * g.hx;
+                int gy = y0 - LDS_HALO + row;
+                gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+                v[j] = src[(size_t)(r0 * 3 + rc) * g.vh + plane + gy * g.hx + xh];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + j * blockDim.x;
+            if (e < total)
+                stage[e] = v[j];
+        }
+    }
+    __syncthreads();
+    const int ry = threadIdx.x / g.hx, xh = threadIdx.x - ry * g.hx;
+    const int y = y0 + ry;
+    const int i = plane + y * g.hx + xh;
+    Site s;
+    s.y = y;
+    s.z = z;
+    s.t = t;
+    s.x = 2 * xh + ((y + z + t + p) & 1);
+    cplx<A> acc[NIN][3], tmp[NIN][3];
+    zero<NIN, A>(acc);
+    zero<NIN, A>(tmp);
+    HopBuf<NIN, A> buf[2];
+    A sgn[2];
+    bool back[2];
+    auto load = [&](int k, int slot) {
+        A sg;
+        const HopAddr h = hop_addr<LP, A>(g, p, prm.links, i, s, k, sg);
+        LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m, h.f);
+        const int mu = k >> 2;
+        if (mu >= 2) {
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+                if (r < nr)
+                    FieldIO<FP>::template load<A>(prm.in, g.vh, r0 + r, h.ipsi, buf[slot].v[r]);
+        } else {
+            // LDS row and column of the neighbour: x-hops stay in the row,
+            // y-hops move rows (the staged rows start at y0 - 3)
+            const int type = k & 3;
+            const int step = type == 0 ? 1 : type == 1 ? -1 : type == 2 ? 3 : -3;
+            int row = ry + LDS_HALO, col = xh;
+            if (mu == 1) {
+                row += step;
+            } else {
+                int xn = s.x + step;
+                xn = xn < 0 ? xn + g.nx : (xn >= g.nx ? xn - g.nx : xn);
+                col = xn >> 1;
+            }
+#pragma unroll
+            for (int r = 0; r < NIN; ++r) {
+                if (r < nr) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const E e = stage[((r * 3 + c) * nrow + row) * g.hx + col];
+                        buf[slot].v[r][c].re = (A)e.x;
+                        buf[slot].v[r][c].im = (A)e.y;
+                    }
+                }
+            }
+        }
+        sgn[slot] = sg;
+        back[slot] = h.back;
+    };
+    load(0, 0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int cur = k & 1;
+        if (k + 1 < 16)
+            load(k + 1, cur ^ 1);
+        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp, (k & 3) >> 1);
+        if ((k & 3) == 3) {
+            const int mu = k >> 2;
+            const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+            const A eta = (par & 1) ? (A)-1 : (A)1;
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    acc[r][a].re = fma(eta, tmp[r][a].re, acc[r][a].re);
+                    acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
+                    tmp[r][a].re = tmp[r][a].im = (A)0;
+                }
+        }
+    }
+    double dot[NIN];
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        dot[r] = 0.0;
+        if (r < nr) {
+            dot[r] = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            FieldIO<FP>::template store<A>(prm.out, g.vh, r0 + r, i, acc[r]);
+        }
     }
     if (EPI == EPI_AXPY_DOT)
         dslash_dot_reduce<NIN>(prm, dot, bp);

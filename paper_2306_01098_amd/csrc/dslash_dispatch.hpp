@@ -10,6 +10,32 @@ namespace hisq {
 
 template <int LP, int FP, int NIN, int EPI>
 hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
+    if (s.variant == VAR_LDS) {
+        // one block per piece of LDS_BAND y-rows at fixed (t, z), in the
+        // banded z-slab order (dslash_shape_fits checked the geometry)
+        if constexpr (FP == HISQ_FP64 || FP == HISQ_FP32) {
+            const int threads = LDS_BAND * prm.g.hx;
+            const int nsb = prm.g.vh / threads;
+            const int nouter = (prm.nrhs + NIN - 1) / NIN;
+            DslashParams p = prm;
+            p.xcd_remap = 2;
+            p.band = LDS_BAND;
+            const size_t shm = lds_stage_bytes(prm.g, FP, NIN);
+            const bool nt = LinkIO<LP>::stream && nouter == 1;
+            if (nt)
+                dslash_lds_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream>
+                    <<<dim3((unsigned)(nsb * nouter)), threads, shm, st>>>(p);
+            else
+                dslash_lds_kernel<LP, FP, NIN, EPI, false><<<dim3((unsigned)(nsb * nouter)), threads, shm, st>>>(p);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess && EPI == EPI_AXPY_DOT && p.dot_out != nullptr)
+                e = launch_sum_partials(p.partials, p.nrhs, nsb, p.dot_out, p.dot_stride > 0 ? p.dot_stride : 1,
+                                        p.skip, st);
+            return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
     const int nsb = (prm.g.vh + sites_per_block - 1) / sites_per_block;
     const int nouter = (prm.nrhs + NIN - 1) / NIN;

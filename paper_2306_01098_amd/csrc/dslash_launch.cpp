@@ -14,16 +14,29 @@ hipError_t dslash_launch_f64w14(const DslashParams &, int, DslashShape, hipStrea
 hipError_t dslash_launch_f32w14(const DslashParams &, int, DslashShape, hipStream_t);
 
 bool dslash_shape_supported(DslashShape s) {
-    const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR;
+    const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR || s.variant == VAR_LDS;
     const bool nin_ok = s.nin == 1 || s.nin == 2 || s.nin == 4 || s.nin == 8;
-    const bool blk_ok = s.block == 64 || s.block == 128 || s.block == 256;
+    const bool blk_ok = s.block == 64 || s.block == 128 || s.block == 256 || s.variant == VAR_LDS;
     const bool remap_ok = s.xcd_remap == 0 || s.xcd_remap == 1 || s.xcd_remap == 2;
     return var_ok && nin_ok && blk_ok && remap_ok;
 }
 
-bool dslash_shape_fits(DslashShape s, const Geom &g) { return s.xcd_remap != 2 || g.nz % 8 == 0; }
+bool dslash_shape_fits(DslashShape s, const Geom &g) {
+    if (s.variant == VAR_LDS)  // whole pieces of LDS_BAND rows, full wavefronts, the staging within 64 KiB
+        return g.nz % 8 == 0 && g.ny % LDS_BAND == 0 && (LDS_BAND * g.hx) % 64 == 0 && LDS_BAND * g.hx <= 256;
+    return s.xcd_remap != 2 || g.nz % 8 == 0;
+}
+
+bool dslash_shape_fits(DslashShape s, const Geom &g, int fp) {
+    if (!dslash_shape_fits(s, g))
+        return false;
+    return s.variant != VAR_LDS ||
+           ((fp == HISQ_FP64 || fp == HISQ_FP32) && lds_stage_bytes(g, fp, s.nin) <= 65536);
+}
 
 int dslash_partial_blocks(const Geom &g, DslashShape s) {
+    if (s.variant == VAR_LDS)
+        return g.vh / (LDS_BAND * g.hx);
     const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
     return (g.vh + sites_per_block - 1) / sites_per_block;
 }
@@ -31,6 +44,8 @@ int dslash_partial_blocks(const Geom &g, DslashShape s) {
 hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape s, hipStream_t st) {
     if (!dslash_shape_supported(s))
         return hipErrorInvalidValue;
+    if (s.variant == VAR_LDS && !dslash_shape_fits(s, prm.g, fp))
+        s = DslashShape{VAR_SITE, s.nin, 64, prm.g.nz % 8 == 0 ? 2 : 1};  // geometry or format not staged
     if (!dslash_shape_fits(s, prm.g))
         s.xcd_remap = 1;  // z-slab order needs N_z divisible by 8
     if (lp == HISQ_FP64 && fp == HISQ_FP64)

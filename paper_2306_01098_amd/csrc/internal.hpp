@@ -30,8 +30,11 @@ struct DslashParams;
 hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, DslashShape shape,
                          hipStream_t st);
 bool dslash_shape_supported(DslashShape s);
-// Block order 2 (XCDs take z-slabs) needs N_z divisible by 8.
+// Block order 2 (XCDs take z-slabs) needs N_z divisible by 8; the LDS-staged
+// variant also N_y divisible by 8 and 4 N_x in {64, 128, 192, 256}, and (with
+// the field precision fp) FP64 or FP32 fields within 64 KiB of staging.
 bool dslash_shape_fits(DslashShape s, const Geom &g);
+bool dslash_shape_fits(DslashShape s, const Geom &g, int fp);
 // Blocks per right-hand side of a Dslash launch in shape s (the number of
 // EPI_AXPY_DOT partials per right-hand side).
 int dslash_partial_blocks(const Geom &g, DslashShape s);

@@ -60,8 +60,16 @@ DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     return s;
 }
 
-std::vector<DslashShape> candidate_shapes(const Geom &g, int nrhs, int lp) {
+std::vector<DslashShape> candidate_shapes(const Geom &g, int nrhs, int lp, int fp) {
     std::vector<DslashShape> out;
+    // LDS-staged neighbours: one block per piece of rows, block size fixed
+    // by N_x, z-slab order
+    for (int nin : {1, 2, 4, 8}) {
+        const DslashShape s{VAR_LDS, nin, LDS_BAND * g.hx, 2};
+        if (nin <= nrhs && dslash_shape_fits(s, g, fp) &&
+            !((lp == HISQ_FP64 || lp == HISQ_FP64R12 || lp == HISQ_FP64W14) && nin > 4))
+            out.push_back(s);
+    }
     for (int var : {VAR_SITE, VAR_DIR})
         for (int nin : {1, 2, 4, 8}) {
             if (nin > 1 && nin > nrhs)
@@ -123,7 +131,7 @@ hisq_status tune_dslash(hisq_context *ctx, const Geom &g, int lp, int fp, int nr
     DslashShape best = default_shape(g, lp, fp, nrhs);
     float best_ms = 1e30f;
     hisq_status status = HISQ_OK;
-    for (const DslashShape &s : candidate_shapes(g, nrhs, lp)) {
+    for (const DslashShape &s : candidate_shapes(g, nrhs, lp, fp)) {
         hipError_t err = hipSuccess;
         const float ms = time_shape(prm, lp, fp, s, st, 5, e0, e1, &err);
         if (err != hipSuccess) {
@@ -196,7 +204,18 @@ hisq_status hisq_set_dslash_shape(hisq_context *ctx, const hisq_lattice *lat, hi
     if (s == HISQ_OK) s = check_ptr(shape, "shape");
     if (s != HISQ_OK)
         return s;
-    const DslashShape d{shape->variant, shape->nin, shape->block, shape->xcd_remap};
+    DslashShape d{shape->variant, shape->nin, shape->block, shape->xcd_remap};
+    if (d.variant == VAR_LDS) {  // block size and order follow from the lattice
+        const Geom g = make_geom(*lat);
+        d.block = LDS_BAND * g.hx;
+        d.xcd_remap = 2;
+        const int fp = prec == HISQ_FP16N ? HISQ_FP32 : field_prec_of(prec);
+        if (!dslash_shape_fits(d, g, fp))
+            return fail(HISQ_ERR_INVALID_ARG,
+                        "the LDS-staged Dslash needs N_z and N_y divisible by 8, N_x in {16, 32, 48, 64}, FP64 or "
+                        "FP32 fields and at most 64 KiB of staging for nin = %d",
+                        d.nin);
+    }
     if (!dslash_shape_supported(d))
         return fail(HISQ_ERR_INVALID_ARG, "unsupported shape (variant %d, nin %d, block %d, remap %d)", d.variant,
                     d.nin, d.block, d.xcd_remap);

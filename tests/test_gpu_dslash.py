@@ -477,3 +477,67 @@ def test_stream_copy_is_exact(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(dst[:n], src)
     assert int(dst[n:].count_nonzero()) == 0
+
+
+# ---------------------------------------------------------------------------
+# LDS-staged neighbours (variant 2): blocks of 8 y-rows x N_x/2 sites, x- and
+# y-hop neighbour vectors read from LDS.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32r12", "fp64w14"])
+@pytest.mark.parametrize("dims,t_bc,nrhs", [((16, 8, 8, 4), -1, 3), ((32, 16, 8, 6), 1, 5)])
+@pytest.mark.parametrize("nin", [1, 2, 4])
+def test_lds_staged_dslash_matches_oracle(gpu_lib, fields, prec, dims, t_bc, nrhs, nin):
+    """Both parities, every column against the oracle on the stored formats;
+    ragged groups of right-hand sides (nrhs not a multiple of nin)."""
+    h = gpu_lib
+    w = fields(dims, t_bc, nrhs)
+    lat = h.lattice(dims, t_bc)
+    ctx = h.Context(0)
+    h.hisq_set_dslash_shape(lat, prec, nrhs, (2, nin, 64, 0), ctx)
+    got_shape = h.hisq_get_dslash_shape(lat, prec, nrhs, ctx)
+    assert got_shape[0] == 2 and got_shape[2] == 4 * dims[0] and got_shape[3] == 2
+    links = h.pack_links_from_host(lat, prec, w["fat"], w["naik"])
+    q = O.quantized_lattice(O.lattice_from(w), prec)
+    for parity in (0, 1):
+        src = w["src_o"] if parity == 0 else w["src"]
+        inp = h.pack_field_from_host(lat, prec, src)
+        out = h.empty_field(lat, prec, nrhs)
+        out.fill_(0xFF)
+        h.hisq_dslash(lat, prec, parity, links, inp, out, nrhs, ctx=ctx)
+        got = h.unpack_field_to_host(lat, prec, out, nrhs)
+        srcq = O.quantize_field(src, prec)
+        ref = np.stack([q.D_eo(s) if parity == 0 else q.D_oe(s) for s in srcq])
+        tol = 1e-13 if prec.startswith("fp64") else 2e-6
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (parity, np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("lp,fp", [("fp64", "fp64"), ("fp32", "fp32"), ("fp16n", "fp32")])
+def test_lds_staged_apply_m_dot(gpu_lib, fields, lp, fp):
+    """The epilogues (m^2 y - D x and the fused dot) of the staged variant, and
+    the FP16N-link x FP32-field pair of FP16N CG."""
+    h = gpu_lib
+    dims, t_bc, nrhs, mass = (16, 8, 8, 4), -1, 3, 0.1
+    w = fields(dims, t_bc, nrhs, "smooth")
+    lat = h.lattice(dims, t_bc)
+    ctx = h.Context(0)
+    h.hisq_set_dslash_shape(lat, lp, nrhs, (2, 2, 64, 2), ctx)
+    links = h.pack_links_from_host(lat, lp, w["fat"], w["naik"])
+    inp = h.pack_field_from_host(lat, fp, w["src"])
+    out, tmp = h.empty_field(lat, fp, nrhs), h.empty_field(lat, fp, nrhs)
+    dots = torch.full((nrhs,), float("nan"), dtype=torch.float64, device="cuda")
+    ws = h.empty_workspace(h.hisq_apply_m_dot_workspace_bytes(lat, nrhs))
+    h.hisq_apply_m_dot(lat, lp, fp, mass, links, inp, out, tmp, dots, ws, nrhs, ctx=ctx)
+    got = h.unpack_field_to_host(lat, fp, out, nrhs)
+    ref, dref = _m_dot_reference(w, lp, fp, mass, w["src"])
+    _check_m_dot(got, dots.cpu().numpy(), ref, dref, lp, ("lds", lp, fp))
+
+
+def test_lds_staged_shape_is_refused_where_it_does_not_fit(gpu_lib):
+    h = gpu_lib
+    ctx = h.Context(0)
+    for dims in ((6, 8, 8, 4), (16, 6, 8, 4), (16, 8, 6, 4), (20, 8, 8, 4)):
+        with pytest.raises(h.HisqError):
+            h.hisq_set_dslash_shape(h.lattice(dims, -1), "fp32", 4, (2, 4, 64, 2), ctx)
+    with pytest.raises(h.HisqError):   # FP64, 8 rhs per block at N_x = 64: 172 KiB of staging
+        h.hisq_set_dslash_shape(h.lattice((64, 8, 8, 4), -1), "fp64", 8, (2, 8, 64, 2), ctx)
