@@ -265,9 +265,10 @@ hisq_status hisq_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, hisq_pr
  * shape and results as hisq_apply_m_dot (bitwise: the same kernels).
  * Limit: the call needs nrhs * (block count of the launch shape) doubles of
  * partials; every call with hisq_apply_m_dot_workspace_bytes(lat, nrhs) <=
- * HISQ_NOALLOC_SCRATCH_BYTES fits (e.g. 32^4 with 16 rhs, or 64^4 with 1
- * rhs); a call whose launch shape needs more returns HISQ_ERR_WORKSPACE
- * before any launch.  Every call
+ * HISQ_NOALLOC_SCRATCH_BYTES fits (e.g. 32^4 with 4 rhs, or 48^3x12 with 3);
+ * larger calls fit when their launch shape has enough sites per block (the
+ * built-in shapes of 32^4 and 48^3x12 with 16 rhs do); a call whose shape
+ * needs more returns HISQ_ERR_WORKSPACE before any launch.  Every call
  * on one device shares that device's array: each call writes every partial
  * it reads, but calls that overlap in time on one device (concurrent streams
  * or threads) race and give wrong dot products.  Asynchronous. */
@@ -472,7 +473,9 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
  *             divisible by 8, N_x in {16, 32, 48, 64} and FP64 or FP32
  *             fields within 64 KiB of LDS per block, else
  *             hisq_set_dslash_shape returns HISQ_ERR_INVALID_ARG; with FP16N
- *             fields the launch falls back to variant 0).
+ *             fields the launch falls back to variant 0); 3: sixteen lanes
+ *             per site, lane k computing hop k alone, combined by four
+ *             butterfly shuffles (for small lattices; nin 1 or 2).
  *   nin       right-hand sides per thread sharing each link load (1, 2, 4, 8;
  *             the remaining right-hand sides run as further blocks: the
  *             N_inner x N_outer split of the paper's Sec. 5.1).

@@ -72,9 +72,9 @@ hisq_status set_device(hisq_context *ctx) {
 }
 
 size_t apply_m_dot_partials_max(const Geom &g, int nrhs) {
-    // the smallest site block of any launch shape is 16 sites (four lanes per
-    // site in blocks of 64 threads)
-    return (size_t)nrhs * (size_t)((g.vh + 15) / 16);
+    // the smallest site block of any launch shape is 4 sites (sixteen lanes
+    // per site in blocks of 64 threads)
+    return (size_t)nrhs * (size_t)((g.vh + 3) / 4);
 }
 
 hisq_status check_apply_m_dot(hisq_context *ctx, const hisq_lattice *lat, int link_prec, int field_prec, double mass,

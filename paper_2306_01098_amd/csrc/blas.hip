@@ -373,16 +373,17 @@ __device__ __forceinline__ void cgcg_decide(CgScalars &s, const double (&tot)[4]
 template <bool NT>
 __device__ __forceinline__ void cgcg_sums(const CgVecParams &prm, int j, size_t off, double (&tot)[4],
                                           double *lds) {
-    const int wave = threadIdx.x >> 6;
-    if (wave < 4) {
-        const size_t o = off + (size_t)j * prm.rr_nblk;
-        const double *slot = wave == 0   ? prm.rr_part + o
-                             : wave == 1 ? prm.rw_part + (size_t)j * prm.rw_nblk
-                             : wave == 2 ? prm.rs_part + o
-                                         : prm.ps_part + o;
-        const double v = wave_sum_slot<NT>(slot, wave == 1 ? prm.rw_nblk : prm.rr_nblk);
+    // slot k by wave k mod (waves of the block): any block of 64 .. 256 threads
+    const int nwaves = blockDim.x >> 6;
+    const size_t o = off + (size_t)j * prm.rr_nblk;
+    for (int k = threadIdx.x >> 6; k < 4; k += nwaves) {
+        const double *slot = k == 0   ? prm.rr_part + o
+                             : k == 1 ? prm.rw_part + (size_t)j * prm.rw_nblk
+                             : k == 2 ? prm.rs_part + o
+                                      : prm.ps_part + o;
+        const double v = wave_sum_slot<NT>(slot, k == 1 ? prm.rw_nblk : prm.rr_nblk);
         if ((threadIdx.x & 63) == 0)
-            lds[wave] = v;
+            lds[k] = v;
     }
     __syncthreads();
 #pragma unroll
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(BLK) cgcg_update_kernel(CgVecParams prm) {
     if (!st.go)
         return;
     __shared__ double lds[12];
-    const int i = blockIdx.x * BLK + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double part[3] = {0.0, 0.0, 0.0};
     if (i < prm.vh) {
         cplx<T> r[3], w[3], p[3], sv[3];
@@ -517,7 +518,7 @@ __global__ void __launch_bounds__(BLK) cgcg_fused_kernel(CgVecParams prm, const 
             st_out[j] = s;
         return;
     }
-    const int i = blockIdx.x * BLK + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool site = i < prm.vh;
     // the vectors are loaded before the partial sums so the two overlap
     cplx<T> r[3], w[3], p[3], sv[3];
@@ -609,7 +610,7 @@ __global__ void __launch_bounds__(BLK) residual_cols_kernel(int vh, const void *
             col_off[j] = 0;
     }
     __shared__ double lds[12];
-    const int i = blockIdx.x * BLK + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double part[3] = {0.0, 0.0, 0.0};
     const bool sp = s && p;
     if (i < vh) {
@@ -771,39 +772,49 @@ hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStre
     return hipGetLastError();
 }
 
+// Threads per block of the single-reduction CG vector kernels: 64 on small
+// lattices, which 256-thread blocks spread over too few CUs (8^4: 8 blocks
+// of 256 against 32 of 64), else 256.  The <r, r> partials of the update
+// kernel and of the residual kernel must come from blocks of the same size.
+int cg_vec_block(int vh) { return vh <= 32768 ? 64 : BLK; }
+int cg_vec_blocks(int vh) { return (vh + cg_vec_block(vh) - 1) / cg_vec_block(vh); }
+
 hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipStream_t st) {
     cgcg_finalize_kernel<<<dim3((unsigned)p.nrhs), 256, 0, st>>>(p, after_check);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const dim3 g = grid_for(p.vh, p.nrhs);
+    const int b = cg_vec_block(p.vh);
+    const dim3 g((unsigned)cg_vec_blocks(p.vh), (unsigned)p.nrhs);
     if (fp == HISQ_FP64)
-        cgcg_update_kernel<HISQ_FP64><<<g, BLK, 0, st>>>(p);
+        cgcg_update_kernel<HISQ_FP64><<<g, b, 0, st>>>(p);
     else
-        cgcg_update_kernel<HISQ_FP32><<<g, BLK, 0, st>>>(p);
+        cgcg_update_kernel<HISQ_FP32><<<g, b, 0, st>>>(p);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
                                 const int *tr_skip, const void *s, const void *p, double *spart, double *ppart,
                                 int *skip, int *col_off, hipStream_t st) {
-    const dim3 g = grid_for(vh, ncol);
+    const int bs = cg_vec_block(vh);
+    const dim3 g((unsigned)cg_vec_blocks(vh), (unsigned)ncol);
     if (fp == HISQ_FP64)
         residual_cols_kernel<HISQ_FP64>
-            <<<g, BLK, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+            <<<g, bs, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
     else
         residual_cols_kernel<HISQ_FP32>
-            <<<g, BLK, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+            <<<g, bs, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
     return hipGetLastError();
 }
 
 hipError_t launch_cgcg_fused(const CgVecParams &p, int fp, const CgScalars *st_in, CgScalars *st_out, int *col_off,
                              int after_check, int in_buf, hipStream_t st) {
-    const dim3 g = grid_for(p.vh, p.nrhs);
+    const int b = cg_vec_block(p.vh);
+    const dim3 g((unsigned)cg_vec_blocks(p.vh), (unsigned)p.nrhs);
     if (fp == HISQ_FP64)
-        cgcg_fused_kernel<HISQ_FP64><<<g, BLK, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
+        cgcg_fused_kernel<HISQ_FP64><<<g, b, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
     else
-        cgcg_fused_kernel<HISQ_FP32><<<g, BLK, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
+        cgcg_fused_kernel<HISQ_FP32><<<g, b, 0, st>>>(p, st_in, st_out, col_off, after_check, in_buf);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct Layout {
 Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     Layout L;
     L.fs = field_prec_of(inner) == HISQ_FP64 ? HISQ_FP64 : HISQ_FP32;
-    L.nblk_max = std::max(g.vh / 16 + 1, blas_blocks(g.vh));
+    L.nblk_max = std::max(g.vh / 4 + 1, blas_blocks(g.vh));  // a Dslash site block holds >= 4 sites
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -63,7 +63,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     // <p, A p> partials (two-reduction CG) or Re <r, A r> partials (single-reduction CG)
     L.dpart = take(sizeof(double) * (size_t)std::max(ncol, 1) * L.nblk_max);
     // single-reduction CG: two sets each of the <r, r>, Re <r, s> and <p, s> partials
-    L.part_set = (size_t)std::max(ncol, 1) * blas_blocks(g.vh);
+    L.part_set = (size_t)std::max(ncol, 1) * cg_vec_blocks(g.vh);
     L.rr = take(sizeof(double) * 2 * L.part_set);
     L.rspart = take(sizeof(double) * 2 * L.part_set);
     L.pspart = take(sizeof(double) * 2 * L.part_set);
@@ -377,7 +377,7 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     char *rs = S.at<char>(L.r);
     const size_t cs = S.fs_col();
     S.shape_in = pick_shape(S.ctx, g, S.lp_in, L.fs, nrhs);
-    const int nb = blas_blocks(g.vh);
+    const int nb = cg_vec_blocks(g.vh);  // <r, r> partials per column
     double *rr = S.at<double>(L.rr);
     bool breakdown = false;
     for (int j = 0; j < nrhs; ++j) {

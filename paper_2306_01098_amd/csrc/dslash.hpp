@@ -20,7 +20,7 @@
 
 namespace hisq {
 
-enum { VAR_SITE = 0, VAR_DIR = 1, VAR_LDS = 2 };
+enum { VAR_SITE = 0, VAR_DIR = 1, VAR_LDS = 2, VAR_HOP = 3 };
 // EPI_PLAIN: out = D in.  EPI_AXPY: out = ad * D in + ay * y.
 // EPI_AXPY_DOT: as EPI_AXPY, and dot_out[r] = Re <y_r, out_r> (FP64 sums,
 // deterministic: block partials summed in block order by the last block).
@@ -375,6 +375,26 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
 
 // out = ad * acc + ay * y  (EPI_AXPY*) for right-hand side r at site i;
 // returns Re <y, out> in FP64 (products of the stored-precision values).
+// The same with y of the site already loaded (yv; ignored for EPI_PLAIN).
+template <int EPI, typename A>
+__device__ __forceinline__ double epilogue_y(const DslashParams &prm, int r, const cplx<A> (&yv)[3],
+                                             cplx<A> (&v)[3]) {
+    double dot = 0.0;
+    if (EPI != EPI_PLAIN) {
+        const A ad = (A)prm.ad, ay = (A)(prm.ay_per_rhs ? prm.ay_rhs[r] : prm.ay);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a].re = fma(ad, v[a].re, ay * yv[a].re);
+            v[a].im = fma(ad, v[a].im, ay * yv[a].im);
+            if (EPI == EPI_AXPY_DOT) {
+                dot = fma((double)yv[a].re, (double)v[a].re, dot);
+                dot = fma((double)yv[a].im, (double)v[a].im, dot);
+            }
+        }
+    }
+    return dot;
+}
+
 template <int FP, int EPI, typename A>
 __device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i, cplx<A> (&v)[3]) {
     double dot = 0.0;
@@ -461,6 +481,14 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
         dot[r] = 0.0;
     if (valid) {
     const Site s = site_coords(prm.g, prm.out_parity, i);
+    // y of the epilogue is loaded with the first hops, not after them
+    cplx<A> yv[NIN][3];
+    if (EPI != EPI_PLAIN) {
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r0 + r, i, yv[r]);
+    }
     cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
     dslash_direction<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, r0, nr, acc);
@@ -477,7 +505,7 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
 #pragma unroll
     for (int r = 0; r < NIN; ++r) {
         if (r < nr) {
-            const double d = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
+            const double d = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
             dot[r] = mu == 0 ? d : 0.0;  // one lane of the quad counts the site
             if constexpr (FP == HISQ_FP16N) {
                 if (mu == 0)  // one 16-byte record holds the whole site
@@ -491,6 +519,90 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
             }
         }
     }
+    }
+    if (EPI == EPI_AXPY_DOT)
+        dslash_dot_reduce<NIN>(prm, dot, bp);
+}
+
+// Sixteen lanes per output site (VAR_HOP), lane k computing hop k alone (its
+// link and neighbour vectors: one round of loads), the sixteen partial
+// results combined by four butterfly shuffles within the group.  For lattices
+// too small to fill the GPU with one thread or four lanes per site, where each
+// launch is bound by the latency of its chain of loads.  NIN <= 2.
+template <int LP, int FP, int NIN, int EPI, bool NT>
+__global__ void __launch_bounds__(256) dslash_hop_kernel(const DslashParams prm) {
+    using A = typename Prec<LP>::acc;
+    if (prm.skip && *prm.skip)
+        return;
+    const BlockPos<NIN> bp(prm);
+    if (!columns_run(prm, bp))
+        return;
+    const int k = threadIdx.x & 15;
+    const int i = bp.site(prm, bp.sb * (blockDim.x >> 4) + (threadIdx.x >> 4));
+    // a site's sixteen lanes share validity, so whole groups drop out together
+    const bool valid = i < prm.g.vh;
+    if (EPI != EPI_AXPY_DOT && !valid)
+        return;
+    const int r0 = bp.r0, nr = bp.nr;
+    double dot[NIN];
+#pragma unroll
+    for (int r = 0; r < NIN; ++r)
+        dot[r] = 0.0;
+    if (valid) {
+        const Geom &g = prm.g;
+        const int p = prm.out_parity;
+        const Site s = site_coords(g, p, i);
+        A sg;
+        const HopAddr h = hop_addr<LP, A>(g, p, prm.links, i, s, k, sg);
+        HopBuf<NIN, A> b;
+        LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, b.m, h.f);
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                FieldIO<FP>::template load<A>(prm.in, g.vh, r0 + r, h.ipsi, b.v[r]);
+        cplx<A> yv[NIN][3];
+        if (EPI != EPI_PLAIN) {
+#pragma unroll
+            for (int r = 0; r < NIN; ++r)
+                if (r < nr)
+                    FieldIO<FP>::template load<A>(prm.y, g.vh, r0 + r, i, yv[r]);
+        }
+        cplx<A> acc[NIN][3];
+        zero<NIN, A>(acc);
+        hop_apply<LP, NIN, A>(b, h.back, sg, nr, acc, h.f);
+        const int mu = k >> 2;
+        const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+        const A eta = (par & 1) ? (A)-1 : (A)1;
+        // sum over the group: ((k ^ 1) + ...) in a fixed butterfly, identical in all 16 lanes
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                A re = eta * acc[r][a].re, im = eta * acc[r][a].im;
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) {
+                    re += __shfl_xor(re, o, 64);
+                    im += __shfl_xor(im, o, 64);
+                }
+                acc[r][a].re = re;
+                acc[r][a].im = im;
+            }
+#pragma unroll
+        for (int r = 0; r < NIN; ++r) {
+            if (r < nr) {
+                const double d = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
+                dot[r] = k == 0 ? d : 0.0;  // one lane of the group counts the site
+                if constexpr (FP == HISQ_FP16N) {
+                    if (k == 0)
+                        FieldIO<FP>::template store<A>(prm.out, g.vh, r0 + r, i, acc[r]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (k == c)
+                            FieldIO<FP>::template store_colour<A>(prm.out, g.vh, r0 + r, i, c, acc[r][c]);
+                }
+            }
+        }
     }
     if (EPI == EPI_AXPY_DOT)
         dslash_dot_reduce<NIN>(prm, dot, bp);

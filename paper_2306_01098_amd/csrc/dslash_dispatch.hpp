@@ -36,7 +36,7 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
             return hipErrorInvalidValue;
         }
     }
-    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
+    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.variant == VAR_HOP ? s.block / 16 : s.block;
     const int nsb = (prm.g.vh + sites_per_block - 1) / sites_per_block;
     const int nouter = (prm.nrhs + NIN - 1) / NIN;
     const dim3 grid((unsigned)(nsb * nouter));
@@ -46,7 +46,16 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     // non-temporal link loads only when each link is read once (one group of
     // right-hand sides) and the format profits (FP64, FP32)
     const bool nt = LinkIO<LP>::stream && nouter == 1;
-    if (s.variant == VAR_DIR) {
+    if (s.variant == VAR_HOP) {
+        if constexpr (NIN <= 2) {
+            if (nt)
+                dslash_hop_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream><<<grid, s.block, 0, st>>>(p);
+            else
+                dslash_hop_kernel<LP, FP, NIN, EPI, false><<<grid, s.block, 0, st>>>(p);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (s.variant == VAR_DIR) {
         if (nt)
             dslash_dir_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream><<<grid, s.block, 0, st>>>(p);
         else

@@ -14,7 +14,8 @@ hipError_t dslash_launch_f64w14(const DslashParams &, int, DslashShape, hipStrea
 hipError_t dslash_launch_f32w14(const DslashParams &, int, DslashShape, hipStream_t);
 
 bool dslash_shape_supported(DslashShape s) {
-    const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR || s.variant == VAR_LDS;
+    const bool var_ok = s.variant == VAR_SITE || s.variant == VAR_DIR || s.variant == VAR_LDS ||
+                        (s.variant == VAR_HOP && s.nin <= 2);
     const bool nin_ok = s.nin == 1 || s.nin == 2 || s.nin == 4 || s.nin == 8;
     const bool blk_ok = s.block == 64 || s.block == 128 || s.block == 256 || s.variant == VAR_LDS;
     const bool remap_ok = s.xcd_remap == 0 || s.xcd_remap == 1 || s.xcd_remap == 2;
@@ -37,7 +38,7 @@ bool dslash_shape_fits(DslashShape s, const Geom &g, int fp) {
 int dslash_partial_blocks(const Geom &g, DslashShape s) {
     if (s.variant == VAR_LDS)
         return g.vh / (LDS_BAND * g.hx);
-    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.block;
+    const int sites_per_block = s.variant == VAR_DIR ? s.block / 4 : s.variant == VAR_HOP ? s.block / 16 : s.block;
     return (g.vh + sites_per_block - 1) / sites_per_block;
 }
 

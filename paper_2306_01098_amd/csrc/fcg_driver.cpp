@@ -39,7 +39,7 @@ FcgLayout fcg_layout(const Geom &g) {
     L.state = take(sizeof(FcgScalars));
     L.flags = take(64 * sizeof(unsigned));
     L.scal = take(64 * sizeof(double));
-    L.partials = take(sizeof(double) * 2 * (size_t)(g.vh / 16 + 64));
+    L.partials = take(sizeof(double) * 2 * (size_t)(g.vh / 4 + 64));  // a Dslash site block holds >= 4 sites
     const size_t f32 = field_bytes(g, HISQ_FP32, 1), f64 = field_bytes(g, HISQ_FP64, 1);
     L.r = take(f32);
     L.p = take(f32);

@@ -45,6 +45,10 @@ namespace hisq {
 
 struct CgVecParams;
 int blas_blocks(int vh);
+// Block size and count of the single-reduction CG vector kernels (and of
+// launch_residual_cols, whose <r, r> partials they share).
+int cg_vec_block(int vh);
+int cg_vec_blocks(int vh);
 hipError_t launch_cg_xr(const CgVecParams &p, int fp, hipStream_t st);
 hipError_t launch_cg_p(const CgVecParams &p, int fp, int rhs0, int nrhs, hipStream_t st, bool restart_only = false);
 // The true-residual check after r = b - A x of the waiting columns (partials
@@ -56,9 +60,9 @@ hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStre
 hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipStream_t st);
 // r_j = b_j - ax_j for the ncol columns of packed fields b, ax (FP64) and r
 // (sloppy) whose tr_skip[j] is 0 (every column if tr_skip is NULL), with the
-// block partials of ||r_j||^2 at partials + j * blas_blocks(vh) and, if s and
-// p (sloppy, ncol columns) are not NULL, those of Re <r_j, s_j> and
-// Re <p_j, s_j> at spart / ppart + j * blas_blocks(vh); a launch that forms
+// block partials of ||r_j||^2 at partials + j * cg_vec_blocks(vh) and, if s
+// and p (sloppy, ncol columns) are not NULL, those of Re <r_j, s_j> and
+// Re <p_j, s_j> at spart / ppart + j * cg_vec_blocks(vh); a launch that forms
 // residuals clears *skip and col_off[j] of each column it forms (both
 // nullable).
 hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
