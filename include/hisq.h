@@ -31,6 +31,13 @@
  *             Sec. 4.3 ("Indexing and fields").
  *    Packed layouts are private to the library (structure of arrays split by
  *    parity, direction and matrix chunk); convert with the pack/unpack calls.
+ *    A packed field of n columns is one buffer of hisq_field_bytes(lat, prec,
+ *    n) bytes.  For HISQ_FP64 and HISQ_FP16N it is the n one-column fields
+ *    one after another; HISQ_FP32 fields of two or more columns interleave
+ *    the columns in pairs (one 16-byte record per site, colour and pair; for
+ *    odd n the last pair has an unused slot, so the field takes the bytes of
+ *    n + 1 columns), and a column of such a field is not a one-column field
+ *    at an offset.
  *  - Every call returns a hisq_status.  Nothing throws, aborts or exits across
  *    the ABI.  Arguments are validated on the host before any HIP call;
  *    hisq_last_error() returns a message for the calling thread's last error.
@@ -153,7 +160,8 @@ const char *hisq_last_error(void);
 
 /* Bytes of the packed X and W links of one lattice (both parities). */
 size_t hisq_links_bytes(const hisq_lattice *lat, hisq_prec prec);
-/* Bytes of nrhs packed colour-vector fields on one parity (V/2 sites). */
+/* Bytes of a packed colour-vector field of nrhs columns on one parity (V/2
+ * sites; HISQ_FP32 with odd nrhs >= 3: nrhs + 1 columns, see the layouts above). */
 size_t hisq_field_bytes(const hisq_lattice *lat, hisq_prec prec, int32_t nrhs);
 
 /* Pack canonical complex128 links fat_c128 (X) and naik_c128 (W), each of
@@ -438,8 +446,9 @@ hisq_status hisq_ptc_backward(hisq_context *ctx, const hisq_lattice *lat, const 
 hisq_status hisq_ptc_adam_step(hisq_context *ctx, void *w_master, void *w_f32, const void *grad, void *m, void *v,
                                int32_t step, double lr, double beta1, double beta2, double eps, void *stream);
 /* One training step on `batch` (source, solution) pairs of M_e x_i = b_i
- * (src_f32: packed FP32 sources [batch]; sol_f64: packed FP64 solutions
- * [batch], e.g. from hisq_cg).  Loss: the error of the network's
+ * (src_f32: the sources as one packed FP32 field of `batch` columns; sol_f64:
+ * the solutions as one packed FP64 field of `batch` columns, e.g. from
+ * hisq_cg).  Loss: the error of the network's
  * approximation in the energy norm that CG minimises,
  *   L = (1/B) sum_i <e_i, M_e e_i> / <x_i, b_i>,   e_i = N(b_i) - x_i,
  * with M_e applied in FP32 (mass, FP32 links); gradients by the backward pass

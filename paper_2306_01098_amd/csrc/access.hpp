@@ -222,13 +222,36 @@ template <typename A> __device__ __forceinline__ void rebuild_row2_scaled(A m[18
 }
 
 // ---------------------------------------------------------------------------
-// Colour-vector fields on one parity.
+// Colour-vector fields on one parity.  Every access names the column count n
+// of the packed field it reads (a sequence of one-column fields laid end to
+// end, such as the shifted directions of the multi-shift solver or the PTC
+// channels, is addressed with n = 1).
+//   FP64: [column][colour][site] of 16-byte {re, im}.
+//   FP32, n = 1: [colour][site] of 8-byte {re, im}.
+//   FP32, n >= 2: columns 2j and 2j + 1 share 16-byte records {re, im of
+//     column 2j, re, im of column 2j + 1}, [pair][colour][site], so that a
+//     thread holding both columns of a pair issues one 16-byte load per colour
+//     instead of two 8-byte ones; for odd n the second slot of the last pair
+//     is unused (the field takes 24 (n + 1) bytes per site), so every column
+//     of the field belongs to a pair and the first 2k columns are laid out as
+//     a 2k-column field.
+//   FP16N: one 16-byte record per site and column, [column][site].
 // ---------------------------------------------------------------------------
+
+// Index, in 8-byte {re, im} units, of colour c of site i of column r of an
+// n-column FP32 field.
+__host__ __device__ __forceinline__ size_t f32_index(int vh, int n, int r, int c, int i) {
+    if (n >= 2)
+        return (((size_t)(r >> 1) * 3 + c) * vh + i) * 2 + (r & 1);
+    return ((size_t)r * 3 + c) * vh + i;
+}
+
 template <int FP> struct FieldIO;
 
 template <> struct FieldIO<HISQ_FP64> {
     template <typename A>
-    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
+    __device__ __forceinline__ static void load(const void *f, int vh, int n, int r, int i, cplx<A> v[3]) {
+        (void)n;
         const double2 *p = reinterpret_cast<const double2 *>(f) + (size_t)r * 3 * vh + i;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -242,7 +265,8 @@ template <> struct FieldIO<HISQ_FP64> {
     // room for the neighbour vectors (32^3x8 FP64 Dslash 50.0 -> 48.8-49.2 us,
     // FP64 CG 18.55 -> 18.14 ms; FP32 stores showed no gain and stay plain).
     template <typename A>
-    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
+    __device__ __forceinline__ static void store(void *f, int vh, int n, int r, int i, const cplx<A> v[3]) {
+        (void)n;
         nt_d2 *p = reinterpret_cast<nt_d2 *>(f) + (size_t)r * 3 * vh + i;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -253,7 +277,8 @@ template <> struct FieldIO<HISQ_FP64> {
         }
     }
     template <typename A>
-    __device__ __forceinline__ static void store_colour(void *f, int vh, int r, int i, int c, cplx<A> v) {
+    __device__ __forceinline__ static void store_colour(void *f, int vh, int n, int r, int i, int c, cplx<A> v) {
+        (void)n;
         nt_d2 t;
         t.x = (double)v.re;
         t.y = (double)v.im;
@@ -263,25 +288,48 @@ template <> struct FieldIO<HISQ_FP64> {
 
 template <> struct FieldIO<HISQ_FP32> {
     template <typename A>
-    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
-        const float2 *p = reinterpret_cast<const float2 *>(f) + (size_t)r * 3 * vh + i;
+    __device__ __forceinline__ static void load(const void *f, int vh, int n, int r, int i, cplx<A> v[3]) {
+        const float2 *p = reinterpret_cast<const float2 *>(f);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float2 d = p[(size_t)c * vh];
+            const float2 d = p[f32_index(vh, n, r, c, i)];
             v[c].re = (A)d.x;
             v[c].im = (A)d.y;
         }
     }
     template <typename A>
-    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
-        float2 *p = reinterpret_cast<float2 *>(f) + (size_t)r * 3 * vh + i;
+    __device__ __forceinline__ static void store(void *f, int vh, int n, int r, int i, const cplx<A> v[3]) {
+        float2 *p = reinterpret_cast<float2 *>(f);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            p[(size_t)c * vh] = make_float2((float)v[c].re, (float)v[c].im);
+            p[f32_index(vh, n, r, c, i)] = make_float2((float)v[c].re, (float)v[c].im);
     }
     template <typename A>
-    __device__ __forceinline__ static void store_colour(void *f, int vh, int r, int i, int c, cplx<A> v) {
-        reinterpret_cast<float2 *>(f)[((size_t)r * 3 + c) * vh + i] = make_float2((float)v.re, (float)v.im);
+    __device__ __forceinline__ static void store_colour(void *f, int vh, int n, int r, int i, int c, cplx<A> v) {
+        reinterpret_cast<float2 *>(f)[f32_index(vh, n, r, c, i)] = make_float2((float)v.re, (float)v.im);
+    }
+    // Both slots of pair j (columns 2j and 2j + 1) of a multi-column field:
+    // one 16-byte access per colour.
+    template <typename A>
+    __device__ __forceinline__ static void load_pair(const void *f, int vh, int j, int i, cplx<A> v0[3],
+                                                     cplx<A> v1[3]) {
+        const float4 *p = reinterpret_cast<const float4 *>(f) + (size_t)j * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float4 d = p[(size_t)c * vh];
+            v0[c].re = (A)d.x;
+            v0[c].im = (A)d.y;
+            v1[c].re = (A)d.z;
+            v1[c].im = (A)d.w;
+        }
+    }
+    template <typename A>
+    __device__ __forceinline__ static void store_pair(void *f, int vh, int j, int i, const cplx<A> v0[3],
+                                                      const cplx<A> v1[3]) {
+        float4 *p = reinterpret_cast<float4 *>(f) + (size_t)j * 3 * vh + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            p[(size_t)c * vh] = make_float4((float)v0[c].re, (float)v0[c].im, (float)v1[c].re, (float)v1[c].im);
     }
 };
 
@@ -297,7 +345,8 @@ union F16NRecord {
 
 template <> struct FieldIO<HISQ_FP16N> {
     template <typename A>
-    __device__ __forceinline__ static void load(const void *f, int vh, int r, int i, cplx<A> v[3]) {
+    __device__ __forceinline__ static void load(const void *f, int vh, int ncol, int r, int i, cplx<A> v[3]) {
+        (void)ncol;
         F16NRecord rec;
         rec.u = reinterpret_cast<const uint4 *>(f)[(size_t)r * vh + i];
         const float n = rec.s.norm;
@@ -310,7 +359,8 @@ template <> struct FieldIO<HISQ_FP16N> {
     // Norm n = max |component| (exact in FP32); components stored as
     // binary16(v / n) with the division in FP32.
     template <typename A>
-    __device__ __forceinline__ static void store(void *f, int vh, int r, int i, const cplx<A> v[3]) {
+    __device__ __forceinline__ static void store(void *f, int vh, int ncol, int r, int i, const cplx<A> v[3]) {
+        (void)ncol;
         float x[6];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

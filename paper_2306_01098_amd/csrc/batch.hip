@@ -54,11 +54,11 @@ __global__ void __launch_bounds__(TB) batch_dslash_kernel(BatchArgs a) {
         const void *in = ROLE == ROLE_ITER_DOE ? P.p : ROLE == ROLE_ITER_DEO ? P.t : ROLE == ROLE_TRUE_DOE ? P.x : P.t64;
         void *out = ROLE == ROLE_ITER_DOE ? P.t : ROLE == ROLE_ITER_DEO ? P.q : ROLE == ROLE_TRUE_DOE ? P.t64 : P.ax;
         cplx<A> acc[1][3];
-        dslash_site<LP, FP, 1, A, true>(P.g, parity, links, in, i, 0, 1, acc);
+        dslash_site<LP, FP, 1, A, true>(P.g, parity, links, in, i, 1, 0, 1, acc);
         if (AXPY) {
             const void *y = ROLE == ROLE_ITER_DEO ? P.p : P.x;
             cplx<A> yv[3];
-            FieldIO<FP>::template load<A>(y, P.g.vh, 0, i, yv);
+            FieldIO<FP>::template load<A>(y, P.g.vh, 1, 0, i, yv);
             const A m2 = (A)P.m2;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(TB) batch_dslash_kernel(BatchArgs a) {
                 }
             }
         }
-        FieldIO<FP>::template store<A>(out, P.g.vh, 0, i, acc[0]);
+        FieldIO<FP>::template store<A>(out, P.g.vh, 1, 0, i, acc[0]);
     }
     if (!DOT)
         return;
@@ -98,10 +98,10 @@ __global__ void __launch_bounds__(TB) batch_xr_kernel(BatchArgs a) {
         const T al = (T)alpha;
         cplx<T> p[3], q[3], r[3];
         cplx<double> x[3];
-        FieldIO<FP>::template load<T>(P.p, P.g.vh, 0, i, p);
-        FieldIO<FP>::template load<T>(P.q, P.g.vh, 0, i, q);
-        FieldIO<FP>::template load<T>(P.r, P.g.vh, 0, i, r);
-        FieldIO<HISQ_FP64>::template load<double>(P.x, P.g.vh, 0, i, x);
+        FieldIO<FP>::template load<T>(P.p, P.g.vh, 1, 0, i, p);
+        FieldIO<FP>::template load<T>(P.q, P.g.vh, 1, 0, i, q);
+        FieldIO<FP>::template load<T>(P.r, P.g.vh, 1, 0, i, r);
+        FieldIO<HISQ_FP64>::template load<double>(P.x, P.g.vh, 1, 0, i, x);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             x[c].re = fma(alpha, (double)p[c].re, x[c].re);
@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(TB) batch_xr_kernel(BatchArgs a) {
             part[0] = fma((double)r[c].re, (double)r[c].re, part[0]);
             part[0] = fma((double)r[c].im, (double)r[c].im, part[0]);
         }
-        FieldIO<HISQ_FP64>::template store<double>(P.x, P.g.vh, 0, i, x);
-        FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, r);
+        FieldIO<HISQ_FP64>::template store<double>(P.x, P.g.vh, 1, 0, i, x);
+        FieldIO<FP>::template store<T>(P.r, P.g.vh, 1, 0, i, r);
     }
     __shared__ double lds[TB / 64];
     block_sum<1>(part, lds);
@@ -244,15 +244,15 @@ __global__ void __launch_bounds__(TB) batch_p_kernel(BatchArgs a) {
     if (!(RESTART ? st.restart : st.active) || i >= P.g.vh)
         return;
     cplx<T> p[3], r[3];
-    FieldIO<FP>::template load<T>(P.p, P.g.vh, 0, i, p);
-    FieldIO<FP>::template load<T>(P.r, P.g.vh, 0, i, r);
+    FieldIO<FP>::template load<T>(P.p, P.g.vh, 1, 0, i, p);
+    FieldIO<FP>::template load<T>(P.r, P.g.vh, 1, 0, i, r);
     const T b = (T)st.beta;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         p[c].re = fma(b, p[c].re, r[c].re);
         p[c].im = fma(b, p[c].im, r[c].im);
     }
-    FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, p);
+    FieldIO<FP>::template store<T>(P.p, P.g.vh, 1, 0, i, p);
 }
 
 // For masked problems: r = b - ax (sloppy copy) and block partials of
@@ -269,8 +269,8 @@ __global__ void __launch_bounds__(TB) batch_residual_kernel(BatchArgs a, int cop
     double part[1] = {0.0};
     if (a.mask[j] && i < P.g.vh) {
         cplx<double> bv[3], av[3];
-        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 0, i, bv);
-        FieldIO<HISQ_FP64>::template load<double>(P.ax, P.g.vh, 0, i, av);
+        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 1, 0, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(P.ax, P.g.vh, 1, 0, i, av);
         cplx<T> rv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -280,9 +280,9 @@ __global__ void __launch_bounds__(TB) batch_residual_kernel(BatchArgs a, int cop
             rv[c].re = (T)re;
             rv[c].im = (T)im;
         }
-        FieldIO<FP>::template store<T>(P.r, P.g.vh, 0, i, rv);
+        FieldIO<FP>::template store<T>(P.r, P.g.vh, 1, 0, i, rv);
         if (copy_p)
-            FieldIO<FP>::template store<T>(P.p, P.g.vh, 0, i, rv);
+            FieldIO<FP>::template store<T>(P.p, P.g.vh, 1, 0, i, rv);
     }
     __shared__ double lds[TB / 64];
     block_sum<1>(part, lds);
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(TB) batch_bnorm_kernel(BatchArgs a) {
     double part[1] = {0.0};
     if (i < P.g.vh) {
         cplx<double> bv[3];
-        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 0, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(P.b, P.g.vh, 1, 0, i, bv);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             part[0] = fma(bv[c].re, bv[c].re, part[0]);

@@ -48,10 +48,10 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
     cplx<T> p[3], q[3], r[3];
     cplx<double> x[3];
     if (mine) {  // issued before the <p, A p> sum so the loads overlap it
-        FieldIO<FP>::template load<T>(prm.p, prm.vh, rr, i, p);
-        FieldIO<FP>::template load<T>(prm.q, prm.vh, rr, i, q);
-        FieldIO<FP>::template load<T>(prm.r, prm.vh, rr, i, r);
-        FieldIO<HISQ_FP64>::template load<double>(prm.x[rr], prm.vh, 0, i, x);
+        FieldIO<FP>::template load<T>(prm.p, prm.vh, prm.nrhs, rr, i, p);
+        FieldIO<FP>::template load<T>(prm.q, prm.vh, prm.nrhs, rr, i, q);
+        FieldIO<FP>::template load<T>(prm.r, prm.vh, prm.nrhs, rr, i, r);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[rr], prm.vh, 1, 0, i, x);
     }
     const double pq = block_pq(prm, rr, &pq_s);
     const bool go = st.active && finite_pos(pq);
@@ -68,8 +68,8 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
             part[0] = fma((double)r[c].re, (double)r[c].re, part[0]);
             part[0] = fma((double)r[c].im, (double)r[c].im, part[0]);
         }
-        FieldIO<HISQ_FP64>::template store<double>(prm.x[rr], prm.vh, 0, i, x);
-        FieldIO<FP>::template store<T>(prm.r, prm.vh, rr, i, r);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[rr], prm.vh, 1, 0, i, x);
+        FieldIO<FP>::template store<T>(prm.r, prm.vh, prm.nrhs, rr, i, r);
         if (prm.nshift > 0) {
             // shifted solutions: alpha_k = alpha zeta_new / zeta (Jegerlehner)
             const MsGlobal ms = *prm.ms;
@@ -83,14 +83,14 @@ __global__ void __launch_bounds__(BLK) cg_xr_kernel(CgVecParams prm) {
                 const double ak = alpha * zn / sk.zeta;
                 cplx<T> pk[3];
                 cplx<double> xk[3];
-                FieldIO<FP>::template load<T>(prm.ps, prm.vh, k, i, pk);
-                FieldIO<HISQ_FP64>::template load<double>(prm.xs[k], prm.vh, 0, i, xk);
+                FieldIO<FP>::template load<T>(prm.ps, prm.vh, 1, k, i, pk);
+                FieldIO<HISQ_FP64>::template load<double>(prm.xs[k], prm.vh, 1, 0, i, xk);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     xk[c].re = fma(ak, (double)pk[c].re, xk[c].re);
                     xk[c].im = fma(ak, (double)pk[c].im, xk[c].im);
                 }
-                FieldIO<HISQ_FP64>::template store<double>(prm.xs[k], prm.vh, 0, i, xk);
+                FieldIO<HISQ_FP64>::template store<double>(prm.xs[k], prm.vh, 1, 0, i, xk);
             }
         }
     }
@@ -255,29 +255,29 @@ __global__ void __launch_bounds__(BLK) cg_p_kernel(CgVecParams prm, int rhs0, in
     if (!(restart_only ? st.restart : st.active) || i >= prm.vh)
         return;
     cplx<T> p[3], r[3];
-    FieldIO<FP>::template load<T>(prm.p, prm.vh, rr, i, p);
-    FieldIO<FP>::template load<T>(prm.r, prm.vh, rr, i, r);
+    FieldIO<FP>::template load<T>(prm.p, prm.vh, prm.nrhs, rr, i, p);
+    FieldIO<FP>::template load<T>(prm.r, prm.vh, prm.nrhs, rr, i, r);
     const T b = (T)st.beta;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         p[c].re = fma(b, p[c].re, r[c].re);
         p[c].im = fma(b, p[c].im, r[c].im);
     }
-    FieldIO<FP>::template store<T>(prm.p, prm.vh, rr, i, p);
+    FieldIO<FP>::template store<T>(prm.p, prm.vh, prm.nrhs, rr, i, p);
     if (prm.nshift > 0 && rr == 0) {
         for (int k = 0; k < prm.nshift; ++k) {
             const ShiftScalars sk = prm.sh[k];
             if (!sk.active)
                 continue;
             cplx<T> pk[3];
-            FieldIO<FP>::template load<T>(prm.ps, prm.vh, k, i, pk);
+            FieldIO<FP>::template load<T>(prm.ps, prm.vh, 1, k, i, pk);
             const T z = (T)sk.zeta, bk = (T)sk.beta;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 pk[c].re = fma(bk, pk[c].re, z * r[c].re);
                 pk[c].im = fma(bk, pk[c].im, z * r[c].im);
             }
-            FieldIO<FP>::template store<T>(prm.ps, prm.vh, k, i, pk);
+            FieldIO<FP>::template store<T>(prm.ps, prm.vh, 1, k, i, pk);
         }
     }
 }
@@ -412,8 +412,44 @@ __global__ void __launch_bounds__(256) cgcg_finalize_kernel(CgVecParams prm, int
     prm.st[j] = s;
 }
 
-// The vector step of the column blockIdx.y that the finalize kernel stepped
-// (go = 1; go = 2: fresh directions p = r, s = w):
+// Thread -> (site, column) of the single-reduction vector kernels.  One
+// column per block (PAIR = false): column col0 + blockIdx.y, one site per
+// thread.  Column pairs (PAIR = true, for FP32 fields of several columns,
+// whose columns 2j and 2j + 1 share 16-byte records): blocks of twice the
+// threads over the same sites, block row blockIdx.y taking columns
+// col0 + 2 blockIdx.y + {0, 1}; lane l of wave w serves site
+// 32 (w & 1) + (l >> 1) of the block's 64-site group w >> 1 for the column
+// l & 1, so the two lanes of a site read one whole record and the partials
+// come out bitwise as with one column per block (block_sum_pair).
+template <bool PAIR> struct VecPos {
+    int j;  // column (relative to col0)
+    int i;  // site
+    __device__ __forceinline__ VecPos() {
+        if constexpr (PAIR) {
+            const int t = threadIdx.x, w = t >> 6;
+            j = 2 * (int)blockIdx.y + (t & 1);
+            i = blockIdx.x * (blockDim.x >> 1) + (w >> 1) * 64 + (w & 1) * 32 + ((t & 63) >> 1);
+        } else {
+            j = blockIdx.y;
+            i = blockIdx.x * blockDim.x + threadIdx.x;
+        }
+    }
+    // the thread that holds the block's sums for column j
+    __device__ __forceinline__ bool leader() const { return PAIR ? threadIdx.x < 2 : threadIdx.x == 0; }
+};
+
+template <int NV, bool PAIR> __device__ __forceinline__ void vec_block_sum(double (&v)[NV], double *lds) {
+    if constexpr (PAIR)
+        block_sum_pair<NV>(v, lds);
+    else
+        block_sum<NV>(v, lds);
+}
+
+// LDS doubles of vec_block_sum for blocks of up to 2 BLK threads.
+constexpr int vec_lds(int nv, bool pair) { return pair ? (2 * BLK / 128) * 64 * nv : (BLK / 64) * nv; }
+
+// The vector step of the columns the finalize kernel stepped (go = 1; go = 2:
+// fresh directions p = r, s = w):
 //   p = r + beta p, s = w + beta s, x += alpha p (FP64 x), r -= alpha s,
 // with the block partials of <r, r>, Re <r, s> and Re <p, s> of the new
 // vectors (their stored values).
@@ -422,11 +458,12 @@ __global__ void __launch_bounds__(256) cgcg_finalize_kernel(CgVecParams prm, int
 // check block, whose residual kernel clears skip again so that the next
 // iteration decides it), nopend while none is waiting.  (No other block of
 // this launch reads them.)
-template <int FP>
-__global__ void __launch_bounds__(BLK) cgcg_update_kernel(CgVecParams prm) {
+template <int FP, bool PAIR>
+__global__ void __launch_bounds__(PAIR ? 2 * BLK : BLK) cgcg_update_kernel(CgVecParams prm) {
     using T = typename Sloppy<FP>::T;
-    const int j = blockIdx.y;
-    if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) {
+    const VecPos<PAIR> at;
+    const int j = at.j;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         int run = 0, pend = 0;
         for (int k = 0; k < prm.nrhs; ++k) {
             run |= prm.st[k].active;
@@ -436,22 +473,25 @@ __global__ void __launch_bounds__(BLK) cgcg_update_kernel(CgVecParams prm) {
         if (prm.nopend)
             *prm.nopend = pend ? 0 : 1;
     }
-    const CgScalars st = prm.st[j];
-    if (!st.go)
-        return;
-    __shared__ double lds[12];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool col = j < prm.nrhs;
+    CgScalars st{};
+    if (col)
+        st = prm.st[j];
+    if (!PAIR && !st.go)
+        return;  // the whole block belongs to column j
+    __shared__ double lds[vec_lds(3, PAIR)];
+    const int i = at.i;
     double part[3] = {0.0, 0.0, 0.0};
-    if (i < prm.vh) {
+    if (st.go && i < prm.vh) {
         cplx<T> r[3], w[3], p[3], sv[3];
         cplx<double> x[3];
-        FieldIO<FP>::template load<T>(prm.r, prm.vh, j, i, r);
-        FieldIO<FP>::template load<T>(prm.w, prm.vh, j, i, w);
-        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 0, i, x);
+        FieldIO<FP>::template load<T>(prm.r, prm.vh, prm.nrhs, j, i, r);
+        FieldIO<FP>::template load<T>(prm.w, prm.vh, prm.nrhs, j, i, w);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 1, 0, i, x);
         const bool fresh = st.go == 2;
         if (!fresh) {
-            FieldIO<FP>::template load<T>(prm.p, prm.vh, j, i, p);
-            FieldIO<FP>::template load<T>(prm.s, prm.vh, j, i, sv);
+            FieldIO<FP>::template load<T>(prm.p, prm.vh, prm.nrhs, j, i, p);
+            FieldIO<FP>::template load<T>(prm.s, prm.vh, prm.nrhs, j, i, sv);
         }
         const T b = (T)st.beta, a = (T)st.alpha;
         const double ad = st.alpha;
@@ -478,13 +518,13 @@ __global__ void __launch_bounds__(BLK) cgcg_update_kernel(CgVecParams prm) {
             part[2] = fma((double)p[c].re, sre, part[2]);
             part[2] = fma((double)p[c].im, sim, part[2]);
         }
-        FieldIO<FP>::template store<T>(prm.p, prm.vh, j, i, p);
-        FieldIO<FP>::template store<T>(prm.s, prm.vh, j, i, sv);
-        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 0, i, x);
-        FieldIO<FP>::template store<T>(prm.r, prm.vh, j, i, r);
+        FieldIO<FP>::template store<T>(prm.p, prm.vh, prm.nrhs, j, i, p);
+        FieldIO<FP>::template store<T>(prm.s, prm.vh, prm.nrhs, j, i, sv);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 1, 0, i, x);
+        FieldIO<FP>::template store<T>(prm.r, prm.vh, prm.nrhs, j, i, r);
     }
-    block_sum<3>(part, lds);
-    if (threadIdx.x == 0) {
+    vec_block_sum<3, PAIR>(part, lds);
+    if (at.leader() && st.go) {
         const size_t o = (size_t)j * gridDim.x + blockIdx.x;
         prm.rr_part[o] = part[0];
         prm.rs_part[o] = part[1];
@@ -524,11 +564,11 @@ __global__ void __launch_bounds__(BLK) cgcg_fused_kernel(CgVecParams prm, const 
     cplx<T> r[3], w[3], p[3], sv[3];
     cplx<double> x[3];
     if (site) {
-        FieldIO<FP>::template load<T>(prm.r, prm.vh, j, i, r);
-        FieldIO<FP>::template load<T>(prm.w, prm.vh, j, i, w);
-        FieldIO<FP>::template load<T>(prm.p, prm.vh, j, i, p);
-        FieldIO<FP>::template load<T>(prm.s, prm.vh, j, i, sv);
-        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 0, i, x);
+        FieldIO<FP>::template load<T>(prm.r, prm.vh, prm.nrhs, j, i, r);
+        FieldIO<FP>::template load<T>(prm.w, prm.vh, prm.nrhs, j, i, w);
+        FieldIO<FP>::template load<T>(prm.p, prm.vh, prm.nrhs, j, i, p);
+        FieldIO<FP>::template load<T>(prm.s, prm.vh, prm.nrhs, j, i, sv);
+        FieldIO<HISQ_FP64>::template load<double>(prm.x[j], prm.vh, 1, 0, i, x);
     }
     __shared__ double lds_tot[4];  // apart from lds: a wave may reach block_sum while others still read tot
     __shared__ double lds[12];
@@ -572,10 +612,10 @@ __global__ void __launch_bounds__(BLK) cgcg_fused_kernel(CgVecParams prm, const 
             part[2] = fma((double)p[c].re, sre, part[2]);
             part[2] = fma((double)p[c].im, sim, part[2]);
         }
-        FieldIO<FP>::template store<T>(prm.p, prm.vh, j, i, p);
-        FieldIO<FP>::template store<T>(prm.s, prm.vh, j, i, sv);
-        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 0, i, x);
-        FieldIO<FP>::template store<T>(prm.r, prm.vh, j, i, r);
+        FieldIO<FP>::template store<T>(prm.p, prm.vh, prm.nrhs, j, i, p);
+        FieldIO<FP>::template store<T>(prm.s, prm.vh, prm.nrhs, j, i, sv);
+        FieldIO<HISQ_FP64>::template store<double>(prm.x[j], prm.vh, 1, 0, i, x);
+        FieldIO<FP>::template store<T>(prm.r, prm.vh, prm.nrhs, j, i, r);
     }
     block_sum<3>(part, lds);
     if (threadIdx.x == 0) {
@@ -586,41 +626,45 @@ __global__ void __launch_bounds__(BLK) cgcg_fused_kernel(CgVecParams prm, const 
     }
 }
 
-// r_j = b_j - ax_j for the columns j = blockIdx.y whose tr_skip[j] is 0 (all
-// columns when tr_skip is NULL): FP64 inputs, r stored in the sloppy
-// precision, block partials of ||b_j - ax_j||^2 (FP64 values) in
-// partials[j * gridDim.x + block] and, when s and p are not NULL, of
-// Re <r_j, s_j> (the stored r) and Re <p_j, s_j> in spart and ppart (same
-// layout).  b, ax, r, s, p: packed fields of gridDim.y columns.  A launch that
-// forms residuals reopens the iteration launches after it: *skip = 0
-// (nullable) and col_off[j] = 0 (nullable) for each column it forms.
-template <int FP>
-__global__ void __launch_bounds__(BLK) residual_cols_kernel(int vh, const void *b, const void *ax, void *r,
-                                                            double *partials, const int *tr_skip, const void *s,
-                                                            const void *p, double *spart, double *ppart, int *skip,
-                                                            int *col_off) {
+// r_j = b_j - ax_j for the ncol columns j of the launch (block row
+// blockIdx.y; VecPos) whose tr_skip[j] is 0 (all columns when tr_skip is
+// NULL): FP64 inputs b, ax (packed fields of ncol columns), r stored in the
+// sloppy precision as column col0 + j of the nf-column field r, block
+// partials of ||b_j - ax_j||^2 (FP64 values) in partials[j * gridDim.x +
+// block] and, when s and p are not NULL, of Re <r_j, s_j> (the stored r) and
+// Re <p_j, s_j> in spart and ppart (same layout; s and p are nf-column fields
+// like r).  A launch that forms residuals reopens the iteration launches
+// after it: *skip = 0 (nullable) and col_off[j] = 0 (nullable) for each
+// column it forms.  PAIR needs col0 even.
+template <int FP, bool PAIR>
+__global__ void __launch_bounds__(PAIR ? 2 * BLK : BLK)
+    residual_cols_kernel(int vh, int ncol, int nf, int col0, const void *b, const void *ax, void *r, double *partials,
+                         const int *tr_skip, const void *s, const void *p, double *spart, double *ppart, int *skip,
+                         int *col_off) {
     using T = typename Sloppy<FP>::T;
-    const int j = blockIdx.y;
-    if (tr_skip && tr_skip[j] != 0)
-        return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const VecPos<PAIR> at;
+    const int j = at.j;
+    const bool run = j < ncol && !(tr_skip && tr_skip[j] != 0);
+    if (!PAIR && !run)
+        return;  // the whole block belongs to column j
+    if (blockIdx.x == 0 && at.leader() && run) {
         if (skip)
             *skip = 0;
         if (col_off)
             col_off[j] = 0;
     }
-    __shared__ double lds[12];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double lds[vec_lds(3, PAIR)];
+    const int i = at.i;
     double part[3] = {0.0, 0.0, 0.0};
     const bool sp = s && p;
-    if (i < vh) {
+    if (run && i < vh) {
         cplx<double> bv[3], av[3];
-        FieldIO<HISQ_FP64>::template load<double>(b, vh, j, i, bv);
-        FieldIO<HISQ_FP64>::template load<double>(ax, vh, j, i, av);
+        FieldIO<HISQ_FP64>::template load<double>(b, vh, ncol, j, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(ax, vh, ncol, j, i, av);
         cplx<T> rv[3], sv[3], pv[3];
         if (sp) {
-            FieldIO<FP>::template load<T>(s, vh, j, i, sv);
-            FieldIO<FP>::template load<T>(p, vh, j, i, pv);
+            FieldIO<FP>::template load<T>(s, vh, nf, col0 + j, i, sv);
+            FieldIO<FP>::template load<T>(p, vh, nf, col0 + j, i, pv);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -636,10 +680,10 @@ __global__ void __launch_bounds__(BLK) residual_cols_kernel(int vh, const void *
                 part[2] = fma((double)pv[c].im, (double)sv[c].im, part[2]);
             }
         }
-        FieldIO<FP>::template store<T>(r, vh, j, i, rv);
+        FieldIO<FP>::template store<T>(r, vh, nf, col0 + j, i, rv);
     }
-    block_sum<3>(part, lds);
-    if (threadIdx.x == 0) {
+    vec_block_sum<3, PAIR>(part, lds);
+    if (at.leader() && run) {
         const size_t o = (size_t)j * gridDim.x + blockIdx.x;
         partials[o] = part[0];
         if (sp) {
@@ -662,8 +706,8 @@ __global__ void __launch_bounds__(BLK) residual_kernel(int vh, const void *b, co
     double part[1] = {0.0};
     if (i < vh) {
         cplx<double> bv[3], av[3];
-        FieldIO<HISQ_FP64>::template load<double>(b, vh, 0, i, bv);
-        FieldIO<HISQ_FP64>::template load<double>(ax, vh, 0, i, av);
+        FieldIO<HISQ_FP64>::template load<double>(b, vh, 1, 0, i, bv);
+        FieldIO<HISQ_FP64>::template load<double>(ax, vh, 1, 0, i, av);
         cplx<T> rv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -673,7 +717,7 @@ __global__ void __launch_bounds__(BLK) residual_kernel(int vh, const void *b, co
             rv[c].re = (T)re;
             rv[c].im = (T)im;
         }
-        FieldIO<FP>::template store<T>(r, vh, 0, i, rv);
+        FieldIO<FP>::template store<T>(r, vh, 1, 0, i, rv);
     }
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
@@ -687,7 +731,7 @@ __global__ void __launch_bounds__(BLK) norm2_kernel(int vh, const void *v, doubl
     double part[1] = {0.0};
     if (i < vh) {
         cplx<double> a[3];
-        FieldIO<HISQ_FP64>::template load<double>(v, vh, 0, i, a);
+        FieldIO<HISQ_FP64>::template load<double>(v, vh, 1, 0, i, a);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             part[0] = fma(a[c].re, a[c].re, part[0]);
@@ -707,8 +751,8 @@ __global__ void __launch_bounds__(BLK) dot_re_kernel(int vh, const void *a, cons
     double part[1] = {0.0};
     if (i < vh) {
         cplx<double> u[3], v[3];
-        FieldIO<HISQ_FP64>::template load<double>(a, vh, r, i, u);
-        FieldIO<HISQ_FP64>::template load<double>(b, vh, r, i, v);
+        FieldIO<HISQ_FP64>::template load<double>(a, vh, 1, r, i, u);
+        FieldIO<HISQ_FP64>::template load<double>(b, vh, 1, r, i, v);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             part[0] = fma(u[c].re, v[c].re, part[0]);
@@ -729,8 +773,20 @@ __global__ void __launch_bounds__(BLK) copy_kernel(int vh, int n, const void *sr
     if (i >= vh || r >= n)
         return;
     cplx<T> v[3];
-    FieldIO<FS>::template load<T>(src, vh, r, i, v);
-    FieldIO<FD>::template store<T>(dst, vh, r, i, v);
+    FieldIO<FS>::template load<T>(src, vh, n, r, i, v);
+    FieldIO<FD>::template store<T>(dst, vh, n, r, i, v);
+}
+
+// dst (one column) = column k of the n-column field src.
+template <int FP>
+__global__ void __launch_bounds__(BLK) copy_col_kernel(int vh, int n, int k, const void *src, void *dst) {
+    using T = typename Sloppy<FP>::T;
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= vh)
+        return;
+    cplx<T> v[3];
+    FieldIO<FP>::template load<T>(src, vh, n, k, i, v);
+    FieldIO<FP>::template store<T>(dst, vh, 1, 0, i, v);
 }
 
 __global__ void __launch_bounds__(BLK) fill_u32_kernel(unsigned *p, size_t n, unsigned v) {
@@ -785,25 +841,30 @@ hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipSt
     if (e != hipSuccess)
         return e;
     const int b = cg_vec_block(p.vh);
-    const dim3 g((unsigned)cg_vec_blocks(p.vh), (unsigned)p.nrhs);
+    const unsigned nb = (unsigned)cg_vec_blocks(p.vh);
     if (fp == HISQ_FP64)
-        cgcg_update_kernel<HISQ_FP64><<<g, b, 0, st>>>(p);
+        cgcg_update_kernel<HISQ_FP64, false><<<dim3(nb, (unsigned)p.nrhs), b, 0, st>>>(p);
+    else if (p.nrhs >= 2)  // column pairs share 16-byte records
+        cgcg_update_kernel<HISQ_FP32, true><<<dim3(nb, (unsigned)(p.nrhs + 1) / 2), 2 * b, 0, st>>>(p);
     else
-        cgcg_update_kernel<HISQ_FP32><<<g, b, 0, st>>>(p);
+        cgcg_update_kernel<HISQ_FP32, false><<<dim3(nb, 1u), b, 0, st>>>(p);
     return hipGetLastError();
 }
 
-hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
-                                const int *tr_skip, const void *s, const void *p, double *spart, double *ppart,
-                                int *skip, int *col_off, hipStream_t st) {
+hipError_t launch_residual_cols(int vh, int ncol, int nf, int col0, int fp, const void *b, const void *ax, void *r,
+                                double *partials, const int *tr_skip, const void *s, const void *p, double *spart,
+                                double *ppart, int *skip, int *col_off, hipStream_t st) {
     const int bs = cg_vec_block(vh);
-    const dim3 g((unsigned)cg_vec_blocks(vh), (unsigned)ncol);
+    const unsigned nb = (unsigned)cg_vec_blocks(vh);
     if (fp == HISQ_FP64)
-        residual_cols_kernel<HISQ_FP64>
-            <<<g, bs, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+        residual_cols_kernel<HISQ_FP64, false><<<dim3(nb, (unsigned)ncol), bs, 0, st>>>(
+            vh, ncol, nf, col0, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+    else if (ncol >= 2 && col0 % 2 == 0)  // column pairs share 16-byte records
+        residual_cols_kernel<HISQ_FP32, true><<<dim3(nb, (unsigned)(ncol + 1) / 2), 2 * bs, 0, st>>>(
+            vh, ncol, nf, col0, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
     else
-        residual_cols_kernel<HISQ_FP32>
-            <<<g, bs, 0, st>>>(vh, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
+        residual_cols_kernel<HISQ_FP32, false><<<dim3(nb, (unsigned)ncol), bs, 0, st>>>(
+            vh, ncol, nf, col0, b, ax, r, partials, tr_skip, s, p, spart, ppart, skip, col_off);
     return hipGetLastError();
 }
 
@@ -855,6 +916,16 @@ hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst
         copy_kernel<HISQ_FP32, HISQ_FP32><<<g, BLK, 0, st>>>(vh, n, src, dst);
     else if (fs == HISQ_FP32 && fd == HISQ_FP64)
         copy_kernel<HISQ_FP32, HISQ_FP64><<<g, BLK, 0, st>>>(vh, n, src, dst);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_col(int vh, int fp, int n, int k, const void *src, void *dst, hipStream_t st) {
+    if (fp == HISQ_FP64)
+        copy_col_kernel<HISQ_FP64><<<grid_for(vh), BLK, 0, st>>>(vh, n, k, src, dst);
+    else if (fp == HISQ_FP32)
+        copy_col_kernel<HISQ_FP32><<<grid_for(vh), BLK, 0, st>>>(vh, n, k, src, dst);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -67,13 +67,13 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
     L.rr = take(sizeof(double) * 2 * L.part_set);
     L.rspart = take(sizeof(double) * 2 * L.part_set);
     L.pspart = take(sizeof(double) * 2 * L.part_set);
-    const size_t fb = field_bytes(g, L.fs, 1);
-    L.r = take(fb * ncol);
-    L.p = take(fb * ncol);
-    L.q = take(fb * ncol);  // A p (s of the single-reduction CG)
-    L.w = take(fb * ncol);  // A r (single-reduction CG)
-    L.t = take(fb * ncol);
-    L.ps = take(fb * std::max(nshift, 0));
+    const size_t fb = field_bytes(g, L.fs, 1), fbn = field_bytes(g, L.fs, ncol);
+    L.r = take(fbn);
+    L.p = take(fbn);
+    L.q = take(fbn);  // A p (s of the single-reduction CG)
+    L.w = take(fbn);  // A r (single-reduction CG)
+    L.t = take(fbn);
+    L.ps = take(fb * std::max(nshift, 0));  // one-column fields end to end
     const size_t f64 = field_bytes(g, HISQ_FP64, 1);
     L.ax = take(f64);
     L.t64 = take(f64);
@@ -375,7 +375,6 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         return s;
 
     char *rs = S.at<char>(L.r);
-    const size_t cs = S.fs_col();
     S.shape_in = pick_shape(S.ctx, g, S.lp_in, L.fs, nrhs);
     const int nb = cg_vec_blocks(g.vh);  // <r, r> partials per column
     double *rr = S.at<double>(L.rr);
@@ -387,7 +386,7 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         // reads them, and the FP64 norm for the decisions below
         if ((s = S.apply_m64(C.sigma[j], C.x[j], S.at<void>(L.ax))) != HISQ_OK)
             return s;
-        hipError_t e = launch_residual_cols(g.vh, 1, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
+        hipError_t e = launch_residual_cols(g.vh, 1, nrhs, j, L.fs, C.b[j], S.at<void>(L.ax), rs,
                                             rr + (size_t)j * nb, nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, nullptr, st);
         if (e == hipSuccess)
@@ -450,13 +449,15 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     vp.rs_part = S.at<double>(L.rspart);
     vp.ps_part = S.at<double>(L.pspart);
     vp.rr_nblk = nb;
-    // one launch for the scalar and vector steps when every block can afford
-    // to sum its column's partials itself (measured: 32^3x8 and smaller)
-    const bool fused = vp.rw_nblk <= 2048 && nb <= 2048;
-    vp.part_buf = fused ? L.part_set : 0;
-    int *col_off = reinterpret_cast<int *>(S.flags() + F_OFF0);
     vp.rw_part = S.at<double>(L.dpart);
     vp.rw_nblk = dslash_partial_blocks(g, S.shape_in);
+    // one launch for the scalar and vector steps when every block can afford
+    // to sum its column's partials itself (measured: 32^3x8 and smaller);
+    // FP32 fields of several columns take the two-launch step, whose vector
+    // kernel reads them in column pairs
+    const bool fused = vp.rw_nblk <= 2048 && nb <= 2048 && !(L.fs == HISQ_FP32 && nrhs >= 2);
+    vp.part_buf = fused ? L.part_set : 0;
+    int *col_off = reinterpret_cast<int *>(S.flags() + F_OFF0);
     vp.skip = reinterpret_cast<int *>(S.flags() + F_SKIP);
     vp.tr_skip = trf;
     int *nopend = reinterpret_cast<int *>(S.flags() + F_NOPEND);
@@ -502,7 +503,7 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
                 prm.ay_rhs[j] = S.mass * S.mass + C.sigma[j];
             e = launch_dslash(prm, HISQ_FP64, HISQ_FP64, EPI_AXPY, S.shape64m, st);
             if (e == hipSuccess)
-                e = launch_residual_cols(g.vh, nrhs, L.fs, C.b[0], S.at<void>(L.axm), rs, rr, trf, vp.s, vp.p,
+                e = launch_residual_cols(g.vh, nrhs, nrhs, 0, L.fs, C.b[0], S.at<void>(L.axm), rs, rr, trf, vp.s, vp.p,
                                          vp.rs_part, vp.ps_part, fused ? nullptr : vp.skip,
                                          fused ? col_off : nullptr, st);
             return e;
@@ -510,9 +511,8 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         for (int j = 0; j < nrhs; ++j) {
             hipError_t e = S.m64(C.sigma[j], C.x[j], S.at<void>(L.ax), trf + j);
             if (e == hipSuccess)
-                e = launch_residual_cols(g.vh, 1, L.fs, C.b[j], S.at<void>(L.ax), rs + j * cs,
-                                         rr + (size_t)j * nb, trf + j, static_cast<char *>(vp.s) + j * cs,
-                                         static_cast<char *>(vp.p) + j * cs, vp.rs_part + (size_t)j * nb,
+                e = launch_residual_cols(g.vh, 1, nrhs, j, L.fs, C.b[j], S.at<void>(L.ax), rs,
+                                         rr + (size_t)j * nb, trf + j, vp.s, vp.p, vp.rs_part + (size_t)j * nb,
                                          vp.ps_part + (size_t)j * nb, fused ? nullptr : vp.skip,
                                          fused ? col_off + j : nullptr, st);
             if (e != hipSuccess)
@@ -642,7 +642,8 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
             rtrue2[j] = c.rtrue2;
         } else {
             double r2 = 0.0;
-            if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs + j * cs, &r2)) != HISQ_OK)
+            // (the sloppy r is not needed any more: scratch for the residual)
+            if ((s = S.true_residual(C.sigma[j], C.b[j], C.x[j], rs, &r2)) != HISQ_OK)
                 return s;
             rtrue2[j] = r2;
             if (std::isfinite(r2) && r2 <= c.target2 && c.flag != FLAG_BREAKDOWN)

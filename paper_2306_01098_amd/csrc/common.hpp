@@ -127,14 +127,18 @@ template <int LP> __host__ __device__ inline size_t link_block(int f, int p, int
 
 // ---------------------------------------------------------------------------
 // Packed field layout (one parity, nrhs right-hand sides).
-//   FP64 / FP32: [rhs][colour][site] complex (16 / 8 bytes per element).
-//   FP16N:       [rhs][site] 16-byte records {half2 c0, half2 c1, half2 c2,
-//                float norm}: one dwordx4 load fetches a whole site.
+//   FP64:  [rhs][colour][site] complex (16 bytes per element).
+//   FP32:  one column [colour][site] complex (8 bytes per element); two or
+//          more columns in pairs, [pair][colour][site] 16-byte records (the
+//          second slot of the last pair unused when nrhs is odd).
+//   FP16N: [rhs][site] 16-byte records {half2 c0, half2 c1, half2 c2,
+//          float norm}: one dwordx4 load fetches a whole site.
 // ---------------------------------------------------------------------------
 inline size_t field_bytes(const Geom &g, int prec, int nrhs) {
     const int fp = field_prec_of(prec);
     size_t per = fp == HISQ_FP64 ? 48 : fp == HISQ_FP32 ? 24 : 16;
-    return (size_t)nrhs * (size_t)g.vh * per;
+    const int cols = fp == HISQ_FP32 && nrhs >= 2 ? (nrhs + 1) & ~1 : nrhs;
+    return (size_t)cols * (size_t)g.vh * per;
 }
 
 // ---------------------------------------------------------------------------

@@ -192,12 +192,49 @@ __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, 
 
 template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int vh, int ilink, const void *in,
-                                         int ipsi, int r0, int nr, int f) {
+                                         int ipsi, int ncol, int r0, int nr, int f) {
     LinkIO<LP>::template load<NT>(blk, vh, ilink, b.m, f);
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
         if (r < nr)
-            FieldIO<FP>::template load<A>(in, vh, r0 + r, ipsi, b.v[r]);
+            FieldIO<FP>::template load<A>(in, vh, ncol, r0 + r, ipsi, b.v[r]);
+}
+
+// The nr (<= NIN) columns r0 .. r0 + nr - 1 of site i of an ncol-column
+// field.  FP32 fields with NIN even take both slots of each pair with one
+// 16-byte access per colour (r0 is a multiple of NIN, so the group starts on
+// a pair; the pair of an odd last column has an unused second slot, which
+// is loaded and never used, and stored as zero).
+template <int FP, int NIN, typename A>
+__device__ __forceinline__ void load_group(const void *f, int vh, int ncol, int r0, int nr, int i,
+                                           cplx<A> (&v)[NIN][3]) {
+    if constexpr (FP == HISQ_FP32 && NIN % 2 == 0) {
+#pragma unroll
+        for (int r = 0; r < NIN; r += 2)
+            if (r < nr)
+                FieldIO<FP>::template load_pair<A>(f, vh, (r0 + r) >> 1, i, v[r], v[r + 1]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                FieldIO<FP>::template load<A>(f, vh, ncol, r0 + r, i, v[r]);
+    }
+}
+
+template <int FP, int NIN, typename A>
+__device__ __forceinline__ void store_group(void *f, int vh, int ncol, int r0, int nr, int i,
+                                            const cplx<A> (&v)[NIN][3]) {
+    if constexpr (FP == HISQ_FP32 && NIN % 2 == 0) {
+#pragma unroll
+        for (int r = 0; r < NIN; r += 2)
+            if (r < nr)
+                FieldIO<FP>::template store_pair<A>(f, vh, (r0 + r) >> 1, i, v[r], v[r + 1]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                FieldIO<FP>::template store<A>(f, vh, ncol, r0 + r, i, v[r]);
+    }
 }
 
 // The four hops along direction mu (runtime) of site s (half index i, parity
@@ -205,7 +242,7 @@ __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int
 // issued before the current hop is computed.
 template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const char *links, const void *in,
-                                                 int i, const Site &s, int mu, int r0, int nr,
+                                                 int i, const Site &s, int mu, int ncol, int r0, int nr,
                                                  cplx<A> (&acc)[NIN][3]) {
     const int vh = g.vh;
     const int c = mu == 0 ? s.x : mu == 1 ? s.y : mu == 2 ? s.z : s.t;
@@ -221,12 +258,12 @@ __device__ __forceinline__ void dslash_direction(const Geom &g, int p, const cha
     zero<NIN, A>(tmp);
     const int q = 1 - p;
     HopBuf<NIN, A> b0, b1;
-    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(0, p, mu, vh), vh, i, in, n1, r0, nr, 0);
-    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(0, q, mu, vh), vh, n2, in, n2, r0, nr, 0);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(0, p, mu, vh), vh, i, in, n1, ncol, r0, nr, 0);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(0, q, mu, vh), vh, n2, in, n2, ncol, r0, nr, 0);
     hop_apply<LP, NIN, A>(b0, false, s1, nr, tmp, 0);
-    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(1, p, mu, vh), vh, i, in, n3, r0, nr, 1);
+    hop_load<LP, FP, NIN, A, NT>(b0, links + link_block<LP>(1, p, mu, vh), vh, i, in, n3, ncol, r0, nr, 1);
     hop_apply<LP, NIN, A>(b1, true, s2, nr, tmp, 0);
-    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(1, q, mu, vh), vh, n4, in, n4, r0, nr, 1);
+    hop_load<LP, FP, NIN, A, NT>(b1, links + link_block<LP>(1, q, mu, vh), vh, n4, in, n4, ncol, r0, nr, 1);
     hop_apply<LP, NIN, A>(b0, false, s3, nr, tmp, 1);
     hop_apply<LP, NIN, A>(b1, true, s4, nr, tmp, 1);
     const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
@@ -276,7 +313,7 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
 // flight per wavefront instead of one.
 template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
-                                            int r0, int nr, cplx<A> (&acc)[NIN][3]) {
+                                            int ncol, int r0, int nr, cplx<A> (&acc)[NIN][3]) {
     const Site s = site_coords(g, p, i);
     zero<NIN, A>(acc);
     cplx<A> tmp[NIN][3];
@@ -297,10 +334,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         auto load_vec = [&](int k, int slot) {
             A sg;
             const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
-#pragma unroll
-            for (int r = 0; r < NIN; ++r)
-                if (r < nr)
-                    FieldIO<FP>::template load<A>(in, g.vh, r0 + r, h.ipsi, vb[slot][r]);
+            load_group<FP, NIN, A>(in, g.vh, ncol, r0, nr, h.ipsi, vb[slot]);
             sgv[slot] = sg;
             bkv[slot] = h.back;
         };
@@ -343,10 +377,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         A sg;
         const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
         LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m, h.f);
-#pragma unroll
-        for (int r = 0; r < NIN; ++r)
-            if (r < nr)
-                FieldIO<FP>::template load<A>(in, g.vh, r0 + r, h.ipsi, buf[slot].v[r]);
+        load_group<FP, NIN, A>(in, g.vh, ncol, r0, nr, h.ipsi, buf[slot].v);
         sgn[slot] = sg;
         back[slot] = h.back;
     };
@@ -373,6 +404,20 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
     }
 }
 
+// prm.ay_rhs[r] (or prm.ay) by static indices: a dynamic index into the
+// kernel argument would make the compiler copy the whole argument block to
+// scratch memory (280 bytes per lane in the four-lanes-per-site kernel).
+__device__ __forceinline__ double ay_of(const DslashParams &prm, int r) {
+    double v = prm.ay;
+    if (prm.ay_per_rhs) {
+#pragma unroll
+        for (int q = 0; q < HISQ_MAX_RHS; ++q)
+            if (q == r)
+                v = prm.ay_rhs[q];
+    }
+    return v;
+}
+
 // out = ad * acc + ay * y  (EPI_AXPY*) for right-hand side r at site i;
 // returns Re <y, out> in FP64 (products of the stored-precision values).
 // The same with y of the site already loaded (yv; ignored for EPI_PLAIN).
@@ -381,7 +426,7 @@ __device__ __forceinline__ double epilogue_y(const DslashParams &prm, int r, con
                                              cplx<A> (&v)[3]) {
     double dot = 0.0;
     if (EPI != EPI_PLAIN) {
-        const A ad = (A)prm.ad, ay = (A)(prm.ay_per_rhs ? prm.ay_rhs[r] : prm.ay);
+        const A ad = (A)prm.ad, ay = (A)ay_of(prm, r);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             v[a].re = fma(ad, v[a].re, ay * yv[a].re);
@@ -400,8 +445,8 @@ __device__ __forceinline__ double epilogue(const DslashParams &prm, int r, int i
     double dot = 0.0;
     if (EPI != EPI_PLAIN) {
         cplx<A> yv[3];
-        FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r, i, yv);
-        const A ad = (A)prm.ad, ay = (A)(prm.ay_per_rhs ? prm.ay_rhs[r] : prm.ay);
+        FieldIO<FP>::template load<A>(prm.y, prm.g.vh, prm.nrhs, r, i, yv);
+        const A ad = (A)prm.ad, ay = (A)ay_of(prm, r);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             v[a].re = fma(ad, v[a].re, ay * yv[a].re);
@@ -446,14 +491,16 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
         dot[r] = 0.0;
     if (valid) {
         cplx<A> acc[NIN][3];
-        dslash_site<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, r0, nr, acc);
+        dslash_site<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, prm.nrhs, r0, nr, acc);
+        if constexpr (EPI != EPI_PLAIN) {
+            cplx<A> yv[NIN][3];
+            load_group<FP, NIN, A>(prm.y, prm.g.vh, prm.nrhs, r0, nr, i, yv);
 #pragma unroll
-        for (int r = 0; r < NIN; ++r) {
-            if (r < nr) {
-                dot[r] = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
-                FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
-            }
+            for (int r = 0; r < NIN; ++r)
+                if (r < nr)
+                    dot[r] = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
         }
+        store_group<FP, NIN, A>(prm.out, prm.g.vh, prm.nrhs, r0, nr, i, acc);
     }
     if (EPI == EPI_AXPY_DOT)
         dslash_dot_reduce<NIN>(prm, dot, bp);
@@ -487,11 +534,12 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
             if (r < nr)
-                FieldIO<FP>::template load<A>(prm.y, prm.g.vh, r0 + r, i, yv[r]);
+                FieldIO<FP>::template load<A>(prm.y, prm.g.vh, prm.nrhs, r0 + r, i, yv[r]);
     }
     cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
-    dslash_direction<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, r0, nr, acc);
+    dslash_direction<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, prm.nrhs, r0, nr,
+                                         acc);
     // sum over the quad: (mu0 + mu1) + (mu2 + mu3), identical in all 4 lanes
 #pragma unroll
     for (int r = 0; r < NIN; ++r)
@@ -509,13 +557,13 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
             dot[r] = mu == 0 ? d : 0.0;  // one lane of the quad counts the site
             if constexpr (FP == HISQ_FP16N) {
                 if (mu == 0)  // one 16-byte record holds the whole site
-                    FieldIO<FP>::template store<A>(prm.out, prm.g.vh, r0 + r, i, acc[r]);
+                    FieldIO<FP>::template store<A>(prm.out, prm.g.vh, prm.nrhs, r0 + r, i, acc[r]);
             } else {
                 // lane mu < 3 writes colour mu (static indices keep acc in registers)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     if (mu == c)
-                        FieldIO<FP>::template store_colour<A>(prm.out, prm.g.vh, r0 + r, i, c, acc[r][c]);
+                        FieldIO<FP>::template store_colour<A>(prm.out, prm.g.vh, prm.nrhs, r0 + r, i, c, acc[r][c]);
             }
         }
     }
@@ -559,13 +607,13 @@ __global__ void __launch_bounds__(256) dslash_hop_kernel(const DslashParams prm)
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
             if (r < nr)
-                FieldIO<FP>::template load<A>(prm.in, g.vh, r0 + r, h.ipsi, b.v[r]);
+                FieldIO<FP>::template load<A>(prm.in, g.vh, prm.nrhs, r0 + r, h.ipsi, b.v[r]);
         cplx<A> yv[NIN][3];
         if (EPI != EPI_PLAIN) {
 #pragma unroll
             for (int r = 0; r < NIN; ++r)
                 if (r < nr)
-                    FieldIO<FP>::template load<A>(prm.y, g.vh, r0 + r, i, yv[r]);
+                    FieldIO<FP>::template load<A>(prm.y, g.vh, prm.nrhs, r0 + r, i, yv[r]);
         }
         cplx<A> acc[NIN][3];
         zero<NIN, A>(acc);
@@ -594,12 +642,12 @@ __global__ void __launch_bounds__(256) dslash_hop_kernel(const DslashParams prm)
                 dot[r] = k == 0 ? d : 0.0;  // one lane of the group counts the site
                 if constexpr (FP == HISQ_FP16N) {
                     if (k == 0)
-                        FieldIO<FP>::template store<A>(prm.out, g.vh, r0 + r, i, acc[r]);
+                        FieldIO<FP>::template store<A>(prm.out, g.vh, prm.nrhs, r0 + r, i, acc[r]);
                 } else {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         if (k == c)
-                            FieldIO<FP>::template store_colour<A>(prm.out, g.vh, r0 + r, i, c, acc[r][c]);
+                            FieldIO<FP>::template store_colour<A>(prm.out, g.vh, prm.nrhs, r0 + r, i, c, acc[r][c]);
                 }
             }
         }
@@ -676,7 +724,11 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
                 const int row = rem / g.hx, xh = rem - row * g.hx;
                 int gy = y0 - LDS_HALO + row;
                 gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-                v[j] = src[(size_t)(r0 * 3 + rc) * g.vh + plane + gy * g.hx + xh];
+                const int site = plane + gy * g.hx + xh;
+                if constexpr (FP == HISQ_FP32)
+                    v[j] = src[f32_index(g.vh, prm.nrhs, r0 + rc / 3, rc % 3, site)];
+                else
+                    v[j] = src[(size_t)(r0 * 3 + rc) * g.vh + site];
             }
         }
 #pragma unroll
@@ -710,7 +762,7 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
 #pragma unroll
             for (int r = 0; r < NIN; ++r)
                 if (r < nr)
-                    FieldIO<FP>::template load<A>(prm.in, g.vh, r0 + r, h.ipsi, buf[slot].v[r]);
+                    FieldIO<FP>::template load<A>(prm.in, g.vh, prm.nrhs, r0 + r, h.ipsi, buf[slot].v[r]);
         } else {
             // LDS row and column of the neighbour: x-hops stay in the row,
             // y-hops move rows (the staged rows start at y0 - 3)
@@ -766,7 +818,7 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
         dot[r] = 0.0;
         if (r < nr) {
             dot[r] = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
-            FieldIO<FP>::template store<A>(prm.out, g.vh, r0 + r, i, acc[r]);
+            FieldIO<FP>::template store<A>(prm.out, g.vh, prm.nrhs, r0 + r, i, acc[r]);
         }
     }
     if (EPI == EPI_AXPY_DOT)

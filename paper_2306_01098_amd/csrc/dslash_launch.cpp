@@ -49,6 +49,8 @@ hipError_t launch_dslash(const DslashParams &prm, int lp, int fp, int epi, Dslas
         s = DslashShape{VAR_SITE, s.nin, 64, prm.g.nz % 8 == 0 ? 2 : 1};  // geometry or format not staged
     if (!dslash_shape_fits(s, prm.g))
         s.xcd_remap = 1;  // z-slab order needs N_z divisible by 8
+    if (fp == HISQ_FP32 && prm.nrhs < 2)
+        s.nin = 1;  // a one-column FP32 field has no column pairs to load together
     if (lp == HISQ_FP64 && fp == HISQ_FP64)
         return dslash_launch_f64(prm, epi, s, st);
     if (lp == HISQ_FP32 && fp == HISQ_FP32)

@@ -21,8 +21,8 @@ __global__ void __launch_bounds__(FB) dot_kernel(int vh, const void *a, const vo
     double v[2] = {0.0, 0.0};
     if (i < vh) {
         cplx<float> x[3], y[3];
-        FieldIO<HISQ_FP32>::template load<float>(a, vh, 0, i, x);
-        FieldIO<HISQ_FP32>::template load<float>(b, vh, 0, i, y);
+        FieldIO<HISQ_FP32>::template load<float>(a, vh, 1, 0, i, x);
+        FieldIO<HISQ_FP32>::template load<float>(b, vh, 1, 0, i, y);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             v[0] += (double)x[c].re * y[c].re + (double)x[c].im * y[c].im;
@@ -49,10 +49,10 @@ __global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, 
     if (ok && i < vh) {
         cplx<float> pv[3], qv[3], rv[3];
         cplx<double> xv[3];
-        FieldIO<HISQ_FP32>::template load<float>(p, vh, 0, i, pv);
-        FieldIO<HISQ_FP32>::template load<float>(q, vh, 0, i, qv);
-        FieldIO<HISQ_FP32>::template load<float>(r, vh, 0, i, rv);
-        FieldIO<HISQ_FP64>::template load<double>(x, vh, 0, i, xv);
+        FieldIO<HISQ_FP32>::template load<float>(p, vh, 1, 0, i, pv);
+        FieldIO<HISQ_FP32>::template load<float>(q, vh, 1, 0, i, qv);
+        FieldIO<HISQ_FP32>::template load<float>(r, vh, 1, 0, i, rv);
+        FieldIO<HISQ_FP64>::template load<double>(x, vh, 1, 0, i, xv);
         const float fr = (float)ar, fi = (float)ai;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(FB) xr_kernel(int vh, void *x, const void *p, 
             cmac(rv[c], -fr, -fi, qv[c]);
             part[0] += (double)rv[c].re * rv[c].re + (double)rv[c].im * rv[c].im;
         }
-        FieldIO<HISQ_FP64>::template store<double>(x, vh, 0, i, xv);
-        FieldIO<HISQ_FP32>::template store<float>(r, vh, 0, i, rv);
+        FieldIO<HISQ_FP64>::template store<double>(x, vh, 1, 0, i, xv);
+        FieldIO<HISQ_FP32>::template store<float>(r, vh, 1, 0, i, rv);
     }
     block_sum<1>(part, lds);
     if (threadIdx.x == 0)
@@ -160,15 +160,15 @@ __global__ void __launch_bounds__(FB) p_kernel(int vh, const void *z, void *p, c
         return;
     const float br = (float)(st.qz.x / st.pq), bi = (float)(st.qz.y / st.pq);
     cplx<float> zv[3], pv[3];
-    FieldIO<HISQ_FP32>::template load<float>(z, vh, 0, i, zv);
-    FieldIO<HISQ_FP32>::template load<float>(p, vh, 0, i, pv);
+    FieldIO<HISQ_FP32>::template load<float>(z, vh, 1, 0, i, zv);
+    FieldIO<HISQ_FP32>::template load<float>(p, vh, 1, 0, i, pv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         cplx<float> o = zv[c];
         cmac(o, -br, -bi, pv[c]);
         pv[c] = o;
     }
-    FieldIO<HISQ_FP32>::template store<float>(p, vh, 0, i, pv);
+    FieldIO<HISQ_FP32>::template store<float>(p, vh, 1, 0, i, pv);
 }
 
 }  // namespace

@@ -58,16 +58,17 @@ hipError_t launch_cg_restart(const CgVecParams &p, const double *trpart, hipStre
 // columns whose FP64 true residual the check block just formed) and the
 // fused vector update with the <r, r> partials of the new residual.
 hipError_t launch_cgcg_step(const CgVecParams &p, int fp, int after_check, hipStream_t st);
-// r_j = b_j - ax_j for the ncol columns of packed fields b, ax (FP64) and r
-// (sloppy) whose tr_skip[j] is 0 (every column if tr_skip is NULL), with the
+// r_j = b_j - ax_j for the ncol columns j of packed fields b, ax (FP64)
+// whose tr_skip[j] is 0 (every column if tr_skip is NULL), stored in the
+// sloppy precision as column col0 + j of the nf-column field r, with the
 // block partials of ||r_j||^2 at partials + j * cg_vec_blocks(vh) and, if s
-// and p (sloppy, ncol columns) are not NULL, those of Re <r_j, s_j> and
-// Re <p_j, s_j> at spart / ppart + j * cg_vec_blocks(vh); a launch that forms
-// residuals clears *skip and col_off[j] of each column it forms (both
-// nullable).
-hipError_t launch_residual_cols(int vh, int ncol, int fp, const void *b, const void *ax, void *r, double *partials,
-                                const int *tr_skip, const void *s, const void *p, double *spart, double *ppart,
-                                int *skip, int *col_off, hipStream_t st);
+// and p (sloppy nf-column fields like r) are not NULL, those of
+// Re <r_j, s_j> and Re <p_j, s_j> at spart / ppart + j * cg_vec_blocks(vh);
+// a launch that forms residuals clears *skip and col_off[j] of each column
+// it forms (both nullable).
+hipError_t launch_residual_cols(int vh, int ncol, int nf, int col0, int fp, const void *b, const void *ax, void *r,
+                                double *partials, const int *tr_skip, const void *s, const void *p, double *spart,
+                                double *ppart, int *skip, int *col_off, hipStream_t st);
 // The scalar and vector steps of single-reduction CG in one launch (every
 // block sums its column's partials): state read from st_in, written to
 // st_out, partials read from set in_buf and written to the other;
@@ -94,6 +95,8 @@ hipError_t launch_stream_read(const void *src, size_t n16, unsigned *sink, hipSt
 hipError_t launch_sum_partials(const double *partials, int nslots, int nblk, double *out, int stride,
                                const int *skip, hipStream_t st);
 hipError_t launch_copy(int vh, int n, int fs, int fd, const void *src, void *dst, hipStream_t st);
+// dst (a one-column field) = column k of the n-column field src (FP64 or FP32).
+hipError_t launch_copy_col(int vh, int fp, int n, int k, const void *src, void *dst, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t st);
 
 }  // namespace hisq

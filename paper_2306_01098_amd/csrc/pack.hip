@@ -213,10 +213,10 @@ __global__ void __launch_bounds__(256) pack_field_kernel(Geom g, int nrhs, const
         for (int c = 0; c < 3; ++c)
             p[(size_t)c * g.vh] = make_double2(d[2 * c], d[2 * c + 1]);
     } else if (FP == HISQ_FP32) {
-        float2 *p = reinterpret_cast<float2 *>(dst) + (size_t)r * 3 * g.vh + i;
+        float2 *p = reinterpret_cast<float2 *>(dst);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            p[(size_t)c * g.vh] = make_float2((float)d[2 * c], (float)d[2 * c + 1]);
+            p[f32_index(g.vh, nrhs, r, c, i)] = make_float2((float)d[2 * c], (float)d[2 * c + 1]);
     } else {
         double n = 0.0;
 #pragma unroll
@@ -249,10 +249,10 @@ __global__ void __launch_bounds__(256) unpack_field_kernel(Geom g, int nrhs, con
             d[2 * c + 1] = v.y;
         }
     } else if (FP == HISQ_FP32) {
-        const float2 *p = reinterpret_cast<const float2 *>(src) + (size_t)r * 3 * g.vh + i;
+        const float2 *p = reinterpret_cast<const float2 *>(src);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float2 v = p[(size_t)c * g.vh];
+            const float2 v = p[f32_index(g.vh, nrhs, r, c, i)];
             d[2 * c] = v.x;
             d[2 * c + 1] = v.y;
         }

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links
             LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
         for (int ci = 0; ci < CIN; ++ci) {
             cplx<float> v[3], t[3];
-            FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
+            FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 1, 2 * ci + h.par, h.nb, v);
             if (p > 0) {
                 transport(m, h.back, h.sg, v, t);
             } else {
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(PB) layer_fwd_kernel(Geom g, const char *links
     }
 #pragma unroll
     for (int co = 0; co < COUT; ++co)
-        FieldIO<HISQ_FP32>::template store<float>(out, g.vh, 2 * co + par, i, acc[co]);
+        FieldIO<HISQ_FP32>::template store<float>(out, g.vh, 1, 2 * co + par, i, acc[co]);
 }
 
 // g_in_ci(x) = sum_p T_p^+ (sum_co conj(w[co][ci][p]) g_co)(x); T_{+mu}^+ = T_{-mu}.
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *li
             LinkIO<HISQ_FP32>::load(xblock(links, h.lblk, (p - 1) >> 1, g.vh), g.vh, h.lidx, m);
         for (int co = 0; co < COUT; ++co) {
             cplx<float> v[3], t[3];
-            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + h.par, h.nb, v);
+            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 1, 2 * co + h.par, h.nb, v);
             if (p > 0) {
                 transport(m, h.back, h.sg, v, t);
             } else {
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(PB) layer_bwd_in_kernel(Geom g, const char *li
     }
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci)
-        FieldIO<HISQ_FP32>::template store<float>(gin, g.vh, 2 * ci + par, i, acc[ci]);
+        FieldIO<HISQ_FP32>::template store<float>(gin, g.vh, 1, 2 * ci + par, i, acc[ci]);
 }
 
 // Block partials of dL/dw[co][ci][p] = sum_x <(T_p in_ci)(x), g_co(x)>, one
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *lin
 #pragma unroll
     for (int co = 0; co < COUT; ++co) {
         if (valid) {
-            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 2 * co + par, i, gv[co]);
+            FieldIO<HISQ_FP32>::template load<float>(gout, g.vh, 1, 2 * co + par, i, gv[co]);
         } else {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(PB) layer_bwd_w_kernel(Geom g, const char *lin
                 acc[k] = 0.f;
             if (use) {
                 cplx<float> v[3], t[3];
-                FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 2 * ci + h.par, h.nb, v);
+                FieldIO<HISQ_FP32>::template load<float>(in, g.vh, 1, 2 * ci + h.par, h.nb, v);
                 if (p > 0) {
                     transport(m, h.back, h.sg, v, t);
                 } else {
@@ -291,13 +291,13 @@ __global__ void embed_kernel(int vh, const void *in_even, void *a0, const int *s
     const int i = gid - par * vh;
     cplx<float> v[3];
     if (par == 0) {
-        FieldIO<HISQ_FP32>::template load<float>(in_even, vh, 0, i, v);
+        FieldIO<HISQ_FP32>::template load<float>(in_even, vh, 1, 0, i, v);
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             v[a].re = v[a].im = 0.f;
     }
-    FieldIO<HISQ_FP32>::template store<float>(a0, vh, par, i, v);
+    FieldIO<HISQ_FP32>::template store<float>(a0, vh, 1, par, i, v);
 }
 
 __global__ void extract_kernel(int vh, const void *a3, void *out_even, const int *skip) {
@@ -307,8 +307,8 @@ __global__ void extract_kernel(int vh, const void *a3, void *out_even, const int
     if (i >= vh)
         return;
     cplx<float> v[3];
-    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, v);
-    FieldIO<HISQ_FP32>::template store<float>(out_even, vh, 0, i, v);
+    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 1, 0, i, v);
+    FieldIO<HISQ_FP32>::template store<float>(out_even, vh, 1, 0, i, v);
 }
 
 // Block partials of Re <x, b> for the FP64 solution x and FP32 source b
@@ -320,8 +320,8 @@ __global__ void __launch_bounds__(PB) xb_kernel(int vh, const void *x64, const v
     if (i < vh) {
         cplx<double> x[3];
         cplx<float> b[3];
-        FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
-        FieldIO<HISQ_FP32>::template load<float>(b32, vh, 0, i, b);
+        FieldIO<HISQ_FP64>::template load<double>(x64, vh, 1, 0, i, x);
+        FieldIO<HISQ_FP32>::template load<float>(b32, vh, 1, 0, i, b);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             part[0] += x[a].re * (double)b[a].re + x[a].im * (double)b[a].im;
@@ -338,14 +338,14 @@ __global__ void __launch_bounds__(PB) diff_kernel(int vh, const void *a3, const 
         return;
     cplx<float> y[3], d[3];
     cplx<double> x[3];
-    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 0, i, y);
-    FieldIO<HISQ_FP64>::template load<double>(x64, vh, 0, i, x);
+    FieldIO<HISQ_FP32>::template load<float>(a3, vh, 1, 0, i, y);
+    FieldIO<HISQ_FP64>::template load<double>(x64, vh, 1, 0, i, x);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         d[a].re = (float)((double)y[a].re - x[a].re);
         d[a].im = (float)((double)y[a].im - x[a].im);
     }
-    FieldIO<HISQ_FP32>::template store<float>(e, vh, 0, i, d);
+    FieldIO<HISQ_FP32>::template store<float>(e, vh, 1, 0, i, d);
 }
 
 // Output gradient of L_i = <e, A e> / c (c = <x, b>), scaled by 1/B:
@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(PB) energy_grad_kernel(int vh, const void *Ae,
     cplx<float> gv[3];
     if (par == 0) {
         cplx<float> v[3];
-        FieldIO<HISQ_FP32>::template load<float>(Ae, vh, 0, i, v);
+        FieldIO<HISQ_FP32>::template load<float>(Ae, vh, 1, 0, i, v);
         const float coef = (float)(2.0 * inv_batch / cc);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(PB) energy_grad_kernel(int vh, const void *Ae,
         for (int a = 0; a < 3; ++a)
             gv[a].re = gv[a].im = 0.f;
     }
-    FieldIO<HISQ_FP32>::template store<float>(g3, vh, par, i, gv);
+    FieldIO<HISQ_FP32>::template store<float>(g3, vh, 1, par, i, gv);
 }
 
 // Adam on real and imaginary parts as separate parameters; FP64 master

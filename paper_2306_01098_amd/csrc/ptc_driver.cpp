@@ -14,7 +14,7 @@ namespace {
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct PtcLayout {
-    size_t a0, a1, a2, a3, g3, g2, g1, g0, partials, grad, scal, e, t, ae, total;
+    size_t a0, a1, a2, a3, g3, g2, g1, g0, partials, grad, scal, e, t, ae, src, total;
 };
 
 PtcLayout ptc_layout(const Geom &g) {
@@ -42,6 +42,7 @@ PtcLayout ptc_layout(const Geom &g) {
     L.e = take(h32);
     L.t = take(h32);
     L.ae = take(h32);
+    L.src = take(h32);  // the training step's current source as a one-column field
     L.total = off;
     return L;
 }
@@ -211,14 +212,17 @@ hisq_status hisq_ptc_train_step(hisq_context *ctx, const hisq_lattice *lat, doub
     const float2 *w = static_cast<const float2 *>(w_f32);
     double2 *grad = P.at<double2>(P.L.grad);
     double *scal = P.at<double>(P.L.scal);  // [0] <x, b>, [1] loss, [2] <e, A e>
-    const size_t c32 = field_bytes(P.g, HISQ_FP32, 1), c64 = field_bytes(P.g, HISQ_FP64, 1);
+    const size_t c64 = field_bytes(P.g, HISQ_FP64, 1);
     const DslashShape shape = pick_shape(ctx, P.g, HISQ_FP32, HISQ_FP32, 1);
     hipError_t e = ptc_fill_f64(reinterpret_cast<double *>(grad), 2 * PTC_NW, P.st);
     if (e == hipSuccess) e = ptc_fill_f64(scal, 16, P.st);
+    const void *src = P.at<void>(P.L.src);
     for (int k = 0; k < batch && e == hipSuccess; ++k) {
-        const char *src = static_cast<const char *>(src_f32) + k * c32;
+        // source k: column k of the batch-column FP32 field src_f32
+        e = launch_copy_col(P.g.vh, HISQ_FP32, batch, k, src_f32, P.at<void>(P.L.src), P.st);
         const char *sol = static_cast<const char *>(sol_f64) + k * c64;
-        e = forward(P, w, src, nullptr);
+        if (e == hipSuccess)
+            e = forward(P, w, src, nullptr);
         if (e == hipSuccess)
             e = ptc_xb(P.g, sol, src, P.at<double>(P.L.partials), scal + 0, P.st);
         if (e == hipSuccess)

@@ -36,6 +36,54 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
+// The same for the column-pair vector kernels, whose blocks of 2 b threads
+// cover the b sites of a b-thread block for two columns: lane l of wave w
+// holds site 32 (w & 1) + (l >> 1) of the block's 64-site group w >> 1 for
+// column l & 1.  The additions are those of block_sum over the b sites of
+// one column, in the same order (the sites 32 apart first, then the
+// butterfly over the remaining five site bits, then the 64-site groups in
+// order), so a column's partials are bitwise the ones of a one-column block.
+// The sum of the even lanes' column is valid in thread 0, of the odd lanes'
+// in thread 1.  `lds` must hold (blockDim.x / 128) * 64 * NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_pair(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ngroups = blockDim.x >> 7;
+    const int g = wave >> 1;
+    if (wave & 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            lds[(g * 64 + lane) * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (!(wave & 1)) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            v[k] += lds[(g * 64 + lane) * NV + k];
+#pragma unroll
+            for (int o = 32; o >= 2; o >>= 1)
+                v[k] += __shfl_xor(v[k], o, 64);
+        }
+    }
+    __syncthreads();
+    if (!(wave & 1) && lane < 2) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            lds[(g * 2 + lane) * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < ngroups; ++q)
+                s += lds[(q * 2 + threadIdx.x) * NV + k];
+            v[k] = s;
+        }
+    }
+}
+
 // Sums of NV values (NV a power of two <= 64) over the wavefront with
 // log2(NV) halving exchanges: at offset 32, 16, ... each lane gives the
 // partner half of its remaining values and keeps the other half, so NV/2 +

@@ -226,10 +226,17 @@ def empty_links(lat, prec, device="cuda") -> torch.Tensor:
     return torch.empty(hisq_links_bytes(lat, prec), dtype=torch.uint8, device=device)
 
 
+def packed_bytes(lat, prec, nrhs: int) -> int:
+    """Bytes of nrhs packed fields stored as groups of HISQ_MAX_RHS columns
+    one after another (the last group holding the rest)."""
+    full, rest = divmod(int(nrhs), HISQ_MAX_RHS)
+    return full * hisq_field_bytes(lat, prec, HISQ_MAX_RHS) + (hisq_field_bytes(lat, prec, rest) if rest else 0)
+
+
 def empty_field(lat, prec, nrhs: int = 1, device="cuda") -> torch.Tensor:
-    """Room for nrhs packed fields (any number; the C calls take at most
-    HISQ_MAX_RHS at a time)."""
-    return torch.empty(int(nrhs) * hisq_field_bytes(lat, prec, 1), dtype=torch.uint8, device=device)
+    """Room for nrhs packed fields (any number, as groups of HISQ_MAX_RHS
+    columns; the C calls take at most HISQ_MAX_RHS at a time)."""
+    return torch.empty(packed_bytes(lat, prec, nrhs), dtype=torch.uint8, device=device)
 
 
 def hisq_pack_links(lat, prec, fat_c128: torch.Tensor, naik_c128: torch.Tensor, packed: torch.Tensor,
@@ -618,17 +625,18 @@ def pack_links_from_host(lat, prec, fat, naik, ctx=None) -> torch.Tensor:
 
 
 def pack_field_from_host(lat, prec, half, ctx=None) -> torch.Tensor:
-    """Any number of fields: packed column by column in groups of HISQ_MAX_RHS
-    (the packed layout of n fields is the n single fields one after another)."""
+    """Any number of fields, packed in groups of HISQ_MAX_RHS columns one
+    after another (packed_bytes)."""
     half = torch.as_tensor(half, dtype=torch.complex128)
     if half.dim() == 2:
         half = half[None]
     nrhs = half.shape[0]
-    one = hisq_field_bytes(lat, prec, 1)
-    packed = torch.empty(nrhs * one, dtype=torch.uint8, device="cuda")
+    packed = torch.empty(packed_bytes(lat, prec, nrhs), dtype=torch.uint8, device="cuda")
     for k in range(0, nrhs, HISQ_MAX_RHS):
         n = min(HISQ_MAX_RHS, nrhs - k)
-        hisq_pack_field(lat, prec, n, half[k:k + n].contiguous().cuda(), packed[k * one:(k + n) * one], ctx=ctx)
+        o = packed_bytes(lat, prec, k)
+        hisq_pack_field(lat, prec, n, half[k:k + n].contiguous().cuda(),
+                        packed[o:o + hisq_field_bytes(lat, prec, n)], ctx=ctx)
     return packed
 
 
@@ -636,10 +644,10 @@ def unpack_field_to_host(lat, prec, packed, nrhs: int = 1, ctx=None):
     vol = 1
     for d in lat.dims:
         vol *= d
-    one = hisq_field_bytes(lat, prec, 1)
     out = torch.empty((nrhs, vol // 2, 3), dtype=torch.complex128, device="cuda")
     for k in range(0, nrhs, HISQ_MAX_RHS):
         n = min(HISQ_MAX_RHS, nrhs - k)
-        hisq_unpack_field(lat, prec, n, packed[k * one:(k + n) * one], out[k:k + n], ctx=ctx)
+        o = packed_bytes(lat, prec, k)
+        hisq_unpack_field(lat, prec, n, packed[o:o + hisq_field_bytes(lat, prec, n)], out[k:k + n], ctx=ctx)
     torch.cuda.synchronize()
     return out.cpu().numpy()

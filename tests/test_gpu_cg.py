@@ -70,7 +70,7 @@ def test_mixed_precision_reliable_update_cg(gpu_lib, inner, m):
     assert info[0]["reliable_updates"] >= 1
 
 
-@pytest.mark.parametrize("inner,nrhs", [("fp64", 3), ("fp32", 16)])
+@pytest.mark.parametrize("inner,nrhs", [("fp64", 3), ("fp32", 16), ("fp32", 5)])
 def test_multi_rhs_cg(gpu_lib, inner, nrhs):
     h = gpu_lib
     w = gen.workload_smooth((8, 4, 8, 8), 42, -1, 0.3, nrhs)

@@ -62,6 +62,32 @@ def test_pack_unpack_field_format(gpu_lib, fields, prec):
     np.testing.assert_array_equal(back, O.quantize_field(src, prec))
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5])
+def test_fp32_field_pair_layout(gpu_lib, fields, nrhs):
+    """The packed FP32 layout as the header states it, written out here from
+    that description: one column is [colour][site] of {re, im}; in a field of
+    several columns, columns 2j and 2j + 1 share 16-byte records
+    {re, im of 2j, re, im of 2j + 1}, [pair][colour][site], the second slot
+    of the last pair unused for an odd number of columns."""
+    h = gpu_lib
+    w = fields((6, 4, 8, 10), -1, 5)
+    lat = h.lattice(w["dims"], w["t_bc"])
+    src = w["src"][:nrhs]
+    vh = src.shape[1]
+    cols = nrhs + (nrhs % 2) if nrhs >= 2 else 1
+    assert h.hisq_field_bytes(lat, "fp32", nrhs) == cols * vh * 24
+    raw = h.pack_field_from_host(lat, "fp32", src).view(torch.float32).cpu().numpy()
+    q = src.astype(np.complex64)
+    if nrhs == 1:
+        want = np.stack([q[0].real.T, q[0].imag.T], axis=-1).reshape(-1)   # [colour][site][re, im]
+        np.testing.assert_array_equal(raw, want)
+        return
+    rec = raw.reshape(cols // 2, 3, vh, 4)                                  # [pair][colour][site][4]
+    for r in range(nrhs):
+        np.testing.assert_array_equal(rec[r // 2, :, :, 2 * (r % 2)], q[r].real.T)
+        np.testing.assert_array_equal(rec[r // 2, :, :, 2 * (r % 2) + 1], q[r].imag.T)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16n"])
 def test_pack_unpack_links_format(gpu_lib, fields, prec):
     h = gpu_lib
