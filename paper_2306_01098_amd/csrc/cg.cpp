@@ -91,7 +91,7 @@ Layout make_layout(const Geom &g, int inner, int nrhs, int nshift) {
 // F_OFF0 + j: column j inactive (the fused single-reduction step's launch gate)
 enum { F_SKIP = 0, F_NOPEND = 2, F_TR0 = 16, F_OFF0 = 32 };
 // scal[] slots
-enum { S_TMP = 0 };
+enum { S_TMP = 0, S_B = 16, S_R = 32 };  // S_B + j: ||b_j||^2, S_R + j: ||b_j - A x_j||^2
 
 struct Solver {
     hisq_context *ctx = nullptr;
@@ -255,31 +255,97 @@ double now_s() {
 }
 
 // A private non-blocking stream ordered after the caller's stream (graphs
-// cannot be captured on the legacy default stream).
+// cannot be captured on the legacy default stream).  Each thread keeps one
+// such stream and event per device for the life of the process (a solve
+// synchronizes its stream before it returns, so the next solve of the thread
+// finds it idle); creating and destroying them per solve cost about 0.1 ms.
 struct StreamGuard {
     hipStream_t caller = nullptr, own = nullptr;
     hipEvent_t ev = nullptr;
     hipError_t init(hipStream_t c) {
         caller = c;
-        hipError_t e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        struct Slot {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+        };
+        static thread_local std::vector<Slot> *slots = new std::vector<Slot>();
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess)
             return e;
-        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e != hipSuccess)
-            return e;
+        if ((int)slots->size() <= dev)
+            slots->resize(dev + 1);
+        Slot &sl = (*slots)[dev];
+        if (!sl.st) {
+            e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                sl.st = nullptr;
+                return e;
+            }
+        }
+        if (!sl.ev) {
+            e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                sl.ev = nullptr;
+                return e;
+            }
+        }
+        own = sl.st;
+        ev = sl.ev;
         e = hipEventRecord(ev, caller);
         if (e != hipSuccess)
             return e;
         return hipStreamWaitEvent(own, ev, 0);
     }
     ~StreamGuard() {
-        if (own) {
+        if (own)
             (void)hipStreamSynchronize(own);
-            (void)hipStreamDestroy(own);
-        }
-        if (ev)
-            (void)hipEventDestroy(ev);
     }
+};
+
+// Instantiated chunk graphs of earlier solves on this thread, reused when a
+// solve repeats every value its launches were captured with (lattice, mass,
+// shifts, links, fields, workspace layout, launch shapes, chunk length): the
+// kernels read the Krylov state and their flags from device memory, so a
+// chunk graph is a function of those values alone.  Eight entries, the least
+// recently used evicted; a solve synchronizes its stream before it returns,
+// so no evicted graph is still running.  Capturing and instantiating a chunk
+// cost 0.1-0.2 ms per solve.
+class ChunkGraphCache {
+  public:
+    static ChunkGraphCache &mine() {
+        static thread_local ChunkGraphCache *c = new ChunkGraphCache();
+        return *c;
+    }
+    hipGraphExec_t find(const std::vector<uint64_t> &key) {
+        for (Entry &en : e_)
+            if (en.key == key) {
+                en.used = ++tick_;
+                return en.exec;
+            }
+        return nullptr;
+    }
+    void put(const std::vector<uint64_t> &key, hipGraphExec_t exec) {
+        if (e_.size() >= kMax) {
+            size_t lru = 0;
+            for (size_t k = 1; k < e_.size(); ++k)
+                if (e_[k].used < e_[lru].used)
+                    lru = k;
+            (void)hipGraphExecDestroy(e_[lru].exec);
+            e_.erase(e_.begin() + (long)lru);
+        }
+        e_.push_back(Entry{key, exec, ++tick_});
+    }
+
+  private:
+    static constexpr size_t kMax = 8;
+    struct Entry {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    std::vector<Entry> e_;
+    uint64_t tick_ = 0;
 };
 
 struct GraphChunk {
@@ -379,22 +445,34 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     const int nb = cg_vec_blocks(g.vh);  // <r, r> partials per column
     double *rr = S.at<double>(L.rr);
     bool breakdown = false;
+    // ||b_j||^2, and r_j = b_j - A x_j with its <r, r> partials where the
+    // first scalar step reads them and its FP64 norm, for every column; one
+    // read-back of the norms for the decisions below
     for (int j = 0; j < nrhs; ++j) {
-        if ((s = S.norm2(C.b[j], &bnorm2[j])) != HISQ_OK)
-            return s;
-        // r_j = b_j - A x_j, its <r, r> partials where the first scalar step
-        // reads them, and the FP64 norm for the decisions below
-        if ((s = S.apply_m64(C.sigma[j], C.x[j], S.at<void>(L.ax))) != HISQ_OK)
-            return s;
-        hipError_t e = launch_residual_cols(g.vh, 1, nrhs, j, L.fs, C.b[j], S.at<void>(L.ax), rs,
-                                            rr + (size_t)j * nb, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                            nullptr, nullptr, st);
+        hipError_t e = launch_norm2(g.vh, C.b[j], S.partials(), S.scal() + S_B + j, st);
         if (e == hipSuccess)
-            e = launch_sum_partials(rr + (size_t)j * nb, 1, nb, S.scal() + S_TMP, 1, nullptr, st);
+            e = S.m64(C.sigma[j], C.x[j], S.at<void>(L.ax), nullptr);
+        if (e == hipSuccess)
+            e = launch_residual_cols(g.vh, 1, nrhs, j, L.fs, C.b[j], S.at<void>(L.ax), rs, rr + (size_t)j * nb,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        if (e == hipSuccess)
+            e = launch_sum_partials(rr + (size_t)j * nb, 1, nb, S.scal() + S_R + j, 1, nullptr, st);
         if ((s = S.dev(e, "initial residual")) != HISQ_OK)
             return s;
-        if ((s = S.read_double(S.scal() + S_TMP, &rtrue2[j])) != HISQ_OK)
+    }
+    {
+        double norms[S_R + HISQ_MAX_RHS - S_B];
+        hipError_t e = hipMemcpyAsync(norms, S.scal() + S_B, sizeof(norms), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if ((s = S.dev(e, "initial residual norms")) != HISQ_OK)
             return s;
+        for (int j = 0; j < nrhs; ++j) {
+            bnorm2[j] = norms[j];
+            rtrue2[j] = norms[S_R - S_B + j];
+        }
+    }
+    for (int j = 0; j < nrhs; ++j) {
         CgScalars c{};
         c.rho = rtrue2[j];
         c.rmax2 = rtrue2[j];
@@ -523,17 +601,22 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     // iterations between blocks: a flagged column idles until the next one.
     // Chunks of about 0.5 ms (measured: longer chunks overshoot more at the
     // end of a solve).  FP64 iterations flag only at convergence, so they need
-    // one block per chunk.
+    // one block per chunk.  Near the end of a solve (the residual trend
+    // predicts fewer iterations than a chunk) short tail chunks of `unit`
+    // iterations and one block follow instead, so the iterations launched
+    // after convergence are at most those of two tails.
     const int unit = delta > 0.0 ? 4 : 8;
     const int chunk = unit * std::max(1, (int)std::lround(500.0 / (unit * S.iter_us)));
     const int check = delta > 0.0 ? 4 : chunk;
     // a chunk ends with a check block, so the first scalar step of every
-    // chunk, and the one after each block, decides the waiting columns
-    auto chunk_eager = [&]() -> hipError_t {
+    // chunk, and the one after each block, decides the waiting columns; every
+    // chunk has an even number of iterations, so each one starts from state
+    // buffer 0 and partial set 0 of the fused step
+    auto run_iters = [&](int n, int chk) -> hipError_t {
         hipError_t e = hipSuccess;
-        for (int k = 0; k < chunk && e == hipSuccess; ++k) {
-            e = S.iteration_sr(vp, C.sigma, nrhs, k % check == 0 ? 1 : 0, fused, k);
-            if (e == hipSuccess && (k + 1) % check == 0)
+        for (int k = 0; k < n && e == hipSuccess; ++k) {
+            e = S.iteration_sr(vp, C.sigma, nrhs, k % chk == 0 ? 1 : 0, fused, k);
+            if (e == hipSuccess && (k + 1) % chk == 0)
                 e = tr_block();
         }
         return e;
@@ -542,18 +625,66 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
     bool any_active = false;
     for (int j = 0; j < nrhs; ++j)
         any_active |= hs[j].active != 0;
-    GraphChunk gc;
-    bool use_graph = false;
-    if (any_active) {
+    // the graphs of the chunk and of the tail, from this thread's cache when a
+    // solve with the same launch values ran before
+    std::vector<uint64_t> key;
+    {
+        auto add = [&](uint64_t v) { key.push_back(v); };
+        auto addp = [&](const void *q) { add((uint64_t)(uintptr_t)q); };
+        auto addd = [&](double d) {
+            uint64_t u;
+            std::memcpy(&u, &d, sizeof u);
+            add(u);
+        };
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        for (int v : {dev, g.nx, g.ny, g.nz, g.nt, g.t_bc, nrhs, S.lp_in, L.fs, chunk, check, unit, fused ? 1 : 0,
+                      packed ? 1 : 0, L.nblk_max})
+            add((uint64_t)(int64_t)v);
+        addd(S.mass);
+        for (int j = 0; j < nrhs; ++j) {
+            addd(C.sigma[j]);
+            addp(C.b[j]);
+            addp(C.x[j]);
+        }
+        addp(S.links64);
+        addp(S.links_in);
+        addp(S.ws);
+        for (size_t o : {L.state, L.state2, L.shifts, L.ms, L.flags, L.scal, L.partials, L.dpart, L.rr, L.rspart,
+                         L.pspart, L.r, L.p, L.q, L.w, L.t, L.ps, L.ax, L.t64, L.t64m, L.axm, L.total, L.part_set})
+            add(o);
+        for (const DslashShape &sh : {S.shape_in, S.shape64, S.shape64m})
+            for (int v : {sh.variant, sh.nin, sh.block, sh.xcd_remap})
+                add((uint64_t)(int64_t)v);
+    }
+    hipGraphExec_t exec_chunk = nullptr, exec_tail = nullptr;
+    auto graph_of = [&](int n, int chk, int tag) -> hipGraphExec_t {
+        std::vector<uint64_t> k = key;
+        k.push_back((uint64_t)tag);
+        ChunkGraphCache &cache = ChunkGraphCache::mine();
+        if (hipGraphExec_t x = cache.find(k))
+            return x;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = chunk_eager();
-            e = hipStreamEndCapture(st, &gc.graph);
+            const hipError_t le = run_iters(n, chk);
+            e = hipStreamEndCapture(st, &graph);
             if (le == hipSuccess && e == hipSuccess)
-                e = hipGraphInstantiate(&gc.exec, gc.graph, nullptr, nullptr, 0);
-            use_graph = le == hipSuccess && e == hipSuccess;
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (le != hipSuccess || e != hipSuccess)
+                exec = nullptr;
         }
+        if (graph)
+            (void)hipGraphDestroy(graph);
         (void)hipGetLastError();
+        if (exec)
+            cache.put(k, exec);
+        return exec;
+    };
+    if (any_active) {
+        exec_chunk = graph_of(chunk, check, 0);
+        exec_tail = graph_of(unit, unit, 1);
     }
 
     PinnedSlots pin;
@@ -572,31 +703,36 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
         if ((s = S.dev(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming), "event")) != HISQ_OK)
             return s;
 
-    long launched = 0, read = 0;
-    auto launch_chunk = [&]() -> hipError_t {
-        hipError_t e = use_graph ? hipGraphLaunch(gc.exec, st) : chunk_eager();
+    long launched = 0, read = 0, launched_iters = 0;
+    auto launch_chunk = [&](bool tail) -> hipError_t {
+        const int n = tail ? unit : chunk;
+        hipGraphExec_t x = tail ? exec_tail : exec_chunk;
+        hipError_t e = x ? hipGraphLaunch(x, st) : run_iters(n, tail ? unit : check);
         if (e == hipSuccess)
             e = hipMemcpyAsync(pin.slot((int)launched), dst, sizeof(CgScalars) * nrhs, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipEventRecord(ev[launched % PinnedSlots::N], st);
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
             ++launched;
+            launched_iters += n;
+        }
         return e;
     };
     // every real iteration advances some column's count, and a column that
     // keeps failing its true-residual check still advances once per block
-    const long max_chunks = (long)max_iter * check / chunk + 4;
+    // (at least one per `check` iterations, chunks and tails alike)
+    const long max_launch_iters = (long)max_iter * check + 4L * chunk;
     std::vector<double> prev_rho(nrhs, 0.0);
     std::vector<int> prev_it(nrhs, 0);
     bool near_end = false;
     hipError_t e = hipSuccess;
     if (any_active)
-        e = launch_chunk();
+        e = launch_chunk(false);
     bool finished = !any_active;
     while (!finished && e == hipSuccess) {
-        // queue the next chunk while this one runs, unless this one may be the last
-        if (launched == read + 1 && launched < max_chunks && !near_end)
-            e = launch_chunk();
+        // queue the next chunk (a tail near the end) while this one runs
+        if (launched == read + 1 && launched_iters < max_launch_iters)
+            e = launch_chunk(near_end);
         if (e == hipSuccess)
             e = hipEventSynchronize(ev[read % PinnedSlots::N]);
         if (e != hipSuccess)
@@ -620,11 +756,12 @@ static hisq_status run_cg(Solver &S, const Columns &C, int nrhs, int max_iter, d
             prev_rho[j] = c.rho;
             prev_it[j] = c.iters;
         }
-        near_end = worst < chunk;
+        // the queued chunk still runs: near the end if fewer than two chunks remain
+        near_end = worst < 2.0 * chunk;
         if (!finished && launched == read) {
-            if (launched >= max_chunks)
+            if (launched_iters >= max_launch_iters)
                 break;
-            e = launch_chunk();
+            e = launch_chunk(near_end);
         }
     }
     if (e == hipSuccess)
