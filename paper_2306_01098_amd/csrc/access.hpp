@@ -324,6 +324,12 @@ template <> struct FieldIO<HISQ_FP32> {
         }
     }
     template <typename A>
+    __device__ __forceinline__ static void store_colour_pair(void *f, int vh, int j, int i, int c, cplx<A> v0,
+                                                             cplx<A> v1) {
+        reinterpret_cast<float4 *>(f)[((size_t)j * 3 + c) * vh + i] =
+            make_float4((float)v0.re, (float)v0.im, (float)v1.re, (float)v1.im);
+    }
+    template <typename A>
     __device__ __forceinline__ static void store_pair(void *f, int vh, int j, int i, const cplx<A> v0[3],
                                                       const cplx<A> v1[3]) {
         float4 *p = reinterpret_cast<float4 *>(f) + (size_t)j * 3 * vh + i;

@@ -194,10 +194,7 @@ template <int LP, int FP, int NIN, typename A, bool NT>
 __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int vh, int ilink, const void *in,
                                          int ipsi, int ncol, int r0, int nr, int f) {
     LinkIO<LP>::template load<NT>(blk, vh, ilink, b.m, f);
-#pragma unroll
-    for (int r = 0; r < NIN; ++r)
-        if (r < nr)
-            FieldIO<FP>::template load<A>(in, vh, ncol, r0 + r, ipsi, b.v[r]);
+    load_group<FP, NIN, A>(in, vh, ncol, r0, nr, ipsi, b.v);
 }
 
 // The nr (<= NIN) columns r0 .. r0 + nr - 1 of site i of an ncol-column
@@ -530,12 +527,8 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
     const Site s = site_coords(prm.g, prm.out_parity, i);
     // y of the epilogue is loaded with the first hops, not after them
     cplx<A> yv[NIN][3];
-    if (EPI != EPI_PLAIN) {
-#pragma unroll
-        for (int r = 0; r < NIN; ++r)
-            if (r < nr)
-                FieldIO<FP>::template load<A>(prm.y, prm.g.vh, prm.nrhs, r0 + r, i, yv[r]);
-    }
+    if (EPI != EPI_PLAIN)
+        load_group<FP, NIN, A>(prm.y, prm.g.vh, prm.nrhs, r0, nr, i, yv);
     cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
     dslash_direction<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, s, mu, prm.nrhs, r0, nr,
@@ -555,17 +548,35 @@ __global__ void __launch_bounds__(256) dslash_dir_kernel(const DslashParams prm)
         if (r < nr) {
             const double d = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
             dot[r] = mu == 0 ? d : 0.0;  // one lane of the quad counts the site
-            if constexpr (FP == HISQ_FP16N) {
-                if (mu == 0)  // one 16-byte record holds the whole site
-                    FieldIO<FP>::template store<A>(prm.out, prm.g.vh, prm.nrhs, r0 + r, i, acc[r]);
-            } else {
-                // lane mu < 3 writes colour mu (static indices keep acc in registers)
+        }
+    }
+    if constexpr (FP == HISQ_FP16N) {
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr && mu == 0)  // one 16-byte record holds the whole site
+                FieldIO<FP>::template store<A>(prm.out, prm.g.vh, prm.nrhs, r0 + r, i, acc[r]);
+    } else if constexpr (FP == HISQ_FP32 && NIN % 2 == 0) {
+        // lane mu < 3 writes colour mu of both slots of each pair (the unused
+        // slot of an odd last column gets zero)
+#pragma unroll
+        for (int r = 0; r < NIN; r += 2)
+            if (r < nr) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (mu == c)
+                        FieldIO<FP>::template store_colour_pair<A>(prm.out, prm.g.vh, (r0 + r) >> 1, i, c, acc[r][c],
+                                                                   acc[r + 1][c]);
+            }
+    } else {
+        // lane mu < 3 writes colour mu (static indices keep acc in registers)
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     if (mu == c)
                         FieldIO<FP>::template store_colour<A>(prm.out, prm.g.vh, prm.nrhs, r0 + r, i, c, acc[r][c]);
             }
-        }
     }
     }
     if (EPI == EPI_AXPY_DOT)
