@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "api_util.hpp"
@@ -405,17 +407,47 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
         return err;
     };
 
-    // state read-back into pinned memory, a second chunk queued meanwhile
+    // state read-back into pinned memory, a second chunk queued meanwhile;
+    // the pinned buffers are kept for the life of the process and reused by
+    // later calls (allocating pinned memory per call took about 0.1 ms)
     struct Pinned {
         CgScalars *p = nullptr;
+        size_t bytes = 0;
         hipEvent_t ev[2] = {nullptr, nullptr};
+        static std::mutex &mu() {
+            static std::mutex m;
+            return m;
+        }
+        static std::vector<std::pair<void *, size_t>> &pool() {
+            static std::vector<std::pair<void *, size_t>> v;
+            return v;
+        }
+        hipError_t take(size_t need) {
+            std::lock_guard<std::mutex> lk(mu());
+            auto &v = pool();
+            for (size_t k = 0; k < v.size(); ++k)
+                if (v[k].second >= need) {
+                    p = static_cast<CgScalars *>(v[k].first);
+                    bytes = v[k].second;
+                    v.erase(v.begin() + (long)k);
+                    return hipSuccess;
+                }
+            bytes = std::max(need, (size_t)64 << 10);
+            void *q = nullptr;
+            const hipError_t err = hipHostMalloc(&q, bytes, hipHostMallocDefault);
+            p = err == hipSuccess ? static_cast<CgScalars *>(q) : nullptr;
+            return err;
+        }
         ~Pinned() {
             for (hipEvent_t x : ev)
                 if (x) (void)hipEventDestroy(x);
-            if (p) (void)hipHostFree(p);
+            if (p) {
+                std::lock_guard<std::mutex> lk(mu());
+                pool().emplace_back(p, bytes);
+            }
         }
     } pin;
-    e = hipHostMalloc(reinterpret_cast<void **>(&pin.p), sizeof(CgScalars) * n * 2, hipHostMallocDefault);
+    e = pin.take(sizeof(CgScalars) * n * 2);
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&pin.ev[k], hipEventDisableTiming);
     if (e != hipSuccess)

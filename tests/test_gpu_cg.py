@@ -202,3 +202,24 @@ def test_multi_rhs_zero_column_and_iteration_limit(gpu_lib):
     st, info = h.hisq_cg(lat, m, l64, lin, "fp32", nrhs, b, x, 1e-10, 5, ws)
     assert st == h.NOT_CONVERGED
     assert [i["iterations"] for i in info] == [5, 0, 5, 5]
+
+
+def test_repeated_solves_on_the_same_buffers(gpu_lib):
+    """Solves repeated on the same buffers reuse the captured iteration
+    graphs when every launch value repeats, and capture new ones when one
+    changes (here the mass, the inner precision's links and the column
+    count): each solve must still meet the oracle's FP64 true residual."""
+    h = gpu_lib
+    w = gen.workload_haar((8, 8, 4, 8), 47, -1, 2)
+    lat = h.lattice(w["dims"], w["t_bc"])
+    l64 = h.pack_links_from_host(lat, "fp64", w["fat"], w["naik"])
+    l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
+    b = h.pack_field_from_host(lat, "fp64", w["src"])
+    x = h.empty_field(lat, "fp64", 2)
+    ws = h.empty_workspace(h.hisq_cg_workspace_bytes(lat, "fp32", 2, 0))
+    for mass, nrhs, tol in ((0.1, 2, 1e-10), (0.1, 2, 1e-10), (0.2, 2, 1e-10), (0.1, 1, 1e-9), (0.1, 2, 1e-11)):
+        x.zero_()
+        st, info = h.hisq_cg(lat, mass, l64, l32, "fp32", nrhs, b, x, tol, 20000, ws)
+        assert st == h.OK, (mass, nrhs, tol, info)
+        res, _ = oracle_residuals(h, w, lat, x, nrhs, mass, w["src"][:nrhs])
+        assert max(res) <= tol, (mass, nrhs, tol, res)
