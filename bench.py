@@ -466,10 +466,10 @@ def oracle_cg_seconds_per_iteration(O, w, mass, n=4):
 
 def cpu_baseline(gen, w, dims, t_bc, mass, bytes64, legs, inputs):
     """The oracle on the host cores: FP64 D_oe throughput at 32^3x8 (all
-    threads, and one thread in a child process), CG to 1e-10 for the 32^3x8
-    and 8^4 workloads, and estimates for the 48^3x12 per-shift solves and the
-    64 sequential batch solves (measured oracle CG time per iteration x the
-    GPU solves' iteration counts)."""
+    threads, and one thread), CG to 1e-10 for the 32^3x8 and 8^4 workloads,
+    and estimates for the 48^3x12 per-shift solves, the 64 sequential batch
+    solves and the plain CG on two 32^4 held-out sources (measured oracle CG
+    time per iteration x the GPU solves' iteration counts)."""
     import numpy as np
     from oracle import hisq as O
     s0 = w["src"][0]
@@ -536,8 +536,19 @@ def cpu_baseline(gen, w, dims, t_bc, mass, bytes64, legs, inputs):
             "oracle_cg_ms_per_iteration": {"x".join(map(str, k)): round(v * 1e3, 3) for k, v in per_dims.items()},
             "how": "oracle CG seconds per iteration on each lattice size (an 8-iteration solve, timed) x the "
                    "iterations of the GPU's one-by-one solve of each problem"}
-    if est:
-        out["estimates"] = est
+    # 32^4 (the PTC workload): plain FP64 CG on 2 held-out sources, from the
+    # oracle's CG time per iteration at 32^3x8 scaled by the volume (4x) and
+    # the iterations the GPU's plain FP64 CG takes there (the w5 leg when it
+    # ran, else the 602 it measured on these inputs)
+    per32 = cgcpu["32^3x8_m0.01"]["seconds"] / max(1, cgcpu["32^3x8_m0.01"]["iterations"])
+    its5 = [602, 602]
+    if "w5" in legs:
+        its5 = legs["w5"]["fp64_cg"]["iterations"][:2]
+    est["32^4_plain_cg_2_held_out"] = {
+        "seconds_estimate": round(per32 * 4 * sum(its5), 1), "iterations": its5,
+        "how": "oracle CG seconds per iteration at 32^3x8 (the solve timed above) x 4 (the volume ratio) x the "
+               "iterations of plain FP64 CG on each of the two 32^4 held-out sources (GPU w5 leg)"}
+    out["estimates"] = est
     return out
 
 

@@ -721,7 +721,35 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
     // blockDim = LDS_BAND * hx threads and NIN * 3 * nrow * hx elements, so
     // each thread copies at most PER of them; all its loads are issued
     // before the first LDS store
-    {
+    // FP32 fields with NIN even: whole column pairs, one 16-byte record per
+    // (pair, colour, site), staged as such
+    constexpr bool PAIRS = FP == HISQ_FP32 && NIN % 2 == 0;
+    if constexpr (PAIRS) {
+        constexpr int PER = ((NIN / 2) * 3 * (LDS_BAND + 2 * LDS_HALO) + LDS_BAND - 1) / LDS_BAND;
+        const int per_rc = nrow * g.hx;
+        const int total = ((nr + 1) / 2) * 3 * per_rc;
+        const nt_f4 *src = reinterpret_cast<const nt_f4 *>(prm.in);
+        nt_f4 *stage4 = reinterpret_cast<nt_f4 *>(lds_raw);
+        nt_f4 v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            // past the staged records: the group's first record, loaded and
+            // not stored (unconditional loads keep v in registers)
+            const int e0 = threadIdx.x + j * blockDim.x;
+            const int e = e0 < total ? e0 : 0;
+            const int pc = e / per_rc, rem = e - pc * per_rc;
+            const int row = rem / g.hx, xh = rem - row * g.hx;
+            int gy = y0 - LDS_HALO + row;
+            gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+            v[j] = src[((size_t)(r0 / 2) * 3 + pc) * g.vh + plane + gy * g.hx + xh];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + j * blockDim.x;
+            if (e < total)
+                stage4[e] = v[j];
+        }
+    } else {
         constexpr int PER = (NIN * 3 * (LDS_BAND + 2 * LDS_HALO) + LDS_BAND - 1) / LDS_BAND;
         const int per_rc = nrow * g.hx;
         const int total = nr * 3 * per_rc;
@@ -729,18 +757,19 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
         E v[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int e = threadIdx.x + j * blockDim.x;
-            if (e < total) {
-                const int rc = e / per_rc, rem = e - rc * per_rc;
-                const int row = rem / g.hx, xh = rem - row * g.hx;
-                int gy = y0 - LDS_HALO + row;
-                gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-                const int site = plane + gy * g.hx + xh;
-                if constexpr (FP == HISQ_FP32)
-                    v[j] = src[f32_index(g.vh, prm.nrhs, r0 + rc / 3, rc % 3, site)];
-                else
-                    v[j] = src[(size_t)(r0 * 3 + rc) * g.vh + site];
-            }
+            // past the staged elements: the group's first element, loaded and
+            // not stored (unconditional loads keep v in registers)
+            const int e0 = threadIdx.x + j * blockDim.x;
+            const int e = e0 < total ? e0 : 0;
+            const int rc = e / per_rc, rem = e - rc * per_rc;
+            const int row = rem / g.hx, xh = rem - row * g.hx;
+            int gy = y0 - LDS_HALO + row;
+            gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+            const int site = plane + gy * g.hx + xh;
+            if constexpr (FP == HISQ_FP32)
+                v[j] = src[f32_index(g.vh, prm.nrhs, r0 + rc / 3, rc % 3, site)];
+            else
+                v[j] = src[(size_t)(r0 * 3 + rc) * g.vh + site];
         }
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -770,10 +799,7 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
         LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m, h.f);
         const int mu = k >> 2;
         if (mu >= 2) {
-#pragma unroll
-            for (int r = 0; r < NIN; ++r)
-                if (r < nr)
-                    FieldIO<FP>::template load<A>(prm.in, g.vh, prm.nrhs, r0 + r, h.ipsi, buf[slot].v[r]);
+            load_group<FP, NIN, A>(prm.in, g.vh, prm.nrhs, r0, nr, h.ipsi, buf[slot].v);
         } else {
             // LDS row and column of the neighbour: x-hops stay in the row,
             // y-hops move rows (the staged rows start at y0 - 3)
@@ -787,14 +813,32 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
                 xn = xn < 0 ? xn + g.nx : (xn >= g.nx ? xn - g.nx : xn);
                 col = xn >> 1;
             }
+            if constexpr (PAIRS) {
+                // every pair slot of the buffer is read (the ones past the
+                // group's columns hold stale values that are never used),
+                // which keeps the vectors in registers
+                const nt_f4 *stage4 = reinterpret_cast<const nt_f4 *>(lds_raw);
 #pragma unroll
-            for (int r = 0; r < NIN; ++r) {
-                if (r < nr) {
+                for (int r = 0; r < NIN; r += 2) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const E e = stage[((r * 3 + c) * nrow + row) * g.hx + col];
+                        const nt_f4 e = stage4[(((r >> 1) * 3 + c) * nrow + row) * g.hx + col];
                         buf[slot].v[r][c].re = (A)e.x;
                         buf[slot].v[r][c].im = (A)e.y;
+                        buf[slot].v[r + 1][c].re = (A)e.z;
+                        buf[slot].v[r + 1][c].im = (A)e.w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NIN; ++r) {
+                    if (r < nr) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const E e = stage[((r * 3 + c) * nrow + row) * g.hx + col];
+                            buf[slot].v[r][c].re = (A)e.x;
+                            buf[slot].v[r][c].im = (A)e.y;
+                        }
                     }
                 }
             }
@@ -825,13 +869,17 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
     }
     double dot[NIN];
 #pragma unroll
-    for (int r = 0; r < NIN; ++r) {
+    for (int r = 0; r < NIN; ++r)
         dot[r] = 0.0;
-        if (r < nr) {
-            dot[r] = epilogue<FP, EPI, A>(prm, r0 + r, i, acc[r]);
-            FieldIO<FP>::template store<A>(prm.out, g.vh, prm.nrhs, r0 + r, i, acc[r]);
-        }
+    if constexpr (EPI != EPI_PLAIN) {
+        cplx<A> yv[NIN][3];
+        load_group<FP, NIN, A>(prm.y, g.vh, prm.nrhs, r0, nr, i, yv);
+#pragma unroll
+        for (int r = 0; r < NIN; ++r)
+            if (r < nr)
+                dot[r] = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
     }
+    store_group<FP, NIN, A>(prm.out, g.vh, prm.nrhs, r0, nr, i, acc);
     if (EPI == EPI_AXPY_DOT)
         dslash_dot_reduce<NIN>(prm, dot, bp);
 }
