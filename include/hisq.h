@@ -487,7 +487,8 @@ hisq_status hisq_fcg(hisq_context *ctx, const hisq_lattice *lat, double mass, co
  *             butterfly shuffles (for small lattices; nin 1 or 2).
  *   nin       right-hand sides per thread sharing each link load (1, 2, 4, 8;
  *             the remaining right-hand sides run as further blocks: the
- *             N_inner x N_outer split of the paper's Sec. 5.1).
+ *             N_inner x N_outer split of the paper's Sec. 5.1; a one-column
+ *             HISQ_FP32 field runs with nin 1).
  *   block     threads per block (64, 128, 256).
  *   xcd_remap block order.  0: blocks in site order (dealt round-robin over
  *             the 8 XCDs); 1: each XCD takes one contiguous 1/8 of the sites
