@@ -299,7 +299,8 @@ size_t hisq_cg_workspace_bytes(const hisq_lattice *lat, hisq_prec inner, int32_t
  *               iteration vectors are FP32 and the solver is reliable-update
  *               mixed-precision CG: x is accumulated in FP64, all inner
  *               products and norms are FP64, and r is replaced by the FP64
- *               b - A x whenever the iterated residual has fallen by 10x.
+ *               b - A x whenever the iterated residual falls below 0.03
+ *               times its largest value since the last replacement.
  *   b, x        packed HISQ_FP64 fields of nrhs columns on the even sites;
  *               x holds the initial guess on entry and the solution on exit.
  *   tol         stop when ||b - A x|| <= tol ||b|| (FP64 true residual).

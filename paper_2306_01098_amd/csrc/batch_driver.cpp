@@ -294,7 +294,7 @@ hisq_status hisq_cg_batch(hisq_context *ctx, int32_t nproblems, const hisq_probl
     if (e == hipSuccess) e = true_residuals(true);
     if (e != hipSuccess)
         return device_fail(e, "batch setup");
-    const double delta = inner == HISQ_FP64 ? 0.0 : 0.1;
+    const double delta = inner == HISQ_FP64 ? 0.0 : RELIABLE_DELTA;
     bool breakdown = false;
     for (int j = 0; j < n; ++j) {
         CgScalars c{};

@@ -1078,7 +1078,7 @@ hisq_status hisq_cg(hisq_context *ctx, const hisq_lattice *lat, double mass, con
         return s;
     // reliable updates whenever the iterated residual fell by 10x (reduced
     // precision); FP64 CG checks the true residual at convergence only
-    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
+    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : RELIABLE_DELTA;
     Columns C{};
     const size_t c64 = field_bytes(S.g, HISQ_FP64, 1);
     for (int j = 0; j < nrhs; ++j) {
@@ -1196,7 +1196,7 @@ static hisq_status multishift_entry(hisq_context *ctx, const hisq_lattice *lat, 
     if ((s = setup_solver(S, ctx, lat, mass, links_f64, links_inner, inner, 1, nshift, ws, ws_bytes, sg.own)) !=
         HISQ_OK)
         return s;
-    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : 0.1;
+    const double delta = field_prec_of(inner) == HISQ_FP64 ? 0.0 : RELIABLE_DELTA;
     return run_multishift(S, nshift, shifts, b, x, tol, max_iter, delta, info, refine);
 }
 

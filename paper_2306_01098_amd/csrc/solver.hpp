@@ -11,6 +11,15 @@
 
 namespace hisq {
 
+// Reliable-update threshold of the mixed-precision solvers: r is replaced by
+// the FP64 true residual once the iterated residual has fallen by this factor
+// since the last replacement.  Each replacement costs two FP64 operator
+// launches; 0.1 (one per decade) -> 0.03 cut the replacements of the 32^3x8
+// solves to 1e-10 from 9 to 6 with unchanged iteration counts in every link
+// format (FP16N links 8.1 -> 7.6 ms); at 0.01 the FP16N solve needed two more
+// iterations.
+constexpr double RELIABLE_DELTA = 0.03;
+
 enum {
     FLAG_RUN = 0,       // iterating
     FLAG_CONV = 1,      // iterated residual met the target: check the true residual
