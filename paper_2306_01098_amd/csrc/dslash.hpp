@@ -160,9 +160,21 @@ template <int NIN, typename A> struct HopBuf {
     cplx<A> v[NIN][3];
 };
 
+// Whether column r (< NIN, unrolled) of a group of nr >= 1 columns is there.
+// ONE: the caller knows that the group is one column, and the test folds away,
+// which keeps the loads and their use out of a branch.  A field load in a
+// branch of its own had its binary16 conversion placed beside it in that
+// branch, so every hop of the FP16N one-column kernel waited for all of the
+// next hop's loads before computing the current one (32^3x8 FP16N 14.5 ->
+// 13.9 us, FP64 47.9 -> 46.8 us).  Only the plain one-column site kernel
+// takes it: the FP64 kernel with the fused dot product ran 46 -> 53 us with
+// it, and with several columns the compiler hoisted more loads than the
+// register file holds.
+template <bool ONE> __device__ __forceinline__ constexpr bool has_col(int r, int nr) { return ONE || r < nr; }
+
 // tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b); row 2 of a
 // compressed link (field f) is rebuilt here, after its loads have landed.
-template <int LP, int NIN, typename A>
+template <int LP, int NIN, typename A, bool ONE = false>
 __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, A sg, int nr,
                                           cplx<A> (&tmp)[NIN][3], int f) {
     HopBuf<NIN, A> b = bin;
@@ -170,7 +182,7 @@ __device__ __forceinline__ void hop_apply(const HopBuf<NIN, A> &bin, bool back, 
         LinkIO<LP>::finish(b.m, f);
 #pragma unroll
     for (int r = 0; r < NIN; ++r) {
-        if (r < nr) {
+        if (has_col<ONE>(r, nr)) {
             cplx<A> v[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -202,34 +214,34 @@ __device__ __forceinline__ void hop_load(HopBuf<NIN, A> &b, const char *blk, int
 // 16-byte access per colour (r0 is a multiple of NIN, so the group starts on
 // a pair; the pair of an odd last column has an unused second slot, which
 // is loaded and never used, and stored as zero).
-template <int FP, int NIN, typename A>
+template <int FP, int NIN, typename A, bool ONE = false>
 __device__ __forceinline__ void load_group(const void *f, int vh, int ncol, int r0, int nr, int i,
                                            cplx<A> (&v)[NIN][3]) {
     if constexpr (FP == HISQ_FP32 && NIN % 2 == 0) {
 #pragma unroll
         for (int r = 0; r < NIN; r += 2)
-            if (r < nr)
+            if (has_col<ONE>(r, nr))
                 FieldIO<FP>::template load_pair<A>(f, vh, (r0 + r) >> 1, i, v[r], v[r + 1]);
     } else {
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
-            if (r < nr)
+            if (has_col<ONE>(r, nr))
                 FieldIO<FP>::template load<A>(f, vh, ncol, r0 + r, i, v[r]);
     }
 }
 
-template <int FP, int NIN, typename A>
+template <int FP, int NIN, typename A, bool ONE = false>
 __device__ __forceinline__ void store_group(void *f, int vh, int ncol, int r0, int nr, int i,
                                             const cplx<A> (&v)[NIN][3]) {
     if constexpr (FP == HISQ_FP32 && NIN % 2 == 0) {
 #pragma unroll
         for (int r = 0; r < NIN; r += 2)
-            if (r < nr)
+            if (has_col<ONE>(r, nr))
                 FieldIO<FP>::template store_pair<A>(f, vh, (r0 + r) >> 1, i, v[r], v[r + 1]);
     } else {
 #pragma unroll
         for (int r = 0; r < NIN; ++r)
-            if (r < nr)
+            if (has_col<ONE>(r, nr))
                 FieldIO<FP>::template store<A>(f, vh, ncol, r0 + r, i, v[r]);
     }
 }
@@ -308,7 +320,7 @@ __device__ __forceinline__ HopAddr hop_addr(const Geom &g, int p, const char *li
 // The sixteen hops are software-pipelined: the loads of hop k+1 are issued
 // before hop k is computed, so two hops' worth of link and vector loads are in
 // flight per wavefront instead of one.
-template <int LP, int FP, int NIN, typename A, bool NT>
+template <int LP, int FP, int NIN, typename A, bool NT, bool ONE = false>
 __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *links, const void *in, int i,
                                             int ncol, int r0, int nr, cplx<A> (&acc)[NIN][3]) {
     const Site s = site_coords(g, p, i);
@@ -374,7 +386,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         A sg;
         const HopAddr h = hop_addr<LP, A>(g, p, links, i, s, k, sg);
         LinkIO<LP>::template load<NT>(h.blk, g.vh, h.ilink, buf[slot].m, h.f);
-        load_group<FP, NIN, A>(in, g.vh, ncol, r0, nr, h.ipsi, buf[slot].v);
+        load_group<FP, NIN, A, ONE>(in, g.vh, ncol, r0, nr, h.ipsi, buf[slot].v);
         sgn[slot] = sg;
         back[slot] = h.back;
     };
@@ -384,7 +396,7 @@ __device__ __forceinline__ void dslash_site(const Geom &g, int p, const char *li
         const int cur = k & 1;
         if (k + 1 < 16)
             load(k + 1, cur ^ 1);
-        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp, (k & 3) >> 1);
+        hop_apply<LP, NIN, A, ONE>(buf[cur], back[cur], sgn[cur], nr, tmp, (k & 3) >> 1);
         if ((k & 3) == 3) {
             const int mu = k >> 2;
             const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
@@ -471,6 +483,7 @@ __device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, doubl
 // each link is read once: one group of right-hand sides, FP64 or FP32 links).
 template <int LP, int FP, int NIN, int EPI, bool NT>
 __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm) {
+    constexpr bool ONE = NIN == 1 && EPI == EPI_PLAIN;  // has_col
     using A = typename Prec<LP>::acc;
     if (prm.skip && *prm.skip)
         return;
@@ -488,7 +501,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
         dot[r] = 0.0;
     if (valid) {
         cplx<A> acc[NIN][3];
-        dslash_site<LP, FP, NIN, A, NT>(prm.g, prm.out_parity, prm.links, prm.in, i, prm.nrhs, r0, nr, acc);
+        dslash_site<LP, FP, NIN, A, NT, ONE>(prm.g, prm.out_parity, prm.links, prm.in, i, prm.nrhs, r0, nr, acc);
         if constexpr (EPI != EPI_PLAIN) {
             cplx<A> yv[NIN][3];
             load_group<FP, NIN, A>(prm.y, prm.g.vh, prm.nrhs, r0, nr, i, yv);
@@ -497,7 +510,7 @@ __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm
                 if (r < nr)
                     dot[r] = epilogue_y<EPI, A>(prm, r0 + r, yv[r], acc[r]);
         }
-        store_group<FP, NIN, A>(prm.out, prm.g.vh, prm.nrhs, r0, nr, i, acc);
+        store_group<FP, NIN, A, ONE>(prm.out, prm.g.vh, prm.nrhs, r0, nr, i, acc);
     }
     if (EPI == EPI_AXPY_DOT)
         dslash_dot_reduce<NIN>(prm, dot, bp);
