@@ -12,7 +12,8 @@ namespace hisq {
 // Built-in shapes (measured on MI355X at 32^3x8 and 48^3x12): one thread per
 // site (four lanes per site on lattices too small to fill the chip); with
 // several right-hand sides one thread per site holding four of them (FP16N
-// links: two) in blocks of 256 (FP32 fields) or 128.
+// links: two; FP32 links and fields: eight) in blocks of 256 (FP32 and FP16N
+// fields) or 128 (FP64 fields; eight FP32 rhs).
 DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     // measured on 32^3x8 at one right-hand side and 48^3x12 at 4 and 16:
     // the per-site mapping wins everywhere once the N_outer groups of a site
@@ -56,8 +57,16 @@ DslashShape default_shape(const Geom &g, int lp, int fp, int nrhs) {
     // 16 rhs at 48^3x12, blocks of 64 -> 128: FP32 520 -> 476 us, FP32R12
     // 467 -> 431 us, FP64 995 -> 935 us, FP16N 466 -> 457 us; 128 -> 256 with
     // FP32 fields and FP32-family links: FP32 476-514 -> 473-483 us, FP32R12
-    // 430-465 -> 427-433 us over four boxes (FP64 mixed, 935-1001 -> 970-973)
-    s.block = fp == HISQ_FP32 && lp != HISQ_FP16N ? 256 : 128;
+    // 430-465 -> 427-433 us over four boxes (FP64 mixed, 935-1001 -> 970-973);
+    // FP16N fields 452 -> 433 us
+    s.block = (fp == HISQ_FP32 && lp != HISQ_FP16N) || fp == HISQ_FP16N ? 256 : 128;
+    // FP32 links and fields, whole groups of 8: eight rhs per thread in blocks
+    // of 128 (16 rhs at 48^3x12: 476 -> 460 us; the 16-rhs CG 0.421 -> 0.407
+    // s; FP32R12 links gain nothing from it)
+    if (lp == HISQ_FP32 && fp == HISQ_FP32 && nrhs % 8 == 0) {
+        s.nin = 8;
+        s.block = 128;
+    }
     // z-slab order in 8-row y-bands: 16 rhs at 48^3x12, FP32 606 -> 585 us,
     // FP64 1231 -> 1105 us
     if (g.nz % 8 == 0)
