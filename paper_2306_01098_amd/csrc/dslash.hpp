@@ -782,9 +782,13 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
     s.z = z;
     s.t = t;
     s.x = 2 * xh + ((y + z + t + p) & 1);
-    cplx<A> acc[NIN][3], tmp[NIN][3];
+    cplx<A> acc[NIN][3];
     zero<NIN, A>(acc);
-    zero<NIN, A>(tmp);
+    auto eta = [&](int k) -> A {  // eta_mu(s) of hop k, folded into its sign
+        const int mu = k >> 2;
+        const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
+        return (par & 1) ? (A)-1 : (A)1;
+    };
     HopBuf<NIN, A> buf[2];
     A sgn[2];
     bool back[2];
@@ -838,7 +842,7 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
                 }
             }
         }
-        sgn[slot] = sg;
+        sgn[slot] = sg * eta(k);
         back[slot] = h.back;
     };
     load(0, 0);
@@ -847,20 +851,7 @@ __global__ void __launch_bounds__(256) dslash_lds_kernel(const DslashParams prm)
         const int cur = k & 1;
         if (k + 1 < 16)
             load(k + 1, cur ^ 1);
-        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, tmp, (k & 3) >> 1);
-        if ((k & 3) == 3) {
-            const int mu = k >> 2;
-            const int par = (mu >= 1 ? s.x : 0) + (mu >= 2 ? s.y : 0) + (mu >= 3 ? s.z : 0);
-            const A eta = (par & 1) ? (A)-1 : (A)1;
-#pragma unroll
-            for (int r = 0; r < NIN; ++r)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    acc[r][a].re = fma(eta, tmp[r][a].re, acc[r][a].re);
-                    acc[r][a].im = fma(eta, tmp[r][a].im, acc[r][a].im);
-                    tmp[r][a].re = tmp[r][a].im = (A)0;
-                }
-        }
+        hop_apply<LP, NIN, A>(buf[cur], back[cur], sgn[cur], nr, acc, (k & 3) >> 1);
     }
     double dot[NIN];
 #pragma unroll

@@ -70,6 +70,24 @@ def test_mixed_precision_reliable_update_cg(gpu_lib, inner, m):
     assert info[0]["reliable_updates"] >= 1
 
 
+@pytest.mark.parametrize("inner,m", [("fp32", 0.05), ("fp32r12", 0.05), ("fp16n", 0.2)])
+def test_multi_rhs_cg_lds_staged_default(gpu_lib, inner, m):
+    """Where N_y and N_z divide by 8 and N_x is 16..64, the built-in shape of a
+    multi-column solve with FP32 fields stages the x- and y-hop vectors in LDS
+    (four columns per thread; six columns: a ragged second group).  Every
+    column meets the tolerance by the oracle."""
+    h = gpu_lib
+    nrhs = 6
+    w = gen.workload_smooth((16, 8, 8, 8), 43, -1, 0.3, nrhs)
+    lat, l64, lin, b, x, ws = setup(h, w, inner, nrhs)
+    if inner != "fp16n":  # the query reports FP16N fields; the iterations use FP32 fields
+        assert h.hisq_get_dslash_shape(lat, inner, nrhs, None)[:2] == (2, 4)
+    st, info = h.hisq_cg(lat, m, l64, lin, inner, nrhs, b, x, 1e-10, 20000, ws)
+    assert st == h.OK, info
+    res, _ = oracle_residuals(h, w, lat, x, nrhs, m, w["src"])
+    assert max(res) <= 1e-10, res
+
+
 @pytest.mark.parametrize("inner,nrhs", [("fp64", 3), ("fp32", 16), ("fp32", 5)])
 def test_multi_rhs_cg(gpu_lib, inner, nrhs):
     h = gpu_lib
