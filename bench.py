@@ -106,8 +106,8 @@ def leg_w1(h, gen, O, torch):
 
 
 def leg_dslash16(h, gen, O, torch):
-    """48^3x12 smooth links: the 16-rhs FP32 Dslash alone (default shape), 30
-    launches (10 untimed), for kernel timing and hardware counters."""
+    """48^3x12 smooth links: the 16-rhs FP32 Dslash alone (default shape), 70
+    launches (50 untimed), for kernel timing and hardware counters."""
     import numpy as np
     w = gen.workload_3()
     dims = w["dims"]
@@ -116,7 +116,7 @@ def leg_dslash16(h, gen, O, torch):
     l32 = h.pack_links_from_host(lat, "fp32", w["fat"], w["naik"])
     inp = h.pack_field_from_host(lat, "fp32", w["src"])
     o = h.empty_field(lat, "fp32", 16)
-    for _ in range(10):
+    for _ in range(50):  # the first few tens of launches run up to 10 % slower
         h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -145,7 +145,7 @@ def leg_w3(h, gen, O, torch, w=None):
     out = {}
     inp = h.pack_field_from_host(lat, "fp32", w["src"])
     o = h.empty_field(lat, "fp32", 16)
-    for _ in range(10):
+    for _ in range(50):  # the first few tens of launches run up to 10 % slower
         h.hisq_dslash(lat, "fp32", 0, l32, inp, o, 16)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
