@@ -166,10 +166,11 @@ template <int NIN, typename A> struct HopBuf {
 // branch of its own had its binary16 conversion placed beside it in that
 // branch, so every hop of the FP16N one-column kernel waited for all of the
 // next hop's loads before computing the current one (32^3x8 FP16N 14.5 ->
-// 13.9 us, FP64 47.9 -> 46.8 us).  Only the plain one-column site kernel
-// takes it: the FP64 kernel with the fused dot product ran 46 -> 53 us with
-// it, and with several columns the compiler hoisted more loads than the
-// register file holds.
+// 13.9 us, FP64 47.9 -> 46.8 us).  The one-column site kernel takes it with
+// every epilogue (FP64 CG 16.9 -> 16.6 ms; before eta was folded into the hop
+// signs the FP64 kernel with the fused dot product ran 46 -> 53 us with it);
+// with several columns the compiler hoisted more loads than the register file
+// holds.
 template <bool ONE> __device__ __forceinline__ constexpr bool has_col(int r, int nr) { return ONE || r < nr; }
 
 // tmp += U v (or -U^+ v) with v = sg * (neighbour vectors in b); row 2 of a
@@ -465,7 +466,7 @@ __device__ __forceinline__ void dslash_dot_reduce(const DslashParams &prm, doubl
 // each link is read once: one group of right-hand sides, FP64 or FP32 links).
 template <int LP, int FP, int NIN, int EPI, bool NT>
 __global__ void __launch_bounds__(256) dslash_site_kernel(const DslashParams prm) {
-    constexpr bool ONE = NIN == 1 && EPI == EPI_PLAIN;  // has_col
+    constexpr bool ONE = NIN == 1;  // has_col
     using A = typename Prec<LP>::acc;
     if (prm.skip && *prm.skip)
         return;
