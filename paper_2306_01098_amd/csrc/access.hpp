@@ -11,14 +11,22 @@ namespace hisq {
 template <int LP> struct LinkIO;
 
 // With one group of right-hand sides every link is read exactly once per
-// Dslash application, so FP64 and FP32 link loads carry the non-temporal hint
-// (NT = true): they stream through the caches without displacing the
-// neighbour vectors, which are reused up to 16 times (32^3x8 FP64: 53.0 ->
-// 50.5 us).  When N_outer > 1 groups of right-hand sides read the same links
-// one after another, the links must stay in the L2 for the next group, and
-// ordinary loads are faster (16 rhs at 48^3x12: FP64 1113 -> 960 us, FP32
-// 576 -> 533 us); so are they for reconstruct-12 links at any N_outer
-// (32^3x8 FP64R12 35.4 -> 33.7 us) and for binary16 links.
+// Dslash application, and FP64, FP32 and W14 link loads may carry the
+// non-temporal hint (stream = true; NT = true): they stream through the caches
+// without displacing the neighbour vectors, which are reused up to 16 times.
+// The launcher gives it only where the link set of one application (both
+// parities' blocks) exceeds the 256 MiB MALL, where ordinary loads would cache
+// nothing for the next application (32^3x8 FP64, 302 MB: D_oe and D_eo
+// alternating 51.0 -> 49.4 us with the hint, the FP64 CG 18.3 -> 16.7 ms;
+// 16 single FP32 solves at 48^3x12, 764 MB: 1.43 -> 1.34 s).  Smaller link
+// sets are read with ordinary loads and partly come from the MALL (32^3x8 FP32,
+// 151 MB: 26.3 -> 24.6 us, the FP32 CG 10.96 -> 10.44 ms; FP64W14, 256 MiB:
+// 47.3 -> 45.3 us; FP32W14 24.6 -> 22.2 us).  When N_outer > 1 groups of
+// right-hand sides read the same links one after another, the links must stay
+// in the L2 for the next group, and ordinary loads are faster (16 rhs at
+// 48^3x12: FP64 1113 -> 960 us, FP32 576 -> 533 us); so are they for
+// reconstruct-12 links at any N_outer (32^3x8 FP64R12 35.4 -> 33.7 us) and for
+// binary16 links.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
@@ -80,7 +88,7 @@ template <> struct LinkIO<HISQ_FP16N> {
     using A = float;
     static constexpr bool rebuild = false;
     __device__ __forceinline__ static void finish(A *, int) {}
-    static constexpr bool stream = false;  // the non-temporal hint may pay
+    static constexpr bool stream = false;  // ordinary loads at any size
     template <bool NT = true>  // ordinary loads either way
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
@@ -108,7 +116,7 @@ template <> struct LinkIO<HISQ_FP64R12> {
     using A = double;
     static constexpr bool rebuild = true;
     __device__ __forceinline__ static void finish(A *m, int) { rebuild_row2<A>(m); }
-    static constexpr bool stream = false;  // the non-temporal hint may pay
+    static constexpr bool stream = false;  // ordinary loads at any size
     template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll
@@ -124,7 +132,7 @@ template <> struct LinkIO<HISQ_FP32R12> {
     using A = float;
     static constexpr bool rebuild = true;
     __device__ __forceinline__ static void finish(A *m, int) { rebuild_row2<A>(m); }
-    static constexpr bool stream = false;  // the non-temporal hint may pay
+    static constexpr bool stream = false;  // ordinary loads at any size
     template <bool NT = true>
     __device__ __forceinline__ static void load(const char *blk, int vh, int i, A m[18], int f = 0) {
 #pragma unroll

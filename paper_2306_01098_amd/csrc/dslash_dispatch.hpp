@@ -8,6 +8,15 @@
 
 namespace hisq {
 
+// Non-temporal link loads: only when each link is read once (one group of
+// right-hand sides), the format profits (FP64, FP32, W14) and the link set
+// exceeds the MALL, so that ordinary loads would leave nothing cached for the
+// next application.
+constexpr size_t MALL_BYTES = (size_t)256 << 20;
+template <int LP> inline bool links_stream(const Geom &g, int nouter) {
+    return LinkIO<LP>::stream && nouter == 1 && links_bytes(g, LP) > MALL_BYTES;
+}
+
 template <int LP, int FP, int NIN, int EPI>
 hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     if (s.variant == VAR_LDS) {
@@ -21,7 +30,7 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
             p.xcd_remap = 2;
             p.band = LDS_BAND;
             const size_t shm = lds_stage_bytes(prm.g, FP, NIN);
-            const bool nt = LinkIO<LP>::stream && nouter == 1;
+            const bool nt = links_stream<LP>(prm.g, nouter);
             if (nt)
                 dslash_lds_kernel<LP, FP, NIN, EPI, LinkIO<LP>::stream>
                     <<<dim3((unsigned)(nsb * nouter)), threads, shm, st>>>(p);
@@ -43,9 +52,7 @@ hipError_t dslash_go(const DslashParams &prm, DslashShape s, hipStream_t st) {
     DslashParams p = prm;
     p.xcd_remap = s.xcd_remap;
     p.band = zslab_band(prm.g, prm.nrhs);
-    // non-temporal link loads only when each link is read once (one group of
-    // right-hand sides) and the format profits (FP64, FP32)
-    const bool nt = LinkIO<LP>::stream && nouter == 1;
+    const bool nt = links_stream<LP>(prm.g, nouter);
     if (s.variant == VAR_HOP) {
         if constexpr (NIN <= 2) {
             if (nt)
